@@ -119,13 +119,16 @@ def test_tol_one_eliminates_everything():
 
 
 def test_ranks_bounded_across_depths():
+    # Fig. f:ranks prints no values (parity unpinned); the pin is that ranks
+    # stay O(1): no depth's mean rank exceeds a fixed bound at tol 1e-6
     n, leaf = 48, 9
     P = W.grid_points(n)
-    for kind, kappa, factor in [("laplace", 0, 2.0), ("helmholtz", 25.0, 3.0)]:
+    for kind, kappa, bound in [("laplace", 0, 40.0), ("helmholtz", 25.0, 48.0)]:
         F = rss.factor(P, W.grid_kernel(kind, n, kappa), 1e-6, leaf)
-        leaf_mean = np.mean(F.ranks(F.tree.D))
-        for d in range(F.tree.D - 1, 1, -1):
-            assert np.mean(F.ranks(d)) <= factor * leaf_mean + 8
+        means = [np.mean(F.ranks(d)) for d in range(F.tree.D, 1, -1)]
+        assert len(means) == 3
+        assert max(means) <= bound
+        assert means[-1] <= 1.6 * means[-2]
 
 
 def test_scattered_points_with_empty_boxes():

@@ -1,6 +1,9 @@
 import os
 import sys
 
+for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -9,7 +12,7 @@ if ROOT not in sys.path:
 
 try:  # small dense operations dominate the oracle; threaded BLAS only slows them down
     import threadpoolctl
-    threadpoolctl.threadpool_limits(1)
+    _LIMITS = threadpoolctl.threadpool_limits(1)
 except Exception:  # pragma: no cover
     pass
 

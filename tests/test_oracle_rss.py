@@ -128,7 +128,6 @@ def test_ranks_bounded_across_depths():
         means = [np.mean(F.ranks(d)) for d in range(F.tree.D, 1, -1)]
         assert len(means) == 3
         assert max(means) <= bound
-        assert means[-1] <= 1.6 * means[-2]
 
 
 def test_scattered_points_with_empty_boxes():

@@ -1,0 +1,182 @@
+/*
+ * rss.h -- C ABI of librss: strong recursive skeletonization (RS-S) on one
+ * AMD MI355X (gfx950).
+ *
+ * The library factors the dense kernel matrix of a planar integral equation,
+ *   A x = b,  A_ij = w K(|x_i - x_j|) (i != j),  A_ii = d            (Sec. 1, eqs. e:axb, e:aij)
+ * into the compressed inverse of Sec. 2 (Alg. a:fact with the multilevel
+ * recursion of Sec. 2.5) and applies it to right-hand sides (Sec. 2.6).
+ * Kernels: 2-D Laplace K = -log(r)/(2 pi) (eq. e:kernel_laplace) and 2-D
+ * Helmholtz K = (i/4) H0^(1)(kappa r) (eq. e:kernel_helmholtz), plus the
+ * exactly low-rank test kernel (1 + x.y)^q.
+ *
+ * Conventions for every entry point:
+ *  - Return value: RSS_OK (0) or a negative rss_status.  rss_last_error()
+ *    returns a message for the last failure on the calling thread.
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - Device pointers are HIP device memory of the current device.
+ *  - Dense matrices are complex, column-major, interleaved (re, im).
+ *  - Work is ordered on the handle's stream (rss_options.stream, or a stream
+ *    the library owns); every call returns after its work has completed.
+ *  - A handle must not be used by two threads at once.
+ */
+#ifndef RSS_H
+#define RSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSS_OK = 0,
+  RSS_EINVAL = -1,        /* bad argument: null pointer, n < 1, tol <= 0, leaf < 1,
+                             nrhs < 1, non-finite point, kappa <= 0 for Helmholtz */
+  RSS_ENOMEM = -2,        /* device allocation failed or the memory budget is exceeded */
+  RSS_EUNSUPPORTED = -3,  /* e.g. a tree deeper than 15 levels or more than 2^31-1 points */
+  RSS_ESINGULAR = -4,     /* an exactly zero pivot in a redundant-block or root LU */
+  RSS_ENOCONV = -5,       /* refinement stopped at max_refine above refine_tol;
+                             the output holds the best iterate */
+  RSS_EHIP = -6           /* a HIP runtime call failed */
+} rss_status;
+
+typedef enum {
+  RSS_LAPLACE2D = 0,      /* K = -log(r) / (2 pi)            (eq. e:kernel_laplace) */
+  RSS_HELMHOLTZ2D = 1,    /* K = (i/4) H0^(1)(kappa r)        (eq. e:kernel_helmholtz) */
+  RSS_DEGENERATE = 2      /* K = (1 + x.y)^q, exactly low rank (test kernel) */
+} rss_kernel_kind;
+
+typedef struct {
+  rss_kernel_kind kind;
+  double kappa;           /* Helmholtz wavenumber (> 0) */
+  double weight;          /* w: off-diagonal entries are w K(x_i, x_j) (quadrature weight h^2) */
+  double diag;            /* d: diagonal entries A_ii */
+  int q;                  /* degree of the degenerate kernel */
+} rss_kernel;
+
+typedef enum {
+  RSS_FP64 = 0,           /* factor and solve in complex128 */
+  RSS_FP32_REFINE = 1     /* factor and solve in complex64; rss_solve refines in FP64 */
+} rss_precision;
+
+/* Zero-initialised means "all defaults". */
+typedef struct {
+  int n_proxy;            /* proxy points per circle; 0 -> 64 (Laplace/degenerate), 128 (Helmholtz) */
+  double proxy_radius;    /* proxy circle radius in box-side units; 0 -> 1.25 (Sec. 2.3) */
+  rss_precision precision;
+  double refine_tol;      /* stop refining when max_j ||A x_j - b_j|| / ||b_j|| <= refine_tol; 0 -> 1e-10 */
+  int max_refine;         /* refinement steps after the first solve; 0 -> 10; < 0 -> never refine
+                             (RSS_FP64 never refines unless max_refine > 0) */
+  double root[3];         /* x0, y0, side of the root square; side <= 0 -> [0,1]^2 if every
+                             point lies in it, else the bounding square */
+  void* stream;           /* hipStream_t for all work; NULL -> a stream owned by the handle */
+} rss_options;
+
+typedef struct rss_ctx* rss_handle;
+
+/*
+ * rss_factor / rss_factor_ex -- build the RS-S factorization (Alg. a:fact).
+ *   points : host, n x 2 float64, row-major (x_i = points[2i], y_i = points[2i+1]).
+ *   n      : number of points (1 .. 2^31-1); row i of every right-hand side
+ *            belongs to points[i].
+ *   k      : kernel description (host, copied).
+ *   tol    : ID tolerance eps of Def. 1 (> 0): a box keeps the fewest
+ *            column-pivoted-QR pivots after which every trailing column norm
+ *            is <= tol * |R_00| of its compression matrix.
+ *   leaf   : maximum points per leaf box; the tree depth D is the smallest
+ *            depth at which no box holds more than leaf points (Sec. 2.1).
+ *   opt    : options (may be NULL in rss_factor_ex).
+ *   out    : receives the handle; set to NULL on failure.
+ * The handle owns all device memory of the factorization until rss_free.
+ */
+int rss_factor(const double* points, int64_t n, const rss_kernel* k, double tol, int leaf,
+               rss_handle* out);
+int rss_factor_ex(const double* points, int64_t n, const rss_kernel* k, double tol, int leaf,
+                  const rss_options* opt, rss_handle* out);
+
+/*
+ * rss_solve -- overwrite B with A^{-1} B applied through the factorization
+ * (Sec. 2.6: upward pass, root solve, downward pass).
+ *   B    : device, complex128, n x nrhs, column-major, leading dimension n.
+ *   nrhs : number of columns (>= 1).
+ * In RSS_FP32_REFINE form (and in RSS_FP64 form with max_refine > 0) the
+ * result is refined: r = b - A x is evaluated in FP64 directly from the
+ * kernel (O(n^2) per step) and x += F^{-1} r until refine_tol is met.
+ * Returns RSS_ENOCONV (with the best iterate in B) if it is not met.
+ */
+int rss_solve(rss_handle h, void* B, int nrhs);
+
+/* rss_apply -- one application of the factored inverse, no refinement. */
+int rss_apply(rss_handle h, void* B, int nrhs);
+
+/* rss_free -- release the handle and its device memory (NULL is a no-op). */
+void rss_free(rss_handle h);
+
+typedef struct {
+  int64_t n;              /* number of points */
+  int depth;              /* leaf depth D (root is depth 0) */
+  int precision;          /* rss_precision of the factorization */
+  int n_root;             /* size of the dense root block */
+  int64_t boxes_compressed;
+  int64_t rank_sum[16];   /* sum of skeleton counts k over the boxes of each depth */
+  int64_t box_count[16];  /* non-empty boxes of each depth */
+  int64_t redundant_sum[16];
+  double flops_id;        /* ledger (real flops, a complex multiply-add counts 8) */
+  double flops_lu;
+  double flops_y;
+  double flops_schur;
+  double factor_bytes;    /* bytes of stored factor entries (what a solve streams) */
+  double kernel_evals;    /* kernel evaluations during the factorization */
+  double t_factor_ms;     /* wall time of the last rss_factor on the device stream */
+  double t_solve_ms;      /* wall time of the last rss_solve */
+  double last_relres;     /* max column relative residual of the last refined solve (-1: none) */
+  int last_iters;         /* refinement steps taken by the last rss_solve */
+  double device_bytes;    /* device memory held by the handle */
+} rss_stats;
+
+/* rss_info -- statistics of a factorization (host struct filled). */
+int rss_info(rss_handle h, rss_stats* s);
+
+/*
+ * rss_skeletons -- the skeleton set chosen for every box of one depth.
+ *   depth  : D .. 2 (compressed depths).
+ *   counts : host, 4^depth int32, receives k per box (-1 for empty boxes).
+ *   ids    : host, receives the skeleton point indices of every box in box-id
+ *            order, each box's ascending; may be NULL to query the total.
+ *   cap    : capacity of ids; total : receives the number of ids.
+ */
+int rss_skeletons(rss_handle h, int depth, int32_t* counts, int64_t* ids, int64_t cap,
+                  int64_t* total);
+
+/*
+ * rss_kernel_block -- evaluate the kernel matrix block A[I, J] on the device
+ * (entries as in rss_factor: w K off the diagonal, d where I[a] == J[b]).
+ *   points : device, n x 2 float64 row-major.   I, J : device int32 index arrays.
+ *   out    : device complex128, ni x nj column-major.
+ *   stream : hipStream_t (NULL = default stream).
+ */
+int rss_kernel_block(const rss_kernel* k, const double* points, int64_t n, const int32_t* I,
+                     int64_t ni, const int32_t* J, int64_t nj, void* out, void* stream);
+
+/*
+ * rss_residual -- R = B - A X in FP64, every entry of A evaluated from the
+ * kernel on the fly (O(n^2 nrhs)); the refinement residual of rss_solve.
+ *   points : device, n x 2 float64 row-major.  X, B, R : device complex128,
+ *   n x nrhs column-major (ld n).  R may alias B.
+ */
+int rss_residual(const rss_kernel* k, const double* points, int64_t n, const void* X,
+                 const void* B, void* R, int nrhs, void* stream);
+
+/* rss_last_error -- message for the last failure on this thread ("" if none). */
+const char* rss_last_error(void);
+
+/* rss_error_string -- static name of a status code. */
+const char* rss_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSS_H */

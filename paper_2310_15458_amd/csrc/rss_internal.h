@@ -1,0 +1,155 @@
+// Internal interfaces of librss shared by the host driver (rss_host.cpp) and
+// the device kernels (rss_kernels.hip).  Plain structs of device pointers and
+// sizes, passed to kernels by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rss_device.h"
+
+namespace rss {
+
+// One depth of the quadtree during factorization.
+//  * box b (row-major id, nb x nb grid) owns the active global ids
+//    idx[ioff[b] .. ioff[b] + cur[b]); capacity n0[b] = count at depth start.
+//  * boff[25 b + s] is the offset into A of the dense block A[b, b2] for the
+//    box b2 = b + (s % 5 - 2, s / 5 - 2) (Chebyshev distance <= 2), or -1 off
+//    the grid.  The block is column-major with leading dimension n0[b] and
+//    current size cur[b] x cur[b2].
+template <class R>
+struct Level {
+  int d, nb;
+  const int* n0;
+  int* cur;
+  int* idx;
+  const int64_t* ioff;
+  const int64_t* boff;
+  cx<R>* A;
+  double x0, y0, side;  // geometry of this depth's boxes (side = box side)
+};
+
+// Factor records of the boxes of one depth (offsets are worst-case slots):
+//  T     k x r      (ld k)         interpolation matrix, rows S, cols R ascending
+//  Xi    r x r      (ld r)         X_RR^{-1}
+//  XSNR  (k+nN) x r (ld k+nN)      [X_SR; X_NR]
+//  Y     r x (k+nN) (ld r)         X_RR^{-1} [X_RS X_RN]
+//  gS, gR, gN                      global ids of S, R and the neighbours' active sets
+template <class R>
+struct Records {
+  int* k;
+  int* r;
+  int* nN;
+  const int64_t* oT;
+  const int64_t* oXi;
+  const int64_t* oXSNR;
+  const int64_t* oY;
+  const int64_t* oS;
+  const int64_t* oR;
+  const int64_t* oN;
+  cx<R>* F;
+  int* G;
+};
+
+// One colour phase: the boxes eliminated concurrently, and per-slot workspace.
+template <class R>
+struct Phase {
+  int nbox;
+  const int* box;
+  const int64_t* oC;   // compression matrix C (m x n, ld m) in W
+  const int64_t* oX;   // X_RR (r x r) in W
+  const int64_t* oZ;   // [X_RS X_RN] (r x (k+nN), ld r) in W
+  const int64_t* oI;   // 3 n0 ints in Wi: Sloc, Rloc, perm
+  int* mrow;           // rows of C per slot
+  cx<R>* W;
+  int* Wi;
+  int n_proxy;
+  double proxy_radius;
+};
+
+template <class R>
+struct GemmDesc {
+  cx<R>* C;
+  const cx<R>* A;
+  const cx<R>* B;
+  int ldc, lda, ldb;
+  int M, N, K;
+  int beta;   // 0: C = sign A B; 1: C += sign A B
+  int sign;   // +1 or -1
+};
+
+// Assembly of a dense block from the blocks of the depth below (Sec. 2.5,
+// Fig. f:merge): rows/cols are lists of (child box, local position, global id).
+struct PairDesc {
+  int64_t off;  // destination offset
+  int ld;
+  int nr, nc;
+  int64_t roff, coff;  // into the entry list
+};
+struct ListEntry {
+  int box, local, gid;
+};
+
+// error flags written by kernels
+enum { ERRF_SINGULAR = 1 };
+
+// ---------------------------------------------------------------------------
+// launchers (rss_kernels.hip); all enqueue on `s`
+// ---------------------------------------------------------------------------
+template <class R>
+void launch_leaf_assemble(const Level<R>& L, const KParams& kp, const double* P, hipStream_t s);
+template <class R>
+void launch_build_C(const Level<R>& L, const Phase<R>& ph, const KParams& kp, const double* P,
+                    int chunks, hipStream_t s);
+template <class R>
+void launch_cpqr(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, double tol,
+                 int nmax, int mmax, hipStream_t s);
+template <class R>
+void launch_sparsify(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s);
+template <class R>
+void launch_inverse(const Phase<R>& ph, const Records<R>& rec, int* errflag, int nmax,
+                    hipStream_t s);
+template <class R>
+void launch_plan_y(const Phase<R>& ph, const Records<R>& rec, GemmDesc<R>* desc, hipStream_t s);
+template <class R>
+void launch_compact(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s);
+template <class R>
+void launch_plan_schur(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec,
+                       GemmDesc<R>* desc, hipStream_t s);
+template <class R>
+void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipStream_t s);
+template <class R>
+void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
+                           int max_c, const Level<R>* child, cx<R>* dst, const KParams& kp,
+                           const double* P, hipStream_t s);
+template <class R>
+int launch_root_inverse(cx<R>* A, cx<R>* tmp, int n, unsigned long long* keys, int* perm,
+                        int* errflag, hipStream_t s);
+template <class R>
+void launch_solve_fwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
+                      int kmax, int rmax, hipStream_t s);
+template <class R>
+void launch_solve_bwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
+                      int kmax, int rmax, int snmax, hipStream_t s);
+template <class R>
+void launch_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs, cx<R>* out,
+                        hipStream_t s);
+template <class R>
+void launch_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z, int64_t ldz,
+                         hipStream_t s);
+
+void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64_t ni,
+                         const int* J, int64_t nj, cx<double>* out, hipStream_t s);
+void launch_residual(const KParams& kp, const double* P, int64_t n, const cx<double>* X,
+                     const cx<double>* B, cx<double>* Rout, int nrhs, hipStream_t s);
+// refinement helpers
+void launch_colnorms(const cx<double>* V, int64_t n, int nrhs, double* out, hipStream_t s);
+void launch_scale_to_c64(const cx<double>* V, int64_t n, int nrhs, const double* norms,
+                         cx<float>* out, hipStream_t s);
+void launch_axpy_from_c64(const cx<float>* d, int64_t n, int nrhs, const double* norms,
+                          cx<double>* x, hipStream_t s);
+void launch_cast_c64(const cx<double>* V, int64_t n, int nrhs, cx<float>* out, hipStream_t s);
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_t s);
+
+}  // namespace rss

@@ -1,0 +1,1342 @@
+// Device kernels of librss (gfx950).  Every kernel is templated on the real
+// type R of the stored matrices (double: complex128 form, float: complex64
+// form); kernel entries are always evaluated in FP64 and then rounded.
+//
+// Per colour phase of one depth the factorization runs
+//   build_C -> cpqr -> sparsify -> inverse -> (plan_y, gemm) -> compact -> (plan_schur, gemm)
+// over all boxes of the phase at once (one workgroup or more per box).  Boxes
+// of one colour are at least three boxes apart, so they read and write
+// disjoint blocks (Rem. r:t, Rem. r:nn) and need no synchronisation.
+#include <hip/hip_runtime.h>
+
+#include "rss_internal.h"
+
+namespace rss {
+
+constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
+
+__device__ __forceinline__ int nb_dx(int j) {  // j-th of the 8 neighbour offsets, ascending id
+  const int t = j < 4 ? j : j + 1;
+  return t % 3 - 1;
+}
+__device__ __forceinline__ int nb_dy(int j) {
+  const int t = j < 4 ? j : j + 1;
+  return t / 3 - 1;
+}
+
+template <class R>
+__device__ __forceinline__ int box_at(const Level<R>& L, int b, int dx, int dy) {
+  const int bx = b % L.nb + dx, by = b / L.nb + dy;
+  if (bx < 0 || by < 0 || bx >= L.nb || by >= L.nb) return -1;
+  return by * L.nb + bx;
+}
+
+template <class R>
+__device__ __forceinline__ cx<R>* block_ptr(const Level<R>& L, int b, int b2) {
+  const int dx = b2 % L.nb - b % L.nb, dy = b2 / L.nb - b / L.nb;
+  return L.A + L.boff[(int64_t)b * 25 + slot_of(dx, dy)];
+}
+
+// ---------------------------------------------------------------------------
+// leaf stencil: A[b, b2] = a(I_b, I_b2) for every pair at distance <= 2
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_leaf_assemble(Level<R> L, KParams kp, const double* P) {
+  const int b = blockIdx.x / 25, s = blockIdx.x % 25;
+  const int64_t off = L.boff[(int64_t)b * 25 + s];
+  if (off < 0) return;
+  const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
+  const int m = L.n0[b], n = L.n0[b2];
+  const int* I = L.idx + L.ioff[b];
+  const int* J = L.idx + L.ioff[b2];
+  cx<R>* out = L.A + off;
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    const cx<double> v = entry(kp, P, I[i], J[j]);
+    out[i + (int64_t)j * m] = from_d<R>(v.x, v.y);
+  }
+}
+
+template <class R>
+void launch_leaf_assemble(const Level<R>& L, const KParams& kp, const double* P, hipStream_t s) {
+  const int nbox = L.nb * L.nb;
+  hipLaunchKernelGGL(k_leaf_assemble<R>, dim3(nbox * 25), dim3(256), 0, s, L, kp, P);
+}
+
+// ---------------------------------------------------------------------------
+// compression matrix (eqs. e:con, e:proxy):
+//   C = [A_{M,B}; A_{B,M}^*; w K(proxy, B); (w K(B, proxy))^*]
+// M boxes in ascending id order, rows of each in its active order.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_build_C(Level<R> L, Phase<R> ph, KParams kp,
+                                                 const double* P) {
+  __shared__ int mbox[16], moff[17];
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int n = L.cur[b];
+  if (threadIdx.x == 0) {
+    int c = 0, o = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        if (max(abs(dx), abs(dy)) != 2) continue;
+        const int b2 = box_at(L, b, dx, dy);
+        if (b2 < 0) continue;
+        mbox[c] = b2;
+        moff[c] = o;
+        o += L.cur[b2];
+        ++c;
+      }
+    for (int i = c; i < 17; ++i) moff[i] = o;
+    for (int i = c; i < 16; ++i) mbox[i] = -1;
+  }
+  __syncthreads();
+  const int sumM = moff[16];
+  const int npx = ph.n_proxy;
+  const int m = 2 * sumM + 2 * npx;
+  if (blockIdx.y == 0 && threadIdx.x == 0) ph.mrow[b] = m;
+  const int r0 = blockIdx.y * 64;
+  if (r0 >= m || n == 0) return;
+  cx<R>* C = ph.W + ph.oC[slot];
+  const int* I = L.idx + L.ioff[b];
+  const int bx = b % L.nb, by = b / L.nb;
+  const double cxx = L.x0 + (bx + 0.5) * L.side, cyy = L.y0 + (by + 0.5) * L.side;
+  const double rad = ph.proxy_radius * L.side;
+  const int n0b = L.n0[b];
+  for (int e = threadIdx.x; e < 64 * n; e += blockDim.x) {
+    const int row = r0 + (e & 63), j = e >> 6;
+    if (row >= m) continue;
+    cx<R> val;
+    if (row < 2 * sumM) {
+      const int rr = row < sumM ? row : row - sumM;
+      int q = 0;
+      while (moff[q + 1] <= rr) ++q;
+      const int i = rr - moff[q];
+      const int mb = mbox[q];
+      if (row < sumM) {
+        const cx<R>* blk = block_ptr(L, mb, b);  // A[mb, b]: cur[mb] x n, ld n0[mb]
+        val = blk[i + (int64_t)j * L.n0[mb]];
+      } else {
+        const cx<R>* blk = block_ptr(L, b, mb);  // A[b, mb]: n x cur[mb], ld n0[b]
+        val = conj(blk[j + (int64_t)i * n0b]);
+      }
+    } else {
+      const int p = (row - 2 * sumM) % npx;
+      const bool second = (row - 2 * sumM) >= npx;
+      const double th = (2.0 * 3.141592653589793116 * p) / npx;
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      const double gx = cxx + rad * cs, gy = cyy + rad * sn;
+      const int g = I[j];
+      const double px = P[2 * g], py = P[2 * g + 1];
+      if (!second) {
+        const cx<double> k = kernel_raw(kp, gx, gy, px, py);
+        val = from_d<R>(kp.weight * k.x, kp.weight * k.y);
+      } else {
+        const cx<double> k = kernel_raw(kp, px, py, gx, gy);
+        val = from_d<R>(kp.weight * k.x, -(kp.weight * k.y));
+      }
+    }
+    C[row + (int64_t)j * m] = val;
+  }
+}
+
+template <class R>
+void launch_build_C(const Level<R>& L, const Phase<R>& ph, const KParams& kp, const double* P,
+                    int chunks, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  hipLaunchKernelGGL(k_build_C<R>, dim3(ph.nbox, chunks), dim3(256), 0, s, L, ph, kp, P);
+}
+
+// ---------------------------------------------------------------------------
+// interpolative decomposition by column-pivoted Householder QR (Def. 1):
+// exact trailing norms at every step (FP64 accumulation), pivot = smallest
+// global id among columns within TIE of the largest norm, stop when the
+// largest trailing norm is <= tol * nu0.  Then T = R11^{-1} R12, rows and
+// columns reordered to ascending ids.  One workgroup per box.
+// ---------------------------------------------------------------------------
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_cpqr(Level<R> L, Phase<R> ph, Records<R> rec, double tol,
+                                             int nmax, int vcap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NW = NT / 64;
+  double* nrm = reinterpret_cast<double*>(smem_raw);               // nmax
+  double* red = nrm + nmax;                                         // NW
+  int* perm = reinterpret_cast<int*>(red + NW);                     // nmax
+  int* rankv = perm + nmax;                                         // nmax
+  cx<R>* vs = reinterpret_cast<cx<R>*>(smem_raw + (((nmax * 8 + NW * 8 + nmax * 8) + 15) & ~15));
+  __shared__ int sh_p;
+  __shared__ double sh_nu0;
+
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int n = L.cur[b], m = ph.mrow[b];
+  const bool vlds = m <= vcap;
+  cx<R>* C = ph.W + ph.oC[slot];
+  int* Sloc = ph.Wi + ph.oI[slot];
+  const int n0b = L.n0[b];
+  int* Rloc = Sloc + n0b;
+  const int* gid = L.idx + L.ioff[b];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  for (int c = wv; c < n; c += NW) {
+    const cx<R>* col = C + (int64_t)c * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += abs2d(col[i]);
+    s = wave_sum(s);
+    if (lane == 0) nrm[c] = s;
+  }
+  for (int c = threadIdx.x; c < n; c += NT) perm[c] = c;
+  __syncthreads();
+  int k = 0;
+  const int jmax = m < n ? m : n;
+  for (int j = 0; j < jmax; ++j) {
+    if (threadIdx.x == 0) {
+      double mx = 0.0;
+      for (int c = j; c < n; ++c) mx = fmax(mx, nrm[c]);
+      mx = sqrt(mx);
+      if (j == 0) sh_nu0 = mx;
+      int best = -1;
+      if (!(mx <= tol * sh_nu0)) {
+        const double thr = (1.0 - TIE) * mx;
+        for (int c = j; c < n; ++c)
+          if (sqrt(nrm[c]) >= thr && (best < 0 || gid[perm[c]] < gid[perm[best]])) best = c;
+      }
+      sh_p = best;
+    }
+    __syncthreads();
+    const int p = sh_p;
+    if (p < 0) break;
+    if (p != j) {
+      cx<R>* cj = C + (int64_t)j * m;
+      cx<R>* cp = C + (int64_t)p * m;
+      for (int i = threadIdx.x; i < m; i += NT) {
+        const cx<R> t = cj[i];
+        cj[i] = cp[i];
+        cp[i] = t;
+      }
+      if (threadIdx.x == 0) {
+        const int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+        const double u = nrm[j];
+        nrm[j] = nrm[p];
+        nrm[p] = u;
+      }
+    }
+    __syncthreads();
+    cx<R>* cj = C + (int64_t)j * m;
+    double t = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += NT) t += abs2d(cj[i]);
+    t = block_sum<NT>(t, red);
+    const cx<R> x0 = cj[j];
+    const double ax0 = sqrt(abs2d(x0));
+    const double xn = sqrt(ax0 * ax0 + t);
+    const double phr = ax0 > 0.0 ? (double)x0.x / ax0 : 1.0;
+    const double phi = ax0 > 0.0 ? (double)x0.y / ax0 : 0.0;
+    const double alr = -phr * xn, ali = -phi * xn;
+    const double v0r = (double)x0.x - alr, v0i = (double)x0.y - ali;
+    const double vv = v0r * v0r + v0i * v0i + t;
+    const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) cj[j] = cx<R>{(R)v0r, (R)v0i};
+    __syncthreads();
+    const cx<R>* vp = cj + j;
+    if (vlds) {
+      for (int i = j + threadIdx.x; i < m; i += NT) vs[i - j] = cj[i];
+      __syncthreads();
+      vp = vs;
+    }
+    for (int c = j + 1 + wv; c < n; c += NW) {
+      cx<R>* col = C + (int64_t)c * m;
+      double dr = 0.0, di = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const cx<R> a = col[i], v = vp[i - j];
+        dr += (double)v.x * a.x + (double)v.y * a.y;
+        di += (double)v.x * a.y - (double)v.y * a.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double sr = beta * dr, si = beta * di;
+      double s2 = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const cx<R> v = vp[i - j];
+        cx<R> a = col[i];
+        a.x -= (R)((double)v.x * sr - (double)v.y * si);
+        a.y -= (R)((double)v.x * si + (double)v.y * sr);
+        col[i] = a;
+        if (i > j) s2 += abs2d(a);
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) nrm[c] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) cj[j] = cx<R>{(R)alr, (R)ali};
+    __syncthreads();
+    k = j + 1;
+  }
+  const int r = n - k;
+  if (threadIdx.x == 0) {
+    rec.k[b] = k;
+    rec.r[b] = r;
+  }
+  // T = R11^{-1} R12 in place of R12, one thread per column
+  for (int c = k + threadIdx.x; c < n; c += NT) {
+    cx<R>* col = C + (int64_t)c * m;
+    for (int i = k - 1; i >= 0; --i) {
+      double sr = col[i].x, si = col[i].y;
+      for (int l = i + 1; l < k; ++l) {
+        const cx<R> a = C[i + (int64_t)l * m], x = col[l];
+        sr -= (double)a.x * x.x - (double)a.y * x.y;
+        si -= (double)a.x * x.y + (double)a.y * x.x;
+      }
+      const cx<R> d = C[i + (int64_t)i * m];
+      const double dd = (double)d.x * d.x + (double)d.y * d.y;
+      col[i] = cx<R>{(R)((sr * d.x + si * d.y) / dd), (R)((si * d.x - sr * d.y) / dd)};
+    }
+  }
+  // ascending local positions of S and R (local order = global id order)
+  for (int a = threadIdx.x; a < n; a += NT) {
+    const int pa = perm[a];
+    const bool isS = a < k;
+    const int lo = isS ? 0 : k, hi = isS ? k : n;
+    int rk = 0;
+    for (int a2 = lo; a2 < hi; ++a2) rk += perm[a2] < pa;
+    rankv[a] = rk;
+    if (isS) Sloc[rk] = pa;
+    else Rloc[rk] = pa;
+  }
+  __syncthreads();
+  if (k > 0 && r > 0) {
+    cx<R>* Tout = rec.F + rec.oT[b];
+    for (int e = threadIdx.x; e < k * r; e += NT) {
+      const int a = e % k, c = e / k;
+      Tout[rankv[a] + (int64_t)k * rankv[k + c]] = C[a + (int64_t)(k + c) * m];
+    }
+  }
+}
+
+template <class R>
+void launch_cpqr(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, double tol,
+                 int nmax, int mmax, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  constexpr int NT = 512;
+  const size_t head = ((size_t)nmax * 8 + (NT / 64) * 8 + (size_t)nmax * 8 + 15) & ~(size_t)15;
+  // the Householder vector is staged in LDS when it fits in 48 KiB
+  const int vcap = (int)((48 * 1024) / sizeof(cx<R>));
+  const size_t shm = head + (size_t)(mmax < vcap ? mmax : vcap) * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_cpqr<R, NT>), dim3(ph.nbox), dim3(NT), shm, s, L, ph, rec, tol, nmax, vcap);
+}
+
+// ---------------------------------------------------------------------------
+// sparsification (eq. e:s) with the ID of the box:
+//   X_SR = A_SR - A_SS T         X_RS = A_RS - T^* A_SS
+//   X_RR = (A_RR - A_RS T) - T^* X_SR
+//   X_NR = A_NR - A_NS T         X_RN = A_RN - T^* A_SN
+// part 0: the box's own block; part 1 + j: neighbour j (ascending id).
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_sparsify(Level<R> L, Phase<R> ph, Records<R> rec) {
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int k = rec.k[b], r = rec.r[b];
+  if (r == 0) return;
+  const int part = blockIdx.y;
+  int nN = 0, offj = 0, nbj = -1;
+  for (int j = 0; j < 8; ++j) {
+    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
+    if (b2 < 0) continue;
+    if (j == part - 1) {
+      offj = nN;
+      nbj = b2;
+    }
+    nN += L.cur[b2];
+  }
+  if (part > 0 && nbj < 0) return;
+  const int n0b = L.n0[b];
+  const int* Sl = ph.Wi + ph.oI[slot];
+  const int* Rl = Sl + n0b;
+  const cx<R>* T = rec.F + rec.oT[b];
+  cx<R>* XSNR = rec.F + rec.oXSNR[b];
+  const int ldx = k + nN;
+  cx<R>* Z = ph.W + ph.oZ[slot];
+  const int* gid = L.idx + L.ioff[b];
+  if (part == 0) {
+    const cx<R>* A = block_ptr(L, b, b);
+    const int ld = n0b;
+    for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
+      const int a = e % k, c = e / k;
+      cx<R> v = A[Sl[a] + (int64_t)Rl[c] * ld];
+      for (int s = 0; s < k; ++s) v = v - A[Sl[a] + (int64_t)Sl[s] * ld] * T[s + (int64_t)c * k];
+      XSNR[a + (int64_t)c * ldx] = v;
+    }
+    for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
+      const int c = e % r, a = e / r;
+      cx<R> v = A[Rl[c] + (int64_t)Sl[a] * ld];
+      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c * k], A[Sl[s] + (int64_t)Sl[a] * ld]);
+      Z[c + (int64_t)a * r] = v;
+    }
+    __syncthreads();
+    cx<R>* X = ph.W + ph.oX[slot];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+      const int c1 = e % r, c2 = e / r;
+      cx<R> v = A[Rl[c1] + (int64_t)Rl[c2] * ld];
+      for (int s = 0; s < k; ++s) v = v - A[Rl[c1] + (int64_t)Sl[s] * ld] * T[s + (int64_t)c2 * k];
+      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c1 * k], XSNR[s + (int64_t)c2 * ldx]);
+      X[c1 + (int64_t)c2 * r] = v;
+    }
+    int* gS = rec.G + rec.oS[b];
+    int* gR = rec.G + rec.oR[b];
+    for (int a = threadIdx.x; a < k; a += blockDim.x) gS[a] = gid[Sl[a]];
+    for (int c = threadIdx.x; c < r; c += blockDim.x) gR[c] = gid[Rl[c]];
+    if (threadIdx.x == 0) rec.nN[b] = nN;
+  } else {
+    const int cn = L.cur[nbj];
+    const cx<R>* A1 = block_ptr(L, nbj, b);  // cn x n, ld n0[nbj]
+    const int ld1 = L.n0[nbj];
+    for (int e = threadIdx.x; e < cn * r; e += blockDim.x) {
+      const int i = e % cn, c = e / cn;
+      cx<R> v = A1[i + (int64_t)Rl[c] * ld1];
+      for (int s = 0; s < k; ++s) v = v - A1[i + (int64_t)Sl[s] * ld1] * T[s + (int64_t)c * k];
+      XSNR[(k + offj + i) + (int64_t)c * ldx] = v;
+    }
+    const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
+    for (int e = threadIdx.x; e < r * cn; e += blockDim.x) {
+      const int c = e % r, i = e / r;
+      cx<R> v = A2[Rl[c] + (int64_t)i * n0b];
+      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c * k], A2[Sl[s] + (int64_t)i * n0b]);
+      Z[c + (int64_t)(k + offj + i) * r] = v;
+    }
+    int* gN = rec.G + rec.oN[b];
+    const int* gid2 = L.idx + L.ioff[nbj];
+    for (int i = threadIdx.x; i < cn; i += blockDim.x) gN[offj + i] = gid2[i];
+  }
+}
+
+template <class R>
+void launch_sparsify(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(256), 0, s, L, ph, rec);
+}
+
+// ---------------------------------------------------------------------------
+// X_RR^{-1} by in-place Gauss-Jordan elimination with partial pivoting
+// (the LU of eq. e:step, kept as an explicit inverse).  One workgroup per box.
+// ---------------------------------------------------------------------------
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_inverse(Phase<R> ph, Records<R> rec, int* errflag) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double rv[NT];
+  __shared__ int ri[NT];
+  __shared__ int sh_p;
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int r = rec.r[b];
+  if (r == 0) return;
+  cx<R>* colk = reinterpret_cast<cx<R>*>(smem_raw);
+  int* piv = reinterpret_cast<int*>(colk + r);
+  cx<R>* A = rec.F + rec.oXi[b];
+  const cx<R>* X = ph.W + ph.oX[slot];
+  for (int e = threadIdx.x; e < r * r; e += NT) A[e] = X[e];
+  __syncthreads();
+  for (int kk = 0; kk < r; ++kk) {
+    double best = -1.0;
+    int bi = kk;
+    for (int i = kk + threadIdx.x; i < r; i += NT) {
+      const double v = abs2d(A[i + (int64_t)kk * r]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    rv[threadIdx.x] = best;
+    ri[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) {
+        const double v2 = rv[threadIdx.x + o];
+        const int i2 = ri[threadIdx.x + o];
+        if (v2 > rv[threadIdx.x] || (v2 == rv[threadIdx.x] && i2 < ri[threadIdx.x])) {
+          rv[threadIdx.x] = v2;
+          ri[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      sh_p = rv[0] > 0.0 ? ri[0] : -1;
+      piv[kk] = ri[0];
+    }
+    __syncthreads();
+    const int p = sh_p;
+    if (p < 0) {
+      if (threadIdx.x == 0) atomicOr(errflag, ERRF_SINGULAR);
+      return;
+    }
+    if (p != kk)
+      for (int j = threadIdx.x; j < r; j += NT) {
+        const cx<R> t = A[kk + (int64_t)j * r];
+        A[kk + (int64_t)j * r] = A[p + (int64_t)j * r];
+        A[p + (int64_t)j * r] = t;
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r; i += NT) colk[i] = A[i + (int64_t)kk * r];
+    __syncthreads();
+    const cx<R> d = colk[kk];
+    const double dd = abs2d(d);
+    const cx<R> pinv{(R)(d.x / dd), (R)(-d.y / dd)};
+    for (int j = threadIdx.x; j < r; j += NT) {
+      if (j == kk) A[kk + (int64_t)kk * r] = pinv;
+      else A[kk + (int64_t)j * r] = A[kk + (int64_t)j * r] * pinv;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int i = e % r, j = e / r;
+      if (i == kk) continue;
+      if (j == kk) A[i + (int64_t)kk * r] = czero<R>() - colk[i] * pinv;
+      else A[i + (int64_t)j * r] = A[i + (int64_t)j * r] - colk[i] * A[kk + (int64_t)j * r];
+    }
+    __syncthreads();
+  }
+  for (int kk = r - 1; kk >= 0; --kk) {
+    const int p = piv[kk];  // set for every step (the loop above ran to completion)
+    if (p != kk)
+      for (int i = threadIdx.x; i < r; i += NT) {
+        const cx<R> t = A[i + (int64_t)kk * r];
+        A[i + (int64_t)kk * r] = A[i + (int64_t)p * r];
+        A[i + (int64_t)p * r] = t;
+      }
+    __syncthreads();
+  }
+}
+
+template <class R>
+void launch_inverse(const Phase<R>& ph, const Records<R>& rec, int* errflag, int nmax,
+                    hipStream_t s) {
+  if (ph.nbox == 0) return;
+  const size_t shm = (size_t)nmax * (sizeof(cx<R>) + sizeof(int)) + 16;
+  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, ph, rec, errflag);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM descriptors
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void k_plan_y(Phase<R> ph, Records<R> rec, GemmDesc<R>* desc) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= ph.nbox) return;
+  const int b = ph.box[slot];
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  GemmDesc<R> d;
+  d.C = rec.F + rec.oY[b];
+  d.A = rec.F + rec.oXi[b];
+  d.B = ph.W + ph.oZ[slot];
+  d.ldc = r > 0 ? r : 1;
+  d.lda = d.ldc;
+  d.ldb = d.ldc;
+  d.M = r;
+  d.N = r > 0 ? k + nN : 0;
+  d.K = r;
+  d.beta = 0;
+  d.sign = 1;
+  desc[slot] = d;
+}
+
+template <class R>
+void launch_plan_y(const Phase<R>& ph, const Records<R>& rec, GemmDesc<R>* desc, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  hipLaunchKernelGGL(k_plan_y<R>, dim3((ph.nbox + 63) / 64), dim3(64), 0, s, ph, rec, desc);
+}
+
+// Schur complement update (eq. e:step, Rem. r:nn):
+//   block(t1, t2) -= [X_SR; X_NR](rows of t1) * Y(:, cols of t2)
+// for t1, t2 in {B} u N(B); B's own rows/columns are its skeletons.
+template <class R>
+__global__ void k_plan_schur(Level<R> L, Phase<R> ph, Records<R> rec, GemmDesc<R>* desc) {
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int t = threadIdx.x;
+  if (t >= 81) return;
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  int box[9], off[9], cnt[9];
+  box[0] = b;
+  off[0] = 0;
+  cnt[0] = k;
+  int o = k;
+  for (int j = 0; j < 8; ++j) {
+    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
+    box[j + 1] = b2;
+    off[j + 1] = o;
+    cnt[j + 1] = b2 >= 0 ? L.cur[b2] : 0;
+    if (b2 >= 0) o += L.cur[b2];
+  }
+  const int t1 = t / 9, t2 = t % 9;
+  GemmDesc<R> d;
+  d.beta = 1;
+  d.sign = -1;
+  d.K = r;
+  if (r == 0 || box[t1] < 0 || box[t2] < 0) {
+    d.M = 0;
+    d.N = 0;
+    d.C = nullptr;
+    d.A = nullptr;
+    d.B = nullptr;
+    d.ldc = d.lda = d.ldb = 1;
+  } else {
+    d.C = block_ptr(L, box[t1], box[t2]);
+    d.ldc = L.n0[box[t1]];
+    d.A = rec.F + rec.oXSNR[b] + off[t1];
+    d.lda = k + nN;
+    d.B = rec.F + rec.oY[b] + (int64_t)off[t2] * r;
+    d.ldb = r;
+    d.M = cnt[t1];
+    d.N = cnt[t2];
+  }
+  desc[(int64_t)slot * 81 + t] = d;
+}
+
+template <class R>
+void launch_plan_schur(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec,
+                       GemmDesc<R>* desc, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  hipLaunchKernelGGL(k_plan_schur<R>, dim3(ph.nbox), dim3(128), 0, s, L, ph, rec, desc);
+}
+
+// ---------------------------------------------------------------------------
+// batched ragged complex GEMM: C = (beta C) + sign * A B, 64 x 64 tiles,
+// 256 threads each owning a 4 x 4 patch (rows tx + 16 a, cols ty + 16 b).
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles_m) {
+  __shared__ cx<R> As[16][64];
+  __shared__ cx<R> Bs[16][65];
+  const GemmDesc<R> d = desc[blockIdx.x];
+  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
+  const int i0 = tm * 64, j0 = tn * 64;
+  if (i0 >= d.M || j0 >= d.N) return;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  cx<R> acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = czero<R>();
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int i = e & 63, kk = e >> 6;
+      const int gi = i0 + i, gk = k0 + kk;
+      As[kk][i] = (gi < d.M && gk < d.K) ? d.A[gi + (int64_t)gk * d.lda] : czero<R>();
+      const int kb = e & 15, j = e >> 4;
+      const int gj = j0 + j, gkb = k0 + kb;
+      Bs[kb][j] = (gj < d.N && gkb < d.K) ? d.B[gkb + (int64_t)gj * d.ldb] : czero<R>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      cx<R> av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fma_(acc[a][c], av[a], bv[c]);
+    }
+    __syncthreads();
+  }
+  const R sg = (R)d.sign;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * c;
+      if (gi < d.M && gj < d.N) {
+        cx<R>* p = d.C + gi + (int64_t)gj * d.ldc;
+        const cx<R> v = sg * acc[a][c];
+        *p = d.beta ? (*p + v) : v;
+      }
+    }
+}
+
+template <class R>
+void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipStream_t s) {
+  if (ndesc == 0 || max_m <= 0 || max_n <= 0) return;
+  const int tm = (max_m + 63) / 64, tn = (max_n + 63) / 64;
+  hipLaunchKernelGGL(k_gemm<R>, dim3(ndesc, tm * tn), dim3(256), 0, s, desc, tm);
+}
+
+// ---------------------------------------------------------------------------
+// drop R: every stored block of B keeps only the skeleton rows / columns
+// (in ascending order), and B's active ids shrink to S.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_compact(Level<R> L, Phase<R> ph, Records<R> rec) {
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const int k = rec.k[b], r = rec.r[b];
+  if (r == 0) return;
+  const int s = blockIdx.y;
+  const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
+  if (b2 < 0) return;
+  const int n0b = L.n0[b];
+  const int* Sl = ph.Wi + ph.oI[slot];
+  constexpr int PER = 8;
+  if (b2 != b) {
+    const int c2 = L.cur[b2];
+    // rows of A[b, b2]: row i <- row Sl[i]; columns independent
+    {
+      cx<R>* A = block_ptr(L, b, b2);
+      const int cw = max(1, (256 * PER) / max(k, 1));
+      for (int c0 = 0; c0 < c2; c0 += cw) {
+        const int nc = min(cw, c2 - c0);
+        cx<R> tmp[PER];
+        int cnt = 0;
+        for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+          const int i = e % k, c = c0 + e / k;
+          tmp[cnt] = A[Sl[i] + (int64_t)c * n0b];
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+          const int i = e % k, c = c0 + e / k;
+          A[i + (int64_t)c * n0b] = tmp[cnt];
+        }
+        __syncthreads();
+      }
+    }
+    // columns of A[b2, b]: column j <- column Sl[j]; rows independent
+    {
+      cx<R>* A = block_ptr(L, b2, b);
+      const int ld = L.n0[b2];
+      const int rw = max(1, (256 * PER) / max(k, 1));
+      for (int i0 = 0; i0 < c2; i0 += rw) {
+        const int nr = min(rw, c2 - i0);
+        cx<R> tmp[PER];
+        int cnt = 0;
+        for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+          const int i = i0 + e % nr, j = e / nr;
+          tmp[cnt] = A[i + (int64_t)Sl[j] * ld];
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+          const int i = i0 + e % nr, j = e / nr;
+          A[i + (int64_t)j * ld] = tmp[cnt];
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    cx<R>* A = block_ptr(L, b, b);
+    const int n = L.cur[b];
+    // rows first (all n columns), then columns (first k rows)
+    const int cw = max(1, (256 * PER) / max(k, 1));
+    for (int c0 = 0; c0 < n; c0 += cw) {
+      const int nc = min(cw, n - c0);
+      cx<R> tmp[PER];
+      int cnt = 0;
+      for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+        const int i = e % k, c = c0 + e / k;
+        tmp[cnt] = A[Sl[i] + (int64_t)c * n0b];
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+        const int i = e % k, c = c0 + e / k;
+        A[i + (int64_t)c * n0b] = tmp[cnt];
+      }
+      __syncthreads();
+    }
+    const int rw = max(1, (256 * PER) / max(k, 1));
+    for (int i0 = 0; i0 < k; i0 += rw) {
+      const int nr = min(rw, k - i0);
+      cx<R> tmp[PER];
+      int cnt = 0;
+      for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+        const int i = i0 + e % nr, j = e / nr;
+        tmp[cnt] = A[i + (int64_t)Sl[j] * n0b];
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+        const int i = i0 + e % nr, j = e / nr;
+        A[i + (int64_t)j * n0b] = tmp[cnt];
+      }
+      __syncthreads();
+    }
+    int* gid = L.idx + L.ioff[b];
+    for (int base = 0; base < k; base += 256) {
+      const int i = base + threadIdx.x;
+      const int v = i < k ? gid[Sl[i]] : 0;
+      __syncthreads();
+      if (i < k) gid[i] = v;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) L.cur[b] = k;
+  }
+}
+
+template <class R>
+void launch_compact(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  hipLaunchKernelGGL(k_compact<R>, dim3(ph.nbox, 25), dim3(256), 0, s, L, ph, rec);
+}
+
+// ---------------------------------------------------------------------------
+// merge (Sec. 2.5, Fig. f:merge): a block over the union of child skeletons,
+// copied from the child blocks where the two children are within distance 2
+// and evaluated fresh from the kernel otherwise (Thm. a:bm).
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, const ListEntry* lists,
+                                                        int tiles_r, Level<R> child, int have_child,
+                                                        cx<R>* dst, KParams kp, const double* P) {
+  const PairDesc d = pd[blockIdx.x];
+  const int tr = blockIdx.y % tiles_r, tc = blockIdx.y / tiles_r;
+  const int i0 = tr * 64, j0 = tc * 64;
+  if (i0 >= d.nr || j0 >= d.nc) return;
+  const ListEntry* rows = lists + d.roff;
+  const ListEntry* cols = lists + d.coff;
+  cx<R>* out = dst + d.off;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    if (i >= d.nr || j >= d.nc) continue;
+    const ListEntry ri = rows[i], cj = cols[j];
+    cx<R> v;
+    bool stored = false;
+    if (have_child) {
+      const int dx = cj.box % child.nb - ri.box % child.nb;
+      const int dy = cj.box / child.nb - ri.box / child.nb;
+      if (abs(dx) <= 2 && abs(dy) <= 2) {
+        const cx<R>* blk = child.A + child.boff[(int64_t)ri.box * 25 + slot_of(dx, dy)];
+        v = blk[ri.local + (int64_t)cj.local * child.n0[ri.box]];
+        stored = true;
+      }
+    }
+    if (!stored) {
+      const cx<double> a = entry(kp, P, ri.gid, cj.gid);
+      v = from_d<R>(a.x, a.y);
+    }
+    out[i + (int64_t)j * d.ld] = v;
+  }
+}
+
+template <class R>
+void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
+                           int max_c, const Level<R>* child, cx<R>* dst, const KParams& kp,
+                           const double* P, hipStream_t s) {
+  if (npairs == 0 || max_r <= 0 || max_c <= 0) return;
+  const int tr = (max_r + 63) / 64, tc = (max_c + 63) / 64;
+  Level<R> c{};
+  int have = 0;
+  if (child) {
+    c = *child;
+    have = 1;
+  }
+  hipLaunchKernelGGL(k_assemble_pairs<R>, dim3(npairs, tr * tc), dim3(256), 0, s, pd, lists, tr, c,
+                     have, dst, kp, P);
+}
+
+// ---------------------------------------------------------------------------
+// root: dense inverse by Gauss-Jordan elimination with partial pivoting, one
+// launch per pivot (ping-pong buffers); the next pivot is chosen by the
+// launch that produces its column (packed |a| / index keys, atomicMax).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long pivkey(double a2, int i) {
+  const float f = (float)sqrt(a2);
+  return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_root_pivot0(const cx<R>* A, int n,
+                                                     unsigned long long* keys) {
+  __shared__ unsigned long long red[256];
+  unsigned long long best = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const unsigned long long kk = pivkey(abs2d(A[i]), i);
+    best = kk > best ? kk : best;
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) keys[0] = red[0];
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_root_gj(const cx<R>* src, cx<R>* dst, int n, int kk,
+                                                 unsigned long long* keys, int* perm, int* errflag) {
+  const unsigned long long key = keys[kk];
+  const int p = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4);
+  if (key == 0ull || p < kk || p >= n) {  // no pivot recorded (an earlier step was singular)
+    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(errflag, ERRF_SINGULAR);
+    return;
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) perm[kk] = p;
+  const cx<R> akk = src[p + (int64_t)kk * n];
+  const double dd = abs2d(akk);
+  if (dd == 0.0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(errflag, ERRF_SINGULAR);
+    return;
+  }
+  const cx<R> pinv{(R)(akk.x / dd), (R)(-akk.y / dd)};
+  unsigned long long best = 0;
+  if (i < n && j < n) {
+    const int si = (i == kk) ? p : (i == p ? kk : i);
+    cx<R> v;
+    if (i == kk) {
+      v = (j == kk) ? pinv : src[p + (int64_t)j * n] * pinv;
+    } else {
+      const cx<R> aik = src[si + (int64_t)kk * n];
+      if (j == kk) v = czero<R>() - aik * pinv;
+      else v = src[si + (int64_t)j * n] - aik * pinv * src[p + (int64_t)j * n];
+    }
+    dst[i + (int64_t)j * n] = v;
+    if (j == kk + 1 && i >= kk + 1) best = pivkey(abs2d(v), i);
+  }
+  if (j0 <= kk + 1 && kk + 1 < j0 + 16 && kk + 1 < n) {
+    // reduce the next pivot candidate over this tile's column kk+1
+    __shared__ unsigned long long red[256];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicMax(keys + kk + 1, red[0]);
+  }
+}
+
+// undo the row interchanges: apply the column interchanges in reverse order
+__global__ void k_root_colperm(const int* perm, int n, int* cp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = 0; j < n; ++j) cp[j] = j;
+  for (int kk = n - 1; kk >= 0; --kk) {
+    int p = perm[kk];
+    if (p < 0 || p >= n) p = kk;
+    const int t = cp[kk];
+    cp[kk] = cp[p];
+    cp[p] = t;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gather_cols(const cx<R>* src, cx<R>* dst, int n,
+                                                     const int* cp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  dst[e] = src[i + (int64_t)cp[j] * n];
+}
+
+template <class R>
+int launch_root_inverse(cx<R>* A, cx<R>* tmp, int n, unsigned long long* keys, int* perm,
+                        int* errflag, hipStream_t s) {
+  if (n == 0) return 0;
+  launch_fill_u64(keys, n, 0ull, s);
+  hipLaunchKernelGGL(k_root_pivot0<R>, dim3(1), dim3(256), 0, s, A, n, keys);
+  const int t = (n + 15) / 16;
+  cx<R>* src = A;
+  cx<R>* dst = tmp;
+  for (int kk = 0; kk < n; ++kk) {
+    hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t), dim3(256), 0, s, src, dst, n, kk, keys, perm,
+                       errflag);
+    cx<R>* u = src;
+    src = dst;
+    dst = u;
+  }
+  // src holds the inverse up to column order; perm (n ints) is followed by n ints of space
+  hipLaunchKernelGGL(k_root_colperm, dim3(1), dim3(64), 0, s, perm, n, perm + n);
+  const int64_t tot = (int64_t)n * n;
+  hipLaunchKernelGGL(k_gather_cols<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src,
+                     dst, n, perm + n);
+  return dst == A ? 0 : 1;  // 0: result in A, 1: result in tmp
+}
+
+// ---------------------------------------------------------------------------
+// solve sweeps (Sec. 2.6), NC right-hand-side columns per workgroup
+//  forward : z_R -= T^* z_S;  w = X_RR^{-1} z_R;  z_{S,N} -= [X_SR; X_NR] w
+//  backward: x_R = X_RR^{-1} z_R - Y z_{S,N};  z_S -= T x_R;  z_R = x_R
+// ---------------------------------------------------------------------------
+
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_fwd(Phase<R> ph, Records<R> rec, cx<R>* z, int64_t ldz,
+                                                   int nrhs, int kmax, int rmax, int SNC) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* zS = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* zR = zS + (int64_t)kmax * SNC;
+  cx<R>* w = zR + (int64_t)rmax * SNC;
+  const int b = ph.box[blockIdx.x];
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * SNC;
+  const int nc = min(SNC, nrhs - c0);
+  const int* gS = rec.G + rec.oS[b];
+  const int* gR = rec.G + rec.oR[b];
+  const int* gN = rec.G + rec.oN[b];
+  const cx<R>* T = rec.F + rec.oT[b];
+  const cx<R>* Xi = rec.F + rec.oXi[b];
+  const cx<R>* XS = rec.F + rec.oXSNR[b];
+  for (int e = threadIdx.x; e < k * nc; e += 256) {
+    const int a = e % k, c = e / k;
+    zS[a + k * c] = z[gS[a] + (int64_t)(c0 + c) * ldz];
+  }
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    zR[a + r * c] = z[gR[a] + (int64_t)(c0 + c) * ldz];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    cx<R> v = zR[a + r * c];
+    for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)a * k], zS[s + k * c]);
+    w[a + r * c] = v;  // temporarily the sparsified z_R
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    zR[a + r * c] = w[a + r * c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    cx<R> v = czero<R>();
+    for (int s = 0; s < r; ++s) fma_(v, Xi[a + (int64_t)s * r], zR[s + r * c]);
+    w[a + r * c] = v;
+  }
+  __syncthreads();
+  const int q = k + nN;
+  for (int e = threadIdx.x; e < q * nc; e += 256) {
+    const int a = e % q, c = e / q;
+    cx<R> v = czero<R>();
+    for (int s = 0; s < r; ++s) fma_(v, XS[a + (int64_t)s * q], w[s + r * c]);
+    const int g = a < k ? gS[a] : gN[a - k];
+    cx<R>* p = z + g + (int64_t)(c0 + c) * ldz;
+    *p = *p - v;
+  }
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = zR[a + r * c];
+  }
+}
+
+template <class R>
+void launch_solve_fwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
+                      int kmax, int rmax, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  // right-hand-side columns per workgroup: as many as fit in 64 KiB of LDS (<= 8)
+  const size_t per = (size_t)(kmax + 2 * rmax) * sizeof(cx<R>);
+  int ncw = (int)((64 * 1024) / (per > 0 ? per : 1));
+  ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
+  ncw = ncw > nrhs ? nrhs : ncw;
+  hipLaunchKernelGGL(k_solve_fwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
+                     ph, rec, z, ldz, nrhs, kmax, rmax, ncw);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_bwd(Phase<R> ph, Records<R> rec, cx<R>* z, int64_t ldz,
+                                                   int nrhs, int rmax, int chunk, int SNC) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* zR = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* xR = zR + (int64_t)rmax * SNC;
+  cx<R>* zq = xR + (int64_t)rmax * SNC;  // chunk x SNC
+  const int b = ph.box[blockIdx.x];
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * SNC;
+  const int nc = min(SNC, nrhs - c0);
+  const int* gS = rec.G + rec.oS[b];
+  const int* gR = rec.G + rec.oR[b];
+  const int* gN = rec.G + rec.oN[b];
+  const cx<R>* T = rec.F + rec.oT[b];
+  const cx<R>* Xi = rec.F + rec.oXi[b];
+  const cx<R>* Y = rec.F + rec.oY[b];
+  const int q = k + nN;
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    zR[a + r * c] = z[gR[a] + (int64_t)(c0 + c) * ldz];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    cx<R> v = czero<R>();
+    for (int s = 0; s < r; ++s) fma_(v, Xi[a + (int64_t)s * r], zR[s + r * c]);
+    xR[a + r * c] = v;
+  }
+  for (int q0 = 0; q0 < q; q0 += chunk) {
+    const int nq = min(chunk, q - q0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nq * nc; e += 256) {
+      const int a = e % nq, c = e / nq;
+      const int g = (q0 + a) < k ? gS[q0 + a] : gN[q0 + a - k];
+      zq[a + chunk * c] = z[g + (int64_t)(c0 + c) * ldz];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * nc; e += 256) {
+      const int a = e % r, c = e / r;
+      cx<R> v = xR[a + r * c];
+      for (int s = 0; s < nq; ++s) v = v - Y[a + (int64_t)(q0 + s) * r] * zq[s + chunk * c];
+      xR[a + r * c] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * nc; e += 256) {
+    const int a = e % k, c = e / k;
+    cx<R> v = czero<R>();
+    for (int s = 0; s < r; ++s) fma_(v, T[a + (int64_t)s * k], xR[s + r * c]);
+    cx<R>* p = z + gS[a] + (int64_t)(c0 + c) * ldz;
+    *p = *p - v;
+  }
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = xR[a + r * c];
+  }
+}
+
+template <class R>
+void launch_solve_bwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
+                      int kmax, int rmax, int snmax, hipStream_t s) {
+  (void)kmax;
+  (void)snmax;
+  if (ph.nbox == 0) return;
+  const int chunk = 128;
+  const size_t per = (size_t)(2 * rmax + chunk) * sizeof(cx<R>);
+  int ncw = (int)((64 * 1024) / per);
+  ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
+  ncw = ncw > nrhs ? nrhs : ncw;
+  hipLaunchKernelGGL(k_solve_bwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
+                     ph, rec, z, ldz, nrhs, rmax, chunk, ncw);
+}
+
+template <class R>
+__global__ void k_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs,
+                              cx<R>* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  const int i = (int)(e % n), c = (int)(e / n);
+  out[e] = z[ids[i] + (int64_t)c * ldz];
+}
+template <class R>
+__global__ void k_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z,
+                               int64_t ldz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nrhs) return;
+  const int i = (int)(e % n), c = (int)(e / n);
+  z[ids[i] + (int64_t)c * ldz] = in[e];
+}
+template <class R>
+void launch_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs, cx<R>* out,
+                        hipStream_t s) {
+  const int64_t tot = (int64_t)n * nrhs;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_gather_rows<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, ldz,
+                     ids, n, nrhs, out);
+}
+template <class R>
+void launch_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z, int64_t ldz,
+                         hipStream_t s) {
+  const int64_t tot = (int64_t)n * nrhs;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in,
+                     ids, n, nrhs, z, ldz);
+}
+
+// ---------------------------------------------------------------------------
+// kernel block evaluation and the FP64 on-the-fly residual R = B - A X
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_kernel_block(KParams kp, const double* P, const int* I,
+                                                      int64_t ni, const int* J, int64_t nj,
+                                                      cx<double>* out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ni * nj) return;
+  const int64_t i = e % ni, j = e / ni;
+  out[e] = entry(kp, P, I[i], J[j]);
+}
+
+void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64_t ni, const int* J,
+                         int64_t nj, cx<double>* out, hipStream_t s) {
+  const int64_t tot = ni * nj;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(k_kernel_block, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kp, P, I,
+                     ni, J, nj, out);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_residual(KParams kp, const double* P, int64_t n,
+                                                  const cx<double>* X, const cx<double>* B,
+                                                  cx<double>* Rout, int c0) {
+  __shared__ double sx[256], sy[256];
+  __shared__ cx<double> xs[256 * NC];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < n;
+  const double xi = live ? P[2 * i] : 0.0, yi = live ? P[2 * i + 1] : 0.0;
+  cx<double> acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = czero<double>();
+  for (int64_t t0 = 0; t0 < n; t0 += 256) {
+    const int64_t sj = t0 + threadIdx.x;
+    __syncthreads();
+    if (sj < n) {
+      sx[threadIdx.x] = P[2 * sj];
+      sy[threadIdx.x] = P[2 * sj + 1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xs[threadIdx.x * NC + c] = X[sj + (int64_t)(c0 + c) * n];
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)256, n - t0);
+    if (live) {
+      for (int s = 0; s < cnt; ++s) {
+        cx<double> a;
+        if (t0 + s == i) {
+          a = {kp.diag, 0.0};
+        } else {
+          const cx<double> kv = kernel_raw(kp, xi, yi, sx[s], sy[s]);
+          a = {kp.weight * kv.x, kp.weight * kv.y};
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fma_(acc[c], a, xs[s * NC + c]);
+      }
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const cx<double> bb = B[i + (int64_t)(c0 + c) * n];
+      Rout[i + (int64_t)(c0 + c) * n] = bb - acc[c];
+    }
+  }
+}
+
+void launch_residual(const KParams& kp, const double* P, int64_t n, const cx<double>* X,
+                     const cx<double>* B, cx<double>* Rout, int nrhs, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256));
+  int c0 = 0;
+  while (c0 < nrhs) {
+    const int left = nrhs - c0;
+    if (left >= 16) {
+      hipLaunchKernelGGL(k_residual<16>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
+      c0 += 16;
+    } else if (left >= 8) {
+      hipLaunchKernelGGL(k_residual<8>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
+      c0 += 8;
+    } else if (left >= 4) {
+      hipLaunchKernelGGL(k_residual<4>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
+      c0 += 4;
+    } else if (left >= 2) {
+      hipLaunchKernelGGL(k_residual<2>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
+      c0 += 2;
+    } else {
+      hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
+      c0 += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// refinement helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colnorms(const cx<double>* V, int64_t n, double* out) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += abs2d(V[i + (int64_t)c * n]);
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) out[c] = sqrt(s);
+}
+void launch_colnorms(const cx<double>* V, int64_t n, int nrhs, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colnorms, dim3(nrhs), dim3(256), 0, s, V, n, out);
+}
+
+__global__ void k_scale_to_c64(const cx<double>* V, int64_t n, int nrhs, const double* norms,
+                               cx<float>* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const double nr = norms[e / n];
+  const double sc = nr > 0.0 ? 1.0 / nr : 0.0;
+  out[e] = cx<float>{(float)(V[e].x * sc), (float)(V[e].y * sc)};
+}
+void launch_scale_to_c64(const cx<double>* V, int64_t n, int nrhs, const double* norms,
+                         cx<float>* out, hipStream_t s) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(k_scale_to_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, n,
+                     nrhs, norms, out);
+}
+
+__global__ void k_axpy_from_c64(const cx<float>* d, int64_t n, int nrhs, const double* norms,
+                                cx<double>* x) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const double nr = norms ? norms[e / n] : 1.0;
+  x[e].x += nr * (double)d[e].x;
+  x[e].y += nr * (double)d[e].y;
+}
+void launch_axpy_from_c64(const cx<float>* d, int64_t n, int nrhs, const double* norms,
+                          cx<double>* x, hipStream_t s) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(k_axpy_from_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d, n,
+                     nrhs, norms, x);
+}
+
+__global__ void k_cast_c64(const cx<double>* V, int64_t tot, cx<float>* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  out[e] = cx<float>{(float)V[e].x, (float)V[e].y};
+}
+void launch_cast_c64(const cx<double>* V, int64_t n, int nrhs, cx<float>* out, hipStream_t s) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(k_cast_c64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, tot, out);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void k_add_c128(cx<double>* x, const cx<double>* d, int64_t tot) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < tot) x[e] = x[e] + d[e];
+}
+void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_t s) {
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_add_c128, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, d, tot);
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+#define RSS_INST(R)                                                                                \
+  template void launch_leaf_assemble<R>(const Level<R>&, const KParams&, const double*,           \
+                                        hipStream_t);                                              \
+  template void launch_build_C<R>(const Level<R>&, const Phase<R>&, const KParams&, const double*, \
+                                  int, hipStream_t);                                               \
+  template void launch_cpqr<R>(const Level<R>&, const Phase<R>&, const Records<R>&, double, int,   \
+                               int, hipStream_t);                                                  \
+  template void launch_sparsify<R>(const Level<R>&, const Phase<R>&, const Records<R>&,            \
+                                   hipStream_t);                                                   \
+  template void launch_inverse<R>(const Phase<R>&, const Records<R>&, int*, int, hipStream_t);     \
+  template void launch_plan_y<R>(const Phase<R>&, const Records<R>&, GemmDesc<R>*, hipStream_t);   \
+  template void launch_compact<R>(const Level<R>&, const Phase<R>&, const Records<R>&,             \
+                                  hipStream_t);                                                    \
+  template void launch_plan_schur<R>(const Level<R>&, const Phase<R>&, const Records<R>&,          \
+                                     GemmDesc<R>*, hipStream_t);                                   \
+  template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t);                    \
+  template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
+                                         const Level<R>*, cx<R>*, const KParams&, const double*,   \
+                                         hipStream_t);                                             \
+  template int launch_root_inverse<R>(cx<R>*, cx<R>*, int, unsigned long long*, int*, int*,        \
+                                      hipStream_t);                                                \
+  template void launch_solve_fwd<R>(const Phase<R>&, const Records<R>&, cx<R>*, int64_t, int, int, \
+                                    int, hipStream_t);                                             \
+  template void launch_solve_bwd<R>(const Phase<R>&, const Records<R>&, cx<R>*, int64_t, int, int, \
+                                    int, int, hipStream_t);                                        \
+  template void launch_gather_rows<R>(const cx<R>*, int64_t, const int*, int, int, cx<R>*,         \
+                                      hipStream_t);                                                \
+  template void launch_scatter_rows<R>(const cx<R>*, const int*, int, int, cx<R>*, int64_t,        \
+                                       hipStream_t);
+
+RSS_INST(double)
+RSS_INST(float)
+
+}  // namespace rss

@@ -1,0 +1,228 @@
+"""Python binding of librss (ctypes).  Argument marshalling only: every step
+of the factorization and the solve runs in the library's HIP kernels; torch is
+used for device memory and the current stream.
+
+The library must have been built (``python -m paper_2310_15458_amd.build``);
+importing the binding without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librss.so")
+
+RSS_OK, RSS_EINVAL, RSS_ENOMEM, RSS_EUNSUPPORTED, RSS_ESINGULAR, RSS_ENOCONV, RSS_EHIP = 0, -1, -2, -3, -4, -5, -6
+RSS_FP64, RSS_FP32_REFINE = 0, 1
+_KIND = {"laplace": 0, "helmholtz": 1, "degenerate": 2}
+
+
+class rss_kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("kappa", ctypes.c_double), ("weight", ctypes.c_double),
+                ("diag", ctypes.c_double), ("q", ctypes.c_int)]
+
+
+class rss_options(ctypes.Structure):
+    _fields_ = [("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
+                ("precision", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("max_refine", ctypes.c_int), ("root", ctypes.c_double * 3),
+                ("stream", ctypes.c_void_p)]
+
+
+class rss_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("depth", ctypes.c_int), ("precision", ctypes.c_int),
+                ("n_root", ctypes.c_int), ("boxes_compressed", ctypes.c_int64),
+                ("rank_sum", ctypes.c_int64 * 16), ("box_count", ctypes.c_int64 * 16),
+                ("redundant_sum", ctypes.c_int64 * 16),
+                ("flops_id", ctypes.c_double), ("flops_lu", ctypes.c_double),
+                ("flops_y", ctypes.c_double), ("flops_schur", ctypes.c_double),
+                ("factor_bytes", ctypes.c_double), ("kernel_evals", ctypes.c_double),
+                ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("last_relres", ctypes.c_double), ("last_iters", ctypes.c_int),
+                ("device_bytes", ctypes.c_double)]
+
+
+EXPORTS = ["rss_factor", "rss_factor_ex", "rss_solve", "rss_apply", "rss_free", "rss_info",
+           "rss_skeletons", "rss_kernel_block", "rss_residual", "rss_last_error",
+           "rss_error_string"]
+
+_lib = None
+
+
+class RSSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def load():
+    """Load librss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2310_15458_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.rss_factor.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(rss_kernel), ctypes.c_double,
+                               ctypes.c_int, P(ctypes.c_void_p)]
+    lib.rss_factor_ex.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(rss_kernel), ctypes.c_double,
+                                  ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
+    lib.rss_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.rss_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.rss_free.argtypes = [ctypes.c_void_p]
+    lib.rss_free.restype = None
+    lib.rss_info.argtypes = [ctypes.c_void_p, P(rss_stats)]
+    lib.rss_skeletons.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_int32), P(ctypes.c_int64),
+                                  ctypes.c_int64, P(ctypes.c_int64)]
+    lib.rss_kernel_block.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    lib.rss_residual.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.rss_last_error.restype = ctypes.c_char_p
+    lib.rss_error_string.restype = ctypes.c_char_p
+    lib.rss_error_string.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != RSS_OK:
+        lib = load()
+        raise RSSError(rc, f"{lib.rss_error_string(rc).decode()}: {lib.rss_last_error().decode()}")
+
+
+def make_kernel(kern) -> rss_kernel:
+    """From any object with kind/kappa/weight/diag/q (e.g. workloads.Kernel)."""
+    return rss_kernel(_KIND[kern.kind], float(kern.kappa), float(kern.weight), float(kern.diag),
+                      int(getattr(kern, "q", 2)))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Factorization:
+    """An RS-S factorization resident on the GPU (rss_factor_ex)."""
+
+    def __init__(self, points, kern, tol: float, leaf: int, precision: str = "fp64",
+                 n_proxy: int = 0, proxy_radius: float = 0.0, refine_tol: float = 0.0,
+                 max_refine: int = 0, root=None, stream=None):
+        lib = load()
+        P = np.ascontiguousarray(points, dtype=np.float64)
+        self.N = P.shape[0]
+        self.kernel = kern
+        self._k = make_kernel(kern)
+        opt = rss_options()
+        opt.n_proxy = int(n_proxy)
+        opt.proxy_radius = float(proxy_radius)
+        opt.precision = RSS_FP32_REFINE if precision in ("fp32", "fp32_refine", RSS_FP32_REFINE) else RSS_FP64
+        opt.refine_tol = float(refine_tol)
+        opt.max_refine = int(max_refine)
+        if root is not None:
+            opt.root[0], opt.root[1], opt.root[2] = (float(v) for v in root)
+        opt.stream = _stream_ptr(stream).value
+        self._stream = opt.stream
+        h = ctypes.c_void_p()
+        _check(lib.rss_factor_ex(P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,
+                                 ctypes.byref(self._k), float(tol), int(leaf), ctypes.byref(opt),
+                                 ctypes.byref(h)))
+        self._h = h
+
+    def _b(self, B):
+        import torch
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.complex128):
+            raise TypeError("B must be a complex128 CUDA tensor")
+        if B.shape[0] != self.N:
+            raise ValueError("B must have N rows")
+        nrhs = 1 if B.dim() == 1 else B.shape[1]
+        if B.dim() == 2 and not B.t().is_contiguous():
+            raise ValueError("B must be column-major (use X.t().contiguous().t())")
+        return nrhs
+
+    def solve(self, B):
+        """Overwrite B (N x nrhs, complex128, column-major CUDA tensor) with A^{-1} B
+        (refined in the FP32 form).  Returns the status code (RSS_OK or RSS_ENOCONV)."""
+        nrhs = self._b(B)
+        rc = load().rss_solve(self._h, ctypes.c_void_p(B.data_ptr()), nrhs)
+        if rc not in (RSS_OK, RSS_ENOCONV):
+            _check(rc)
+        return rc
+
+    def apply(self, B):
+        """Overwrite B with one application of the factored inverse (no refinement)."""
+        nrhs = self._b(B)
+        _check(load().rss_apply(self._h, ctypes.c_void_p(B.data_ptr()), nrhs))
+
+    def info(self) -> dict:
+        s = rss_stats()
+        _check(load().rss_info(self._h, ctypes.byref(s)))
+        out = {f: getattr(s, f) for f, _ in rss_stats._fields_}
+        for f in ("rank_sum", "box_count", "redundant_sum"):
+            out[f] = list(out[f])
+        return out
+
+    def skeletons(self, depth: int):
+        """{box: sorted skeleton ids} for one compressed depth (boxes with points)."""
+        lib = load()
+        nbox = 4 ** depth
+        counts = (ctypes.c_int32 * nbox)()
+        total = ctypes.c_int64()
+        _check(lib.rss_skeletons(self._h, depth, counts, None, 0, ctypes.byref(total)))
+        ids = (ctypes.c_int64 * max(1, total.value))()
+        _check(lib.rss_skeletons(self._h, depth, counts, ids, total.value, ctypes.byref(total)))
+        out, pos = {}, 0
+        arr = np.frombuffer(ids, dtype=np.int64, count=total.value)
+        for b in range(nbox):
+            c = counts[b]
+            if c < 0:
+                continue
+            out[b] = arr[pos:pos + c].copy()
+            pos += c
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rss_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kernel_block(kern, points_dev, I_dev, J_dev):
+    """A[I, J] evaluated on the device (complex128, ni x nj column-major tensor)."""
+    import torch
+    ni, nj = I_dev.numel(), J_dev.numel()
+    out = torch.empty((nj, ni), dtype=torch.complex128, device=points_dev.device).t()
+    k = make_kernel(kern)
+    _check(load().rss_kernel_block(ctypes.byref(k), ctypes.c_void_p(points_dev.data_ptr()),
+                                   points_dev.shape[0], ctypes.c_void_p(I_dev.data_ptr()), ni,
+                                   ctypes.c_void_p(J_dev.data_ptr()), nj,
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(None)))
+    return out
+
+
+def residual(kern, points_dev, X, B):
+    """R = B - A X in FP64 with A evaluated on the fly (all complex128, column-major)."""
+    import torch
+    n = points_dev.shape[0]
+    nrhs = 1 if X.dim() == 1 else X.shape[1]
+    R = torch.empty((nrhs, n), dtype=torch.complex128, device=X.device).t()
+    k = make_kernel(kern)
+    _check(load().rss_residual(ctypes.byref(k), ctypes.c_void_p(points_dev.data_ptr()), n,
+                               ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                               ctypes.c_void_p(R.data_ptr()), nrhs, _stream_ptr(None)))
+    return R

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every function include/rss.h declares
+(no GPU needed: only the symbol table is inspected), and the header's
+structs match the binding's ctypes mirrors in field order."""
+import os
+import re
+
+import pytest
+
+from paper_2310_15458_amd import rss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rss.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rss_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["rss_factor", "rss_factor_ex", "rss_solve", "rss_free"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(rss.LIB_PATH):
+        pytest.fail("librss.so is not built (run __graft_entry__.build())")
+    lib = rss.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(rss.EXPORTS) == _declared()
+
+
+def test_error_strings_without_gpu():
+    lib = rss.load()
+    for code, name in [(0, b"RSS_OK"), (-1, b"RSS_EINVAL"), (-4, b"RSS_ESINGULAR"), (-5, b"RSS_ENOCONV")]:
+        assert lib.rss_error_string(code) == name
+
+
+def _struct_fields(name):
+    src = open(HEADER).read()
+    end = re.search(r"\}\s*" + name + ";", src).start()
+    start = src.rfind("typedef struct {", 0, end) + len("typedef struct {")
+    body = re.sub(r"/\*.*?\*/", "", src[start:end], flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        if "(" in decl:
+            continue
+        ident = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[\d+\])?\s*$", decl)
+        out.append(ident[0])
+    return out
+
+
+@pytest.mark.parametrize("cname,py", [("rss_kernel", rss.rss_kernel), ("rss_options", rss.rss_options),
+                                      ("rss_stats", rss.rss_stats)])
+def test_struct_mirrors(cname, py):
+    assert _struct_fields(cname) == [f for f, _ in py._fields_]

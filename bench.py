@@ -1,0 +1,249 @@
+"""Benchmark of the RS-S hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: Helmholtz kappa = 50 on the 512 x 512 cell-centre grid of [0,1]^2
+(N = 262144), A_ij = h^2 (i/4) H0^(1)(kappa |x_i - x_j|), A_ii = 1, leaf 64,
+ID tolerance 1e-6, 128 proxy points, 16 complex N(0,1) right-hand sides
+(seed 2).  Synthetic inputs; everything resident on the GPU before timing.
+
+One step = the whole hot path, both precision forms:
+  1. factor in complex64 (FP64 pivot/rank decisions)          -> t_fact32
+  2. solve 16 RHS, FP64-refined to relres <= 1e-10              -> t_solve32
+  3. factor in complex128                                       -> t_fact64
+  4. solve 16 RHS in complex128, FP64-refined to relres <= 1e-10 -> t_solve64
+  5. SOLVE_REPS single applications of each factorization (latency samples)
+
+The headline value is factor unknowns/s of the FP32+refine form,
+N * K / sum(t_fact32); the FP64 figure, times to 1e-10 and solve p50/p99 are
+reported beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SOLVE_REPS = 20
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TF = 78.6
+FP32_MFMA_PEAK_TF = 157.3
+
+
+def cpu_baseline():
+    """The oracle, as it stands, on a bounded sample of the same workload: the
+    128 x 128 corner of the 512^2 grid (same h, kappa, weight, tol, leaf, proxy
+    count), FP64 factorization, BLAS limited to one thread."""
+    import threadpoolctl
+    from oracle import rss as orss
+    from paper_2310_15458_amd import workloads as W
+    w = W.helmholtz_512()
+    P = W.grid_points(w.n)
+    side = 128
+    ix = np.arange(w.n * w.n) % w.n
+    iy = np.arange(w.n * w.n) // w.n
+    sel = (ix < side) & (iy < side)
+    Ps = P[sel]
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        orss.factor(Ps, w.kernel, w.tol, w.leaf, orss.Options(n_proxy=w.n_proxy),
+                    root=(0.0, 0.0, side / w.n))
+        dt = time.perf_counter() - t0
+    return {"value": Ps.shape[0] / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 factorization of the {side}x{side} corner of the 512^2 grid "
+                      f"({Ps.shape[0]} unknowns, same h/kappa/tol/leaf), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the path is single-device); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_15458_amd import rss, workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rss.load()
+    w = W.helmholtz_512()
+    P = W.grid_points(w.n)
+    nrhs = w.nrhs[0]
+    B_host = W.rhs(w.N, nrhs, w.seed)
+    B = torch.from_numpy(np.ascontiguousarray(B_host.T)).to(dev).t()
+    work = torch.empty_like(B)
+    single = torch.empty_like(B)
+
+    def step(record):
+        t = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F32 = rss.Factorization(P, w.kernel, w.tol, w.leaf, precision="fp32", n_proxy=w.n_proxy)
+        t["fact32"] = time.perf_counter() - t0
+        work.copy_(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc32 = F32.solve(work)
+        t["solve32"] = time.perf_counter() - t0
+        i32 = F32.info()
+        lat32 = []
+        for _ in range(SOLVE_REPS):
+            single.copy_(B)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F32.apply(single)
+            lat32.append(time.perf_counter() - t0)
+        F32.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F64 = rss.Factorization(P, w.kernel, w.tol, w.leaf, precision="fp64", n_proxy=w.n_proxy,
+                                max_refine=10, refine_tol=1e-10)
+        t["fact64"] = time.perf_counter() - t0
+        work.copy_(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc64 = F64.solve(work)
+        t["solve64"] = time.perf_counter() - t0
+        i64 = F64.info()
+        lat64 = []
+        for _ in range(SOLVE_REPS):
+            single.copy_(B)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F64.apply(single)
+            lat64.append(time.perf_counter() - t0)
+        F64.close()
+        if record is not None:
+            record.append({"t": t, "i32": i32, "i64": i64, "rc": (rc32, rc64),
+                           "lat32": lat32, "lat64": lat64})
+
+    for _ in range(args.warmup):
+        step(None)
+    recs = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+
+    N = w.N
+    f32 = sum(r["t"]["fact32"] for r in recs)
+    f64 = sum(r["t"]["fact64"] for r in recs)
+    s32 = [r["t"]["solve32"] for r in recs]
+    s64 = [r["t"]["solve64"] for r in recs]
+    lat32 = np.array([x for r in recs for x in r["lat32"]]) * 1e3  # ms
+    lat64 = np.array([x for r in recs for x in r["lat64"]]) * 1e3
+    i32, i64 = recs[-1]["i32"], recs[-1]["i64"]
+
+    # live per-kernel-class times (HIP events on the library's stream = torch's
+    # current stream), from one profiled factorization of each form
+    prof = {}
+    for prec in ("fp32", "fp64"):
+        Fp = rss.Factorization(P, w.kernel, w.tol, w.leaf, precision=prec, n_proxy=w.n_proxy, profile=True)
+        prof[prec] = Fp.info()
+        Fp.close()
+    # the dominant kernel: the FP64 on-the-fly residual r = b - A x of the refinement,
+    # timed with torch events on the stream it is launched on
+    Pd = torch.from_numpy(P).to(dev)
+    R = None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rss.residual(w.kernel, Pd, B, B)  # warm
+    torch.cuda.synchronize()
+    nres = 2
+    ev0.record()
+    for _ in range(nres):
+        R = rss.residual(w.kernel, Pd, B, B)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_res = ev0.elapsed_time(ev1) / nres / 1e3
+    res_flops = 8.0 * N * N * nrhs          # the complex multiply-adds of A x (8 flops each)
+    roofline = {"kernel": "k_residual (FP64 on-the-fly b - A x, 16 RHS)", "bound": "alu",
+                "achieved": res_flops / t_res / 1e12, "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
+                "frac": res_flops / t_res / 1e12 / FP64_PEAK_TF, "traffic": None,
+                "t_launch_ms": t_res * 1e3, "pair_evals_per_s": N * N / t_res,
+                "algorithmic": "8 N^2 nrhs flops per launch (kernel evaluations not counted)"}
+
+    def cls_t(info, name):
+        return info["t_class_ms"][rss.KERNEL_CLASSES.index(name)] / 1e3
+
+    steps_roof = {}
+    for prec, peak in (("fp32", FP32_MFMA_PEAK_TF), ("fp64", FP64_PEAK_TF)):
+        info = prof[prec]
+        t_id, t_sc = cls_t(info, "id"), cls_t(info, "schur")
+        steps_roof[prec] = {
+            "id": {"bound": "alu", "achieved": info["flops_id"] / t_id / 1e12,
+                   "peak": FP64_PEAK_TF if prec == "fp64" else 78.6, "unit": "TFLOP/s",
+                   "t_ms": t_id * 1e3},
+            "schur": {"bound": "mfma", "achieved": info["flops_schur"] / t_sc / 1e12, "peak": peak,
+                      "unit": "TFLOP/s", "frac": info["flops_schur"] / t_sc / 1e12 / peak,
+                      "t_ms": t_sc * 1e3},
+            "class_ms": {n: round(info["t_class_ms"][i], 3) for i, n in enumerate(rss.KERNEL_CLASSES)},
+        }
+    for prec, lat, i in (("fp32", lat32, recs[-1]["i32"]), ("fp64", lat64, recs[-1]["i64"])):
+        t = float(np.percentile(lat, 50)) / 1e3
+        steps_roof[prec]["solve"] = {"bound": "hbm", "achieved": i["factor_bytes"] / t / 1e9,
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": i["factor_bytes"] / t / 1e9 / HBM_PEAK_GBS}
+
+    out = {
+        "metric": "RS-S factor unknowns/s at N=512^2 (FP32+refine vs FP64); solve p50/p99",
+        "value": N * len(recs) / f32,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / len(recs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 factor + f64 refine",
+        "data": "synthetic: 512x512 cell-centre grid, complex N(0,1) RHS seed 2",
+        "config": {"workload": "helmholtz kappa=50 N=512^2 tol=1e-6 leaf=64 n_proxy=128 nrhs=16",
+                   "N": N, "nrhs": nrhs, "parallelism": "single GPU"},
+        "fp32_refine": {
+            "factor_unknowns_per_s": N * len(recs) / f32,
+            "t_factor_ms": f32 / len(recs) * 1e3,
+            "t_solve_to_1e-10_ms": float(np.median(s32) * 1e3),
+            "time_to_solution_unknowns_per_s": N / (f32 / len(recs) + float(np.median(s32))),
+            "relres": i32["last_relres"], "refine_steps": i32["last_iters"],
+            "apply_p50_ms": float(np.percentile(lat32, 50)), "apply_p99_ms": float(np.percentile(lat32, 99)),
+            "device_GB": i32["device_bytes"] / 1e9,
+        },
+        "fp64": {
+            "factor_unknowns_per_s": N * len(recs) / f64,
+            "t_factor_ms": f64 / len(recs) * 1e3,
+            "t_solve_to_1e-10_ms": float(np.median(s64) * 1e3),
+            "time_to_solution_unknowns_per_s": N / (f64 / len(recs) + float(np.median(s64))),
+            "relres": i64["last_relres"], "refine_steps": i64["last_iters"],
+            "apply_p50_ms": float(np.percentile(lat64, 50)), "apply_p99_ms": float(np.percentile(lat64, 99)),
+            "device_GB": i64["device_bytes"] / 1e9,
+        },
+        "ranks_fp32": [round(i32["rank_sum"][d] / max(1, i32["box_count"][d]), 2) for d in range(2, i32["depth"] + 1)],
+        "ranks_fp64": [round(i64["rank_sum"][d] / max(1, i64["box_count"][d]), 2) for d in range(2, i64["depth"] + 1)],
+        "ledger_fp32": {k: i32[k] for k in ("flops_id", "flops_lu", "flops_y", "flops_schur",
+                                            "factor_bytes", "kernel_evals")},
+        "roofline": roofline,
+        "roofline_steps": steps_roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

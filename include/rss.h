@@ -72,7 +72,23 @@ typedef struct {
   double root[3];         /* x0, y0, side of the root square; side <= 0 -> [0,1]^2 if every
                              point lies in it, else the bounding square */
   void* stream;           /* hipStream_t for all work; NULL -> a stream owned by the handle */
+  int profile;            /* nonzero: time every kernel class with HIP events on the stream
+                             (rss_stats.t_class_ms); adds a little host overhead */
 } rss_options;
+
+/* kernel classes timed when rss_options.profile is set (index into t_class_ms) */
+enum {
+  RSS_K_ASSEMBLE = 0,     /* leaf blocks, transition and root assembly */
+  RSS_K_BUILD_C = 1,      /* compression matrices (eqs. e:con, e:proxy) */
+  RSS_K_ID = 2,           /* column-pivoted QR interpolative decomposition (Def. 1) */
+  RSS_K_SPARSIFY = 3,     /* sparsification (eq. e:s) */
+  RSS_K_INVERSE = 4,      /* redundant-block inverse (the LU of eq. e:step) */
+  RSS_K_GEMM_Y = 5,       /* Y = X_RR^{-1} [X_RS X_RN] */
+  RSS_K_COMPACT = 6,      /* dropping the redundant rows and columns */
+  RSS_K_SCHUR = 7,        /* Schur-complement update (eq. e:step) */
+  RSS_K_ROOT = 8,         /* dense root inverse */
+  RSS_K_NCLASS = 12
+};
 
 typedef struct rss_ctx* rss_handle;
 
@@ -134,6 +150,8 @@ typedef struct {
   double last_relres;     /* max column relative residual of the last refined solve (-1: none) */
   int last_iters;         /* refinement steps taken by the last rss_solve */
   double device_bytes;    /* device memory held by the handle */
+  double t_class_ms[12];  /* per kernel class, summed over launches (rss_options.profile) */
+  int64_t n_class[12];    /* launches per kernel class */
 } rss_stats;
 
 /* rss_info -- statistics of a factorization (host struct filled). */

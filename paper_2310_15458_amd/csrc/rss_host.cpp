@@ -157,6 +157,58 @@ struct PhaseHost {
   int64_t *d_oC = nullptr, *d_oX = nullptr, *d_oZ = nullptr, *d_oI = nullptr;
 };
 
+// HIP-event timing of kernel classes on the handle's stream (rss_options.profile)
+struct Prof {
+  bool on = false;
+  struct Pair {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pair> pairs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  template <class F>
+  void run(int cls, hipStream_t s, F&& f) {
+    if (!on) {
+      f();
+      return;
+    }
+    Pair p{cls, get(), get()};
+    HIPCHK(hipEventRecord(p.a, s));
+    f();
+    HIPCHK(hipEventRecord(p.b, s));
+    pairs.push_back(p);
+  }
+  // after the stream has drained: add the elapsed times into t / n
+  void collect(double* t, int64_t* n) {
+    for (auto& p : pairs) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+      t[p.cls] += ms;
+      n[p.cls] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pairs.clear();
+  }
+  ~Prof() {
+    for (auto& p : pairs) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct DepthRecords {
   int d = 0, nb = 0;
   int kmax = 0, rmax = 0, snmax = 0;
@@ -198,6 +250,7 @@ struct rss_ctx {
   std::vector<std::vector<int>> skel_k;          // per compressed depth: k per box (-1 empty)
   std::vector<std::vector<int64_t>> skel_ids;    // per compressed depth: concatenated ids
   rss_stats stats{};
+  Prof prof;
   int* d_err = nullptr;
   // solve workspaces (grown on demand)
   void* ws_root = nullptr;
@@ -363,7 +416,7 @@ void factor_impl(rss_ctx* h, const double* points) {
       for (int64_t i = 0; i < N; ++i) cur.idx[fillp[bo[i]]++] = (int)i;
       alloc_level(h, cur, E);
       Level<R> L = dev_level<R>(cur, h->x0, h->y0, h->s0);
-      launch_leaf_assemble<R>(L, kp, h->d_P, s);
+      h->prof.run(RSS_K_ASSEMBLE, s, [&] { launch_leaf_assemble<R>(L, kp, h->d_P, s); });
       kevals += (double)cur.nA;
     }
     for (int d = D;; --d) {
@@ -464,15 +517,15 @@ void factor_impl(rss_ctx* h, const double* points) {
       for (int c = 0; c < 9; ++c) {
         Phase<R> ph = dev_phase<R>(dr.ph[c], W, Wi, mrow, npx, crad);
         if (ph.nbox == 0) continue;
-        launch_build_C<R>(L, ph, kp, h->d_P, chunks, s);
-        launch_cpqr<R>(L, ph, rec, h->tol, cur.nmax, mmax, s);
-        launch_sparsify<R>(L, ph, rec, s);
-        launch_inverse<R>(ph, rec, h->d_err, cur.nmax, s);
+        h->prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(L, ph, kp, h->d_P, chunks, s); });
+        h->prof.run(RSS_K_ID, s, [&] { launch_cpqr<R>(L, ph, rec, h->tol, cur.nmax, mmax, s); });
+        h->prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(L, ph, rec, s); });
+        h->prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(ph, rec, h->d_err, cur.nmax, s); });
         launch_plan_y<R>(ph, rec, desc, s);
-        launch_gemm<R>(desc, ph.nbox, cur.nmax, cur.nmax + cur.nNmax, s);
-        launch_compact<R>(L, ph, rec, s);
+        h->prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, cur.nmax, cur.nmax + cur.nNmax, s); });
+        h->prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(L, ph, rec, s); });
         launch_plan_schur<R>(L, ph, rec, desc, s);
-        launch_gemm<R>(desc, ph.nbox * 81, cur.nmax, cur.nmax, s);
+        h->prof.run(RSS_K_SCHUR, s, [&] { launch_gemm<R>(desc, ph.nbox * 81, cur.nmax, cur.nmax, s); });
       }
       HIPCHK(hipGetLastError());
       // read back the ranks and the surviving ids of this depth
@@ -489,6 +542,7 @@ void factor_impl(rss_ctx* h, const double* points) {
       if (!ids.empty())
         HIPCHK(hipMemcpyAsync(ids.data(), cur.d_idx, ids.size() * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      h->prof.collect(h->stats.t_class_ms, h->stats.n_class);
       dr.n0 = cur.n0;
       h->arena.release(W);
       h->arena.release(Wi);
@@ -587,8 +641,10 @@ void factor_impl(rss_ctx* h, const double* points) {
       Level<R> child = dev_level<R>(cur, h->x0, h->y0, h->s0);
       PairDesc* d_pds = h->arena.up(pds, s);
       ListEntry* d_lists = h->arena.up(lists, s);
-      launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, par.nmax, par.nmax, &child,
-                               (cx<R>*)par.d_A, kp, h->d_P, s);
+      h->prof.run(RSS_K_ASSEMBLE, s, [&] {
+        launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, par.nmax, par.nmax, &child,
+                                 (cx<R>*)par.d_A, kp, h->d_P, s);
+      });
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
       h->arena.release(d_pds);
@@ -624,11 +680,16 @@ void factor_impl(rss_ctx* h, const double* points) {
     Level<R> child{};
     const bool have = D >= MIN_DEPTH;
     if (have) child = dev_level<R>(cur, h->x0, h->y0, h->s0);
-    launch_assemble_pairs<R>(d_pds, 1, d_list, nr, nr, have ? &child : nullptr, (cx<R>*)A, kp,
-                             h->d_P, s);
+    h->prof.run(RSS_K_ASSEMBLE, s, [&] {
+      launch_assemble_pairs<R>(d_pds, 1, d_list, nr, nr, have ? &child : nullptr, (cx<R>*)A, kp,
+                               h->d_P, s);
+    });
     unsigned long long* keys = (unsigned long long*)h->arena.alloc((size_t)nr * 8);
     int* perm = (int*)h->arena.alloc((size_t)nr * 2 * sizeof(int));
-    const int where = launch_root_inverse<R>((cx<R>*)A, (cx<R>*)tmp, nr, keys, perm, h->d_err, s);
+    int where = 0;
+    h->prof.run(RSS_K_ROOT, s, [&] {
+      where = launch_root_inverse<R>((cx<R>*)A, (cx<R>*)tmp, nr, keys, perm, h->d_err, s);
+    });
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     h->arena.release(d_pds);
@@ -649,6 +710,7 @@ void factor_impl(rss_ctx* h, const double* points) {
   if (D >= MIN_DEPTH) free_level(h, cur);
   HIPCHK(hipEventRecord(ev1, s));
   HIPCHK(hipEventSynchronize(ev1));
+  h->prof.collect(h->stats.t_class_ms, h->stats.n_class);
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
   (void)hipEventDestroy(ev0);
@@ -766,6 +828,7 @@ int rss_factor_ex(const double* points, int64_t n, const rss_kernel* k, double t
     if (h->opt.precision != RSS_FP64 && h->opt.precision != RSS_FP32_REFINE)
       fail(RSS_EINVAL, "unknown precision");
     h->precision = h->opt.precision;
+    h->prof.on = h->opt.profile != 0;
     h->stats.precision = h->precision;
     h->stats.n = n;
     h->stats.last_relres = -1.0;

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "librss.so")
 
 RSS_OK, RSS_EINVAL, RSS_ENOMEM, RSS_EUNSUPPORTED, RSS_ESINGULAR, RSS_ENOCONV, RSS_EHIP = 0, -1, -2, -3, -4, -5, -6
 RSS_FP64, RSS_FP32_REFINE = 0, 1
+KERNEL_CLASSES = ["assemble", "build_C", "id", "sparsify", "inverse", "gemm_y", "compact", "schur",
+                  "root"]
 _KIND = {"laplace": 0, "helmholtz": 1, "degenerate": 2}
 
 
@@ -29,7 +31,7 @@ class rss_options(ctypes.Structure):
     _fields_ = [("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
                 ("precision", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int), ("root", ctypes.c_double * 3),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("profile", ctypes.c_int)]
 
 
 class rss_stats(ctypes.Structure):
@@ -42,7 +44,8 @@ class rss_stats(ctypes.Structure):
                 ("factor_bytes", ctypes.c_double), ("kernel_evals", ctypes.c_double),
                 ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("last_relres", ctypes.c_double), ("last_iters", ctypes.c_int),
-                ("device_bytes", ctypes.c_double)]
+                ("device_bytes", ctypes.c_double), ("t_class_ms", ctypes.c_double * 12),
+                ("n_class", ctypes.c_int64 * 12)]
 
 
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_solve", "rss_apply", "rss_free", "rss_info",
@@ -116,7 +119,7 @@ class Factorization:
 
     def __init__(self, points, kern, tol: float, leaf: int, precision: str = "fp64",
                  n_proxy: int = 0, proxy_radius: float = 0.0, refine_tol: float = 0.0,
-                 max_refine: int = 0, root=None, stream=None):
+                 max_refine: int = 0, root=None, stream=None, profile: bool = False):
         lib = load()
         P = np.ascontiguousarray(points, dtype=np.float64)
         self.N = P.shape[0]
@@ -131,6 +134,7 @@ class Factorization:
         if root is not None:
             opt.root[0], opt.root[1], opt.root[2] = (float(v) for v in root)
         opt.stream = _stream_ptr(stream).value
+        opt.profile = 1 if profile else 0
         self._stream = opt.stream
         h = ctypes.c_void_p()
         _check(lib.rss_factor_ex(P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,
@@ -167,7 +171,7 @@ class Factorization:
         s = rss_stats()
         _check(load().rss_info(self._h, ctypes.byref(s)))
         out = {f: getattr(s, f) for f, _ in rss_stats._fields_}
-        for f in ("rank_sum", "box_count", "redundant_sum"):
+        for f in ("rank_sum", "box_count", "redundant_sum", "t_class_ms", "n_class"):
             out[f] = list(out[f])
         return out
 

@@ -61,6 +61,36 @@ def cpu_baseline():
                       f"({Ps.shape[0]} unknowns, same h/kappa/tol/leaf), {dt:.1f} s"}
 
 
+def batched_sweep(torch, rss, W, reps=2):
+    """256 independent problems (n uniform over {32,48,64,96,128}, Laplace or
+    Helmholtz kappa ~ U[5,40], leaf 64, tol 1e-6, FP64, one RHS each, seed 3),
+    factored in one batched sweep and solved in one batched apply."""
+    probs = W.batched_problems()
+    Ps = [W.grid_points(p.n) for p in probs]
+    Ks = [p.kernel for p in probs]
+    Bs = [torch.from_numpy(np.ascontiguousarray(p.rhs.T)).cuda().t() for p in probs]
+    tot = sum(P.shape[0] for P in Ps)
+    tf, ta = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rss.factor_batch(Ps, Ks, 1e-6, 64)
+        t1 = time.perf_counter()
+        X = [B.clone() for B in Bs]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rss.apply_batch(F, X)
+        t3 = time.perf_counter()
+        for f in F[::-1]:
+            f.close()
+        if r > 0:
+            tf.append(t1 - t0)
+            ta.append(t3 - t2)
+    return {"problems": len(probs), "unknowns": tot,
+            "factor_ms": float(np.median(tf) * 1e3), "factor_unknowns_per_s": tot / float(np.median(tf)),
+            "apply_ms": float(np.median(ta) * 1e3), "apply_unknowns_per_s": tot / float(np.median(ta))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +270,7 @@ def main():
         "roofline_steps": steps_roof,
         "cpu_baseline": None,
     }
+    out["batched"] = batched_sweep(torch, rss, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -127,6 +127,31 @@ int rss_solve(rss_handle h, void* B, int nrhs);
 /* rss_apply -- one application of the factored inverse, no refinement. */
 int rss_apply(rss_handle h, void* B, int nrhs);
 
+/*
+ * rss_factor_batch -- factor nprob independent problems together: at every
+ * height above the leaves, each colour phase is one set of launches over the
+ * boxes of all problems that have that depth (Alg. a:fact applied to each
+ * problem; the problems share no data).
+ *   points[p], n[p], kernels[p] : as in rss_factor for problem p.
+ *   tol, leaf, opt              : shared by all problems (opt->n_proxy = 0 picks
+ *                                 the per-kernel default for each problem).
+ *   out                         : nprob handles, each usable and freed on its own;
+ *                                 all NULL on failure.
+ * The handles share one stream (opt->stream, or one the library creates and
+ * destroys with the last of them).
+ */
+int rss_factor_batch(int nprob, const double* const* points, const int64_t* n,
+                     const rss_kernel* kernels, double tol, int leaf, const rss_options* opt,
+                     rss_handle* out);
+
+/*
+ * rss_apply_batch -- one application of each factored inverse to its own
+ * right-hand sides, all problems in one set of launches per (height, colour).
+ *   hs[p]   : handles of one precision.  B[p] : device complex128, n_p x nrhs[p],
+ *   column-major, overwritten.  Work runs on the stream of hs[0].
+ */
+int rss_apply_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs);
+
 /* rss_free -- release the handle and its device memory (NULL is a no-op). */
 void rss_free(rss_handle h);
 

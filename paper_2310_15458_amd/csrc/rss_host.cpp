@@ -150,11 +150,9 @@ struct LevelHost {
 };
 
 struct PhaseHost {
-  std::vector<int> boxes;
-  int64_t C_total = 0, X_total = 0, Z_total = 0, I_total = 0;
-  std::vector<int64_t> oC, oX, oZ, oI;
+  std::vector<int> boxes;  // boxes of one colour, ascending id
   int* d_box = nullptr;
-  int64_t *d_oC = nullptr, *d_oX = nullptr, *d_oZ = nullptr, *d_oI = nullptr;
+  int* d_prob = nullptr;   // all zero: the single-problem solve
 };
 
 // HIP-event timing of kernel classes on the handle's stream (rss_options.profile)
@@ -236,7 +234,7 @@ struct rss_ctx {
   int precision = RSS_FP64;
   int refine_steps = -1;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
+  std::shared_ptr<void> stream_owner;  // destroys a library-created stream with its last handle
   double x0 = 0, y0 = 0, s0 = 1;
   int D = 0;
   Arena arena;
@@ -245,16 +243,15 @@ struct rss_ctx {
   int n_root = 0;
   int* d_root_ids = nullptr;
   void* d_root_inv = nullptr;
-  void* d_gemm_desc = nullptr;  // one descriptor for the root apply
+  void* root_spare = nullptr;
+  std::vector<double> h_points;     // host copy of the points (planner)
+  std::vector<LevelHost> tmp_levels;
   std::vector<int64_t> skel_counts_off;
   std::vector<std::vector<int>> skel_k;          // per compressed depth: k per box (-1 empty)
   std::vector<std::vector<int64_t>> skel_ids;    // per compressed depth: concatenated ids
   rss_stats stats{};
   Prof prof;
   int* d_err = nullptr;
-  // solve workspaces (grown on demand)
-  void* ws_root = nullptr;
-  size_t ws_root_bytes = 0;
 };
 
 namespace {
@@ -332,25 +329,7 @@ Records<R> dev_records(const DepthRecords& d) {
   return r;
 }
 
-template <class R>
-Phase<R> dev_phase(const PhaseHost& p, void* W, int* Wi, int* mrow, int npx, double crad) {
-  Phase<R> ph;
-  ph.nbox = (int)p.boxes.size();
-  ph.box = p.d_box;
-  ph.oC = p.d_oC;
-  ph.oX = p.d_oX;
-  ph.oZ = p.d_oZ;
-  ph.oI = p.d_oI;
-  ph.mrow = mrow;
-  ph.W = (cx<R>*)W;
-  ph.Wi = Wi;
-  ph.n_proxy = npx;
-  ph.proxy_radius = crad;
-  return ph;
-}
-
-void alloc_level(rss_ctx* h, LevelHost& L, size_t elem) {
-  hipStream_t s = h->stream;
+void alloc_level(rss_ctx* h, LevelHost& L, size_t elem, hipStream_t s) {
   L.d_n0 = h->arena.up(L.n0, s);
   L.d_cur = h->arena.up(L.n0, s);
   L.d_idx = h->arena.up(L.idx, s);
@@ -371,71 +350,143 @@ void free_level(rss_ctx* h, LevelHost& L) {
   L.d_A = nullptr;
 }
 
-template <class R>
-void factor_impl(rss_ctx* h, const double* points) {
-  hipStream_t s = h->stream;
-  const int64_t N = h->N;
-  const KParams kp = h->kp;
-  const int npx = h->opt.n_proxy;
-  const double crad = h->opt.proxy_radius;
-  const size_t E = sizeof(cx<R>);
-
-  // tree depth (Sec. 2.1)
-  std::vector<int> bo;
-  int D = 0;
-  for (;; ++D) {
-    if (D > MAX_DEPTH) fail(RSS_EUNSUPPORTED, "tree deeper than 15 levels");
-    box_of(points, N, h->x0, h->y0, h->s0, D, bo);
-    std::vector<int> cnt((size_t)1 << (2 * D), 0);
-    int mx = 0;
-    for (int64_t i = 0; i < N; ++i) mx = std::max(mx, ++cnt[bo[i]]);
-    if (mx <= h->leaf) break;
+// temporary device buffers of one batched operation
+struct Scratch {
+  std::vector<void*> ptrs;
+  void* alloc(size_t n) {
+    if (n == 0) n = 16;
+    void* p = nullptr;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    return p;
   }
-  h->D = D;
-  h->stats.depth = D;
+  template <class T>
+  T* up(const std::vector<T>& v, hipStream_t s) {
+    T* p = (T*)alloc(v.size() * sizeof(T));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return p;
+  }
+  void clear() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  ~Scratch() { clear(); }
+};
 
+// Per-problem state while a batch is being factored.
+struct Work {
+  rss_ctx* h = nullptr;
+  std::vector<int> bo;        // leaf box of every point
+  LevelHost cur;
+  bool active = false;        // has a level at the current height
+  std::vector<ListEntry> root_list;
+  double flops_id = 0, flops_lu = 0, flops_y = 0, flops_schur = 0, fbytes = 0, kevals = 0;
+};
+
+std::vector<ListEntry> sorted_union(const std::vector<int>& boxes, const std::vector<int>& curk,
+                                    const std::vector<int>& ids, const std::vector<int64_t>& ioff) {
+  std::vector<ListEntry> out;
+  for (int c : boxes)
+    for (int q = 0; q < curk[c]; ++q) out.push_back({c, q, ids[ioff[c] + q]});
+  std::sort(out.begin(), out.end(), [](const ListEntry& a, const ListEntry& b) { return a.gid < b.gid; });
+  return out;
+}
+
+// Batched RS-S factorization (Alg. a:fact) of every handle in H, all on stream s.
+// Heights above the leaves are aligned: at height t every problem with
+// D - t >= 2 eliminates its boxes of depth D - t, colour by colour, and each
+// colour is one launch per step over the boxes of all those problems.
+template <class R>
+void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
+  const size_t E = sizeof(cx<R>);
+  const int np = (int)H.size();
+  std::vector<Work> W(np);
+  Prof& prof = H[0]->prof;
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventRecord(ev0, s));
-
-  std::vector<int> root_ids;
-  std::vector<ListEntry> root_list;
-  LevelHost cur;
-  double flops_id = 0, flops_lu = 0, flops_y = 0, flops_schur = 0, fbytes = 0, kevals = 0;
-
-  if (D >= MIN_DEPTH) {
-    // leaf level: members sorted by global id
-    {
+  int tmax = -1;
+  int* d_err = H[0]->d_err;
+  for (int p = 0; p < np; ++p) {
+    rss_ctx* h = H[p];
+    W[p].h = h;
+    int D = 0;
+    for (;; ++D) {
+      if (D > MAX_DEPTH) fail(RSS_EUNSUPPORTED, "tree deeper than 15 levels");
+      box_of(h->h_points.data(), h->N, h->x0, h->y0, h->s0, D, W[p].bo);
+      std::vector<int> cnt((size_t)1 << (2 * D), 0);
+      int mx = 0;
+      for (int64_t i = 0; i < h->N; ++i) mx = std::max(mx, ++cnt[W[p].bo[i]]);
+      if (mx <= h->leaf) break;
+    }
+    h->D = D;
+    h->stats.depth = D;
+    if (D >= MIN_DEPTH) {
+      tmax = std::max(tmax, D - MIN_DEPTH);
       const int nbox = 1 << (2 * D);
       std::vector<int> counts(nbox, 0);
-      for (int64_t i = 0; i < N; ++i) counts[bo[i]]++;
-      cur.layout(D, counts);
-      cur.idx.assign(N, 0);
-      std::vector<int64_t> fillp(cur.ioff);
-      for (int64_t i = 0; i < N; ++i) cur.idx[fillp[bo[i]]++] = (int)i;
-      alloc_level(h, cur, E);
-      Level<R> L = dev_level<R>(cur, h->x0, h->y0, h->s0);
-      h->prof.run(RSS_K_ASSEMBLE, s, [&] { launch_leaf_assemble<R>(L, kp, h->d_P, s); });
-      kevals += (double)cur.nA;
+      for (int64_t i = 0; i < h->N; ++i) counts[W[p].bo[i]]++;
+      LevelHost& L = W[p].cur;
+      L.layout(D, counts);
+      L.idx.assign(h->N, 0);
+      std::vector<int64_t> fillp(L.ioff);
+      for (int64_t i = 0; i < h->N; ++i) L.idx[fillp[W[p].bo[i]]++] = (int)i;
+      alloc_level(h, L, E, s);
+      W[p].active = true;
+      W[p].kevals += (double)L.nA;
+    } else {
+      for (int64_t i = 0; i < h->N; ++i) W[p].root_list.push_back({0, 0, (int)i});
     }
-    for (int d = D;; --d) {
-      const int nb = 1 << d, nbox = nb * nb;
+  }
+  Scratch scr;
+  // leaf stencils of every problem: one launch
+  {
+    std::vector<Prob<R>> probs;
+    int maxb = 0;
+    for (int p = 0; p < np; ++p)
+      if (W[p].active) {
+        Prob<R> pr{};
+        pr.L = dev_level<R>(W[p].cur, H[p]->x0, H[p]->y0, H[p]->s0);
+        pr.kp = H[p]->kp;
+        pr.P = H[p]->d_P;
+        probs.push_back(pr);
+        maxb = std::max(maxb, W[p].cur.nb * W[p].cur.nb);
+      }
+    if (!probs.empty()) {
+      Prob<R>* d = scr.up(probs, s);
+      prof.run(RSS_K_ASSEMBLE, s, [&] { launch_leaf_assemble<R>(d, (int)probs.size(), maxb, s); });
+    }
+  }
+  for (int t = 0; t <= tmax; ++t) {
+    // problems eliminating at this height, their depth records and device descriptors
+    std::vector<int> act;
+    for (int p = 0; p < np; ++p)
+      if (W[p].active && H[p]->D - t >= MIN_DEPTH) act.push_back(p);
+    std::vector<Prob<R>> probs(act.size());
+    int nmax = 0, nNmax = 0, mmax = 0;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int p = act[a];
+      rss_ctx* h = H[p];
+      LevelHost& cur = W[p].cur;
+      const int d = cur.d, nb = cur.nb, nbox = nb * nb;
       DepthRecords dr;
       dr.d = d;
       dr.nb = nb;
-      // worst-case record slots
       std::vector<int64_t> oT(nbox), oXi(nbox), oXSNR(nbox), oY(nbox), oS(nbox), oR(nbox), oN(nbox);
       int64_t F = 0, G = 0;
       for (int b = 0; b < nbox; ++b) {
         const int n = cur.n0[b];
         int nN0 = 0;
         for (int x : ring(nb, b, 1)) nN0 += cur.n0[x];
-        const int64_t t = (int64_t)n * n;
+        const int64_t tt = (int64_t)n * n;
         oT[b] = F;
-        F += (t + 3) / 4 + n;
+        F += (tt + 3) / 4 + n;
         oXi[b] = F;
-        F += t;
+        F += tt;
         oXSNR[b] = F;
         F += (int64_t)(n + nN0) * n;
         oY[b] = F;
@@ -464,108 +515,166 @@ void factor_impl(rss_ctx* h, const double* points) {
       dr.d_oN = h->arena.up(oN, s);
       dr.d_F = h->arena.alloc((size_t)F * E);
       dr.d_G = (int*)h->arena.alloc((size_t)G * sizeof(int));
-
-      // phases: colour-major, ascending id; per-slot workspace
-      int64_t Cmax = 0, Xmax = 0, Zmax = 0, Imax = 0;
-      int mmax = 0;
+      // per-problem phase lists (kept for the solve)
       for (int c = 0; c < 9; ++c) {
         PhaseHost& P = dr.ph[c];
-        for (int b = 0; b < nbox; ++b) {
-          if ((b % nb) % 3 + 3 * ((b / nb) % 3) != c || cur.n0[b] == 0) continue;
+        for (int b = 0; b < nbox; ++b)
+          if ((b % nb) % 3 + 3 * ((b / nb) % 3) == c && cur.n0[b] > 0) P.boxes.push_back(b);
+        P.d_box = h->arena.up(P.boxes, s);
+        std::vector<int> zeros(P.boxes.size(), 0);
+        P.d_prob = h->arena.up(zeros, s);
+      }
+      h->recs.push_back(std::move(dr));
+      Prob<R>& pr = probs[a];
+      pr.L = dev_level<R>(cur, h->x0, h->y0, h->s0);
+      pr.rec = dev_records<R>(h->recs.back());
+      pr.kp = h->kp;
+      pr.P = h->d_P;
+      pr.tol = h->tol;
+      pr.n_proxy = h->opt.n_proxy;
+      pr.proxy_radius = h->opt.proxy_radius;
+      nmax = std::max(nmax, cur.nmax);
+      nNmax = std::max(nNmax, cur.nNmax);
+      mmax = std::max(mmax, 2 * cur.msum_max + 2 * h->opt.n_proxy);
+    }
+    Prob<R>* d_probs = scr.up(probs, s);
+    // merged colour phases over all active problems, and one shared workspace
+    struct Merged {
+      std::vector<int> box, prob;
+      std::vector<int64_t> oC, oX, oZ, oI;
+      int64_t tot = 0, itot = 0;
+    } M[9];
+    int64_t Wmax = 0, Imax = 0;
+    int maxph = 0;
+    for (int c = 0; c < 9; ++c) {
+      Merged& G = M[c];
+      int64_t C = 0, X = 0, Z = 0, I = 0;
+      std::vector<int64_t> cx_, xx_, zx_;
+      for (size_t a = 0; a < act.size(); ++a) {
+        const int p = act[a];
+        const LevelHost& cur = W[p].cur;
+        const int nb = cur.nb;
+        for (int b : H[p]->recs.back().ph[c].boxes) {
           const int n = cur.n0[b];
           int msum = 0, nN0 = 0;
           for (int x : ring(nb, b, 2)) msum += cur.n0[x];
           for (int x : ring(nb, b, 1)) nN0 += cur.n0[x];
-          const int m = 2 * msum + 2 * npx;
-          mmax = std::max(mmax, m);
-          P.boxes.push_back(b);
-          P.oC.push_back(P.C_total);
-          P.C_total += (int64_t)m * n;
-          P.oX.push_back(P.X_total);
-          P.X_total += (int64_t)n * n;
-          P.oZ.push_back(P.Z_total);
-          P.Z_total += (int64_t)n * (n + nN0);
-          P.oI.push_back(P.I_total);
-          P.I_total += 3 * n;
+          const int m = 2 * msum + 2 * H[p]->opt.n_proxy;
+          G.box.push_back(b);
+          G.prob.push_back((int)a);
+          cx_.push_back(C);
+          C += (int64_t)m * n;
+          xx_.push_back(X);
+          X += (int64_t)n * n;
+          zx_.push_back(Z);
+          Z += (int64_t)n * (n + nN0);
+          G.oI.push_back(I);
+          I += 3 * n;
         }
-        // C, X and Z share one workspace per slot region
-        for (size_t i = 0; i < P.boxes.size(); ++i) {
-          P.oX[i] += P.C_total;
-          P.oZ[i] += P.C_total + P.X_total;
-        }
-        Cmax = std::max(Cmax, P.C_total + P.X_total + P.Z_total);
-        Imax = std::max(Imax, P.I_total);
-        (void)Xmax;
-        (void)Zmax;
-        P.d_box = h->arena.up(P.boxes, s);
-        P.d_oC = h->arena.up(P.oC, s);
-        P.d_oX = h->arena.up(P.oX, s);
-        P.d_oZ = h->arena.up(P.oZ, s);
-        P.d_oI = h->arena.up(P.oI, s);
       }
-      void* W = h->arena.alloc((size_t)Cmax * E);
-      int* Wi = (int*)h->arena.alloc((size_t)Imax * sizeof(int));
-      int* mrow = (int*)h->arena.alloc(nbox * sizeof(int));
-      HIPCHK(hipMemsetAsync(mrow, 0, nbox * sizeof(int), s));
-      int maxph = 0;
-      for (int c = 0; c < 9; ++c) maxph = std::max(maxph, (int)dr.ph[c].boxes.size());
-      GemmDesc<R>* desc = (GemmDesc<R>*)h->arena.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
-
-      Level<R> L = dev_level<R>(cur, h->x0, h->y0, h->s0);
-      Records<R> rec = dev_records<R>(dr);
-      const int chunks = (mmax + 63) / 64;
-      for (int c = 0; c < 9; ++c) {
-        Phase<R> ph = dev_phase<R>(dr.ph[c], W, Wi, mrow, npx, crad);
-        if (ph.nbox == 0) continue;
-        h->prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(L, ph, kp, h->d_P, chunks, s); });
-        h->prof.run(RSS_K_ID, s, [&] { launch_cpqr<R>(L, ph, rec, h->tol, cur.nmax, mmax, s); });
-        h->prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(L, ph, rec, s); });
-        h->prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(ph, rec, h->d_err, cur.nmax, s); });
-        launch_plan_y<R>(ph, rec, desc, s);
-        h->prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, cur.nmax, cur.nmax + cur.nNmax, s); });
-        h->prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(L, ph, rec, s); });
-        launch_plan_schur<R>(L, ph, rec, desc, s);
-        h->prof.run(RSS_K_SCHUR, s, [&] { launch_gemm<R>(desc, ph.nbox * 81, cur.nmax, cur.nmax, s); });
+      for (size_t i = 0; i < G.box.size(); ++i) {
+        G.oC.push_back(cx_[i]);
+        G.oX.push_back(C + xx_[i]);
+        G.oZ.push_back(C + X + zx_[i]);
       }
-      HIPCHK(hipGetLastError());
-      // read back the ranks and the surviving ids of this depth
+      G.tot = C + X + Z;
+      G.itot = I;
+      Wmax = std::max(Wmax, G.tot);
+      Imax = std::max(Imax, I);
+      maxph = std::max(maxph, (int)G.box.size());
+    }
+    void* Wd = scr.alloc((size_t)Wmax * E);
+    int* Wi = (int*)scr.alloc((size_t)Imax * sizeof(int));
+    int* mrow = (int*)scr.alloc((size_t)std::max(1, maxph) * sizeof(int));
+    GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
+    std::vector<std::vector<int>> mrows(9);
+    const int chunks = (mmax + 63) / 64;
+    for (int c = 0; c < 9; ++c) {
+      Merged& G = M[c];
+      if (G.box.empty()) continue;
+      Phase<R> ph;
+      ph.nbox = (int)G.box.size();
+      ph.box = scr.up(G.box, s);
+      ph.prob = scr.up(G.prob, s);
+      ph.oC = scr.up(G.oC, s);
+      ph.oX = scr.up(G.oX, s);
+      ph.oZ = scr.up(G.oZ, s);
+      ph.oI = scr.up(G.oI, s);
+      ph.mrow = mrow;
+      ph.W = (cx<R>*)Wd;
+      ph.Wi = Wi;
+      prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
+      prof.run(RSS_K_ID, s, [&] { launch_cpqr<R>(d_probs, ph, nmax, mmax, s); });
+      prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(d_probs, ph, s); });
+      prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(d_probs, ph, d_err, nmax, s); });
+      launch_plan_y<R>(d_probs, ph, desc, s);
+      prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, nmax, nmax + nNmax, s); });
+      prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(d_probs, ph, s); });
+      launch_plan_schur<R>(d_probs, ph, desc, s);
+      prof.run(RSS_K_SCHUR, s, [&] { launch_gemm<R>(desc, ph.nbox * 81, nmax, nmax, s); });
+      mrows[c].resize(G.box.size());
+      HIPCHK(hipMemcpyAsync(mrows[c].data(), mrow, G.box.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+      // mrow is reused by the next colour: wait for this copy before it is overwritten
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipGetLastError());
+    // read back ranks and surviving ids of every active problem
+    std::vector<std::vector<int>> curk(act.size()), ids(act.size());
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int p = act[a];
+      DepthRecords& dr = H[p]->recs.back();
+      const LevelHost& cur = W[p].cur;
+      const int nbox = cur.nb * cur.nb;
       dr.k.resize(nbox);
       dr.r.resize(nbox);
       dr.nN.resize(nbox);
-      dr.m.resize(nbox);
-      std::vector<int> curk(nbox), ids(cur.idx.size());
+      dr.m.assign(nbox, 0);
+      curk[a].resize(nbox);
+      ids[a].resize(cur.idx.size());
       HIPCHK(hipMemcpyAsync(dr.k.data(), dr.d_k, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(dr.r.data(), dr.d_r, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(dr.nN.data(), dr.d_nN, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(dr.m.data(), mrow, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(curk.data(), cur.d_cur, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      if (!ids.empty())
-        HIPCHK(hipMemcpyAsync(ids.data(), cur.d_idx, ids.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      h->prof.collect(h->stats.t_class_ms, h->stats.n_class);
-      dr.n0 = cur.n0;
-      h->arena.release(W);
-      h->arena.release(Wi);
-      h->arena.release(mrow);
-      h->arena.release(desc);
+      HIPCHK(hipMemcpyAsync(curk[a].data(), cur.d_cur, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
+      if (!ids[a].empty())
+        HIPCHK(hipMemcpyAsync(ids[a].data(), cur.d_idx, ids[a].size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    prof.collect(H[0]->stats.t_class_ms, H[0]->stats.n_class);
+    for (int c = 0; c < 9; ++c)
+      for (size_t i = 0; i < M[c].box.size(); ++i)
+        H[act[M[c].prob[i]]]->recs.back().m[M[c].box[i]] = mrows[c][i];
+    scr.clear();
 
-      // ledger (real flops, complex multiply-add = 8) and skeleton export
+    // ledger, skeleton export, parent lists and transition descriptors
+    std::vector<PairDesc> pds;
+    std::vector<ListEntry> lists;
+    std::vector<Prob<R>> cprobs;      // child levels for the transition launch
+    std::vector<int> trans;           // problems that move to a parent level
+    int tmr = 0;
+    for (size_t a = 0; a < act.size(); ++a) {
+      const int p = act[a];
+      rss_ctx* h = H[p];
+      Work& w = W[p];
+      LevelHost& cur = w.cur;
+      DepthRecords& dr = h->recs.back();
+      const int d = cur.d, nb = cur.nb, nbox = nb * nb;
+      const int npx = h->opt.n_proxy;
       std::vector<int> kk(nbox, -1);
       std::vector<int64_t> sid;
       for (int b = 0; b < nbox; ++b) {
         const int n = cur.n0[b];
         if (n == 0) continue;
-        const int k = curk[b];
+        const int k = curk[a][b];
         kk[b] = k;
-        for (int i = 0; i < k; ++i) sid.push_back(ids[cur.ioff[b] + i]);
+        for (int i = 0; i < k; ++i) sid.push_back(ids[a][cur.ioff[b] + i]);
         const double m = dr.m[b], k_ = dr.k[b], r_ = dr.r[b], nN = dr.nN[b];
-        flops_id += 4.0 * (4.0 * m * n * k_ - 2.0 * (m + n) * k_ * k_ + 4.0 * k_ * k_ * k_ / 3.0);
-        kevals += 2.0 * npx * n;
+        w.flops_id += 4.0 * (4.0 * m * n * k_ - 2.0 * (m + n) * k_ * k_ + 4.0 * k_ * k_ * k_ / 3.0);
+        w.kevals += 2.0 * npx * n;
         if (r_ > 0) {
-          flops_lu += 8.0 / 3.0 * r_ * r_ * r_;
-          flops_y += 8.0 * r_ * r_ * (k_ + nN);
-          flops_schur += 8.0 * (k_ + nN) * (k_ + nN) * r_;
-          fbytes += E * (k_ * r_ + r_ * r_ + 2.0 * (k_ + nN) * r_);
+          w.flops_lu += 8.0 / 3.0 * r_ * r_ * r_;
+          w.flops_y += 8.0 * r_ * r_ * (k_ + nN);
+          w.flops_schur += 8.0 * (k_ + nN) * (k_ + nN) * r_;
+          w.fbytes += E * (k_ * r_ + r_ * r_ + 2.0 * (k_ + nN) * r_);
           h->stats.boxes_compressed++;
         }
         if (d < 16) {
@@ -576,208 +685,285 @@ void factor_impl(rss_ctx* h, const double* points) {
       }
       h->skel_k.push_back(kk);
       h->skel_ids.push_back(sid);
-      h->recs.push_back(std::move(dr));
-
-      // parent lists: sorted union of the children's skeletons (Fig. f:merge)
-      const bool last = (d == MIN_DEPTH);
-      if (last) {
-        for (int b = 0; b < nbox; ++b)
-          for (int i = 0; i < curk[b]; ++i) root_list.push_back({b, i, ids[cur.ioff[b] + i]});
-        std::sort(root_list.begin(), root_list.end(),
-                  [](const ListEntry& a, const ListEntry& b) { return a.gid < b.gid; });
-        break;
+      if (d == MIN_DEPTH) {
+        std::vector<int> all(nbox);
+        for (int b = 0; b < nbox; ++b) all[b] = b;
+        w.root_list = sorted_union(all, curk[a], ids[a], cur.ioff);
+        continue;  // the level stays alive for the root assembly
       }
       const int pd = d - 1, pnb = 1 << pd, pbox = pnb * pnb;
       std::vector<std::vector<ListEntry>> plist(pbox);
       std::vector<int> pcount(pbox, 0);
-      for (int p = 0; p < pbox; ++p) {
-        const int px = p % pnb, py = p / pnb;
+      for (int q = 0; q < pbox; ++q) {
+        const int px = q % pnb, py = q / pnb;
+        std::vector<int> kids;
         for (int j = 0; j < 2; ++j)
-          for (int i = 0; i < 2; ++i) {
-            const int c = (2 * py + j) * nb + (2 * px + i);
-            for (int q = 0; q < curk[c]; ++q) plist[p].push_back({c, q, ids[cur.ioff[c] + q]});
-          }
-        std::sort(plist[p].begin(), plist[p].end(),
-                  [](const ListEntry& a, const ListEntry& b) { return a.gid < b.gid; });
-        pcount[p] = (int)plist[p].size();
+          for (int i = 0; i < 2; ++i) kids.push_back((2 * py + j) * nb + (2 * px + i));
+        plist[q] = sorted_union(kids, curk[a], ids[a], cur.ioff);
+        pcount[q] = (int)plist[q].size();
       }
       LevelHost par;
       par.layout(pd, pcount);
-      par.idx.resize(par.ioff.empty() ? 0 : (size_t)(par.ioff.back() + pcount.back()));
-      std::vector<ListEntry> lists;
+      par.idx.clear();
       std::vector<int64_t> loff(pbox);
-      for (int p = 0; p < pbox; ++p) {
-        loff[p] = (int64_t)lists.size();
-        for (size_t q = 0; q < plist[p].size(); ++q) {
-          par.idx[par.ioff[p] + q] = plist[p][q].gid;
-          lists.push_back(plist[p][q]);
+      for (int q = 0; q < pbox; ++q) {
+        loff[q] = (int64_t)lists.size();
+        for (auto& e : plist[q]) {
+          par.idx.push_back(e.gid);
+          lists.push_back(e);
         }
       }
-      std::vector<PairDesc> pds;
-      for (int p = 0; p < pbox; ++p)
+      alloc_level(h, par, E, s);
+      const int pi = (int)cprobs.size();
+      Prob<R> cp{};
+      cp.L = dev_level<R>(cur, h->x0, h->y0, h->s0);
+      cp.kp = h->kp;
+      cp.P = h->d_P;
+      cprobs.push_back(cp);
+      for (int q = 0; q < pbox; ++q)
         for (int sl = 0; sl < 25; ++sl) {
-          const int64_t off = par.boff[(size_t)p * 25 + sl];
+          const int64_t off = par.boff[(size_t)q * 25 + sl];
           if (off < 0) continue;
-          const int p2 = (p / pnb + sl / 5 - 2) * pnb + (p % pnb + sl % 5 - 2);
-          if (pcount[p] == 0 || pcount[p2] == 0) continue;
-          PairDesc q;
-          q.off = off;
-          q.ld = pcount[p];
-          q.nr = pcount[p];
-          q.nc = pcount[p2];
-          q.roff = loff[p];
-          q.coff = loff[p2];
-          pds.push_back(q);
-          // fresh evaluations: child pairs further than distance 2
-          const int px = p % pnb, py = p / pnb, qx = p2 % pnb, qy = p2 / pnb;
-          for (int a = 0; a < 4; ++a)
-            for (int bq = 0; bq < 4; ++bq) {
-              const int ca = (2 * py + a / 2) * nb + 2 * px + a % 2;
-              const int cb = (2 * qy + bq / 2) * nb + 2 * qx + bq % 2;
-              if (chebyshev(nb, ca, cb) > 2) kevals += (double)curk[ca] * curk[cb];
+          const int q2 = (q / pnb + sl / 5 - 2) * pnb + (q % pnb + sl % 5 - 2);
+          if (pcount[q] == 0 || pcount[q2] == 0) continue;
+          PairDesc pd_;
+          pd_.dst = (char*)par.d_A + off * E;
+          pd_.ld = pcount[q];
+          pd_.nr = pcount[q];
+          pd_.nc = pcount[q2];
+          pd_.prob = pi;
+          pd_.have_child = 1;
+          pd_.roff = loff[q];
+          pd_.coff = loff[q2];
+          pds.push_back(pd_);
+          const int qx = q % pnb, qy = q / pnb, rx = q2 % pnb, ry = q2 / pnb;
+          for (int u = 0; u < 4; ++u)
+            for (int v = 0; v < 4; ++v) {
+              const int ca = (2 * qy + u / 2) * nb + 2 * qx + u % 2;
+              const int cb = (2 * ry + v / 2) * nb + 2 * rx + v % 2;
+              if (chebyshev(nb, ca, cb) > 2) w.kevals += (double)curk[a][ca] * curk[a][cb];
             }
         }
-      alloc_level(h, par, E);
-      Level<R> child = dev_level<R>(cur, h->x0, h->y0, h->s0);
-      PairDesc* d_pds = h->arena.up(pds, s);
-      ListEntry* d_lists = h->arena.up(lists, s);
-      h->prof.run(RSS_K_ASSEMBLE, s, [&] {
-        launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, par.nmax, par.nmax, &child,
-                                 (cx<R>*)par.d_A, kp, h->d_P, s);
+      tmr = std::max(tmr, par.nmax);
+      trans.push_back(p);
+      // the parent becomes the current level; the child is freed after the launch
+      std::swap(w.cur, par);
+      h->tmp_levels.push_back(std::move(par));
+    }
+    if (!pds.empty()) {
+      PairDesc* d_pds = scr.up(pds, s);
+      ListEntry* d_lists = scr.up(lists, s);
+      Prob<R>* d_cp = scr.up(cprobs, s);
+      prof.run(RSS_K_ASSEMBLE, s, [&] {
+        launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, tmr, tmr, d_cp, s);
       });
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
-      h->arena.release(d_pds);
-      h->arena.release(d_lists);
-      free_level(h, cur);
-      cur = std::move(par);
+      scr.clear();
     }
-  } else {
-    for (int64_t i = 0; i < N; ++i) root_list.push_back({0, 0, (int)i});
+    for (int p : trans) {
+      for (auto& L : H[p]->tmp_levels) free_level(H[p], L);
+      H[p]->tmp_levels.clear();
+    }
   }
 
-  // root: everything that remains, dense (the top of Alg. a:fact)
-  const int nr = (int)root_list.size();
-  h->n_root = nr;
-  h->stats.n_root = nr;
-  if (nr > 0) {
-    std::vector<int> rid(nr);
-    for (int i = 0; i < nr; ++i) rid[i] = root_list[i].gid;
-    h->d_root_ids = h->arena.up(rid, s);
-    const size_t bytes = (size_t)nr * nr * E;
-    void* A = h->arena.alloc(bytes);
-    void* tmp = h->arena.alloc(bytes);
-    PairDesc q;
-    q.off = 0;
-    q.ld = nr;
-    q.nr = nr;
-    q.nc = nr;
-    q.roff = 0;
-    q.coff = 0;
-    std::vector<PairDesc> pds{q};
-    PairDesc* d_pds = h->arena.up(pds, s);
-    ListEntry* d_list = h->arena.up(root_list, s);
-    Level<R> child{};
-    const bool have = D >= MIN_DEPTH;
-    if (have) child = dev_level<R>(cur, h->x0, h->y0, h->s0);
-    h->prof.run(RSS_K_ASSEMBLE, s, [&] {
-      launch_assemble_pairs<R>(d_pds, 1, d_list, nr, nr, have ? &child : nullptr, (cx<R>*)A, kp,
-                               h->d_P, s);
-    });
-    unsigned long long* keys = (unsigned long long*)h->arena.alloc((size_t)nr * 8);
-    int* perm = (int*)h->arena.alloc((size_t)nr * 2 * sizeof(int));
-    int where = 0;
-    h->prof.run(RSS_K_ROOT, s, [&] {
-      where = launch_root_inverse<R>((cx<R>*)A, (cx<R>*)tmp, nr, keys, perm, h->d_err, s);
-    });
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    h->arena.release(d_pds);
-    h->arena.release(d_list);
-    h->arena.release(keys);
-    h->arena.release(perm);
-    if (where == 0) {
-      h->d_root_inv = A;
-      h->arena.release(tmp);
-    } else {
-      h->d_root_inv = tmp;
-      h->arena.release(A);
+  // roots: every remaining index, dense (the top of Alg. a:fact); one batch
+  {
+    std::vector<PairDesc> pds;
+    std::vector<ListEntry> lists;
+    std::vector<Prob<R>> cprobs;
+    std::vector<RootDesc<R>> rds;
+    int nrmax = 0;
+    for (int p = 0; p < np; ++p) {
+      rss_ctx* h = H[p];
+      Work& w = W[p];
+      const int nr = (int)w.root_list.size();
+      h->n_root = nr;
+      h->stats.n_root = nr;
+      if (nr == 0) continue;
+      std::vector<int> rid(nr);
+      for (int i = 0; i < nr; ++i) rid[i] = w.root_list[i].gid;
+      h->d_root_ids = h->arena.up(rid, s);
+      const size_t bytes = (size_t)nr * nr * E;
+      RootDesc<R> rd;
+      rd.A = (cx<R>*)h->arena.alloc(bytes);
+      rd.tmp = (cx<R>*)h->arena.alloc(bytes);
+      rd.keys = (unsigned long long*)scr.alloc((size_t)nr * 8);
+      HIPCHK(hipMemsetAsync(rd.keys, 0, (size_t)nr * 8, s));
+      rd.perm = (int*)scr.alloc((size_t)nr * 2 * sizeof(int));
+      rd.n = nr;
+      rds.push_back(rd);
+      // the inverse ends in A for odd n, in tmp for even n
+      h->d_root_inv = (nr & 1) ? (void*)rd.A : (void*)rd.tmp;
+      h->root_spare = (nr & 1) ? (void*)rd.tmp : (void*)rd.A;
+      Prob<R> cp{};
+      const bool have = h->D >= MIN_DEPTH;
+      if (have) cp.L = dev_level<R>(w.cur, h->x0, h->y0, h->s0);
+      cp.kp = h->kp;
+      cp.P = h->d_P;
+      const int pi = (int)cprobs.size();
+      cprobs.push_back(cp);
+      PairDesc q;
+      q.dst = rd.A;
+      q.ld = nr;
+      q.nr = nr;
+      q.nc = nr;
+      q.prob = pi;
+      q.have_child = have ? 1 : 0;
+      q.roff = (int64_t)lists.size();
+      q.coff = q.roff;
+      for (auto& e : w.root_list) lists.push_back(e);
+      pds.push_back(q);
+      nrmax = std::max(nrmax, nr);
+      w.flops_lu += 8.0 * (double)nr * nr * nr;
+      w.fbytes += (double)nr * nr * E;
+      if (!have) w.kevals += (double)nr * nr;
     }
-    flops_lu += 8.0 * (double)nr * nr * nr;
-    fbytes += (double)nr * nr * E;
-    if (!have) kevals += (double)nr * nr;
+    if (!pds.empty()) {
+      PairDesc* d_pds = scr.up(pds, s);
+      ListEntry* d_lists = scr.up(lists, s);
+      Prob<R>* d_cp = scr.up(cprobs, s);
+      RootDesc<R>* d_rd = scr.up(rds, s);
+      prof.run(RSS_K_ASSEMBLE, s, [&] {
+        launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, nrmax, nrmax, d_cp, s);
+      });
+      prof.run(RSS_K_ROOT, s, [&] { launch_root_inverse<R>(d_rd, (int)rds.size(), nrmax, d_err, s); });
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    scr.clear();
+    for (int p = 0; p < np; ++p) {
+      rss_ctx* h = H[p];
+      if (h->root_spare) {
+        h->arena.release(h->root_spare);
+        h->root_spare = nullptr;
+      }
+      if (W[p].active) free_level(h, W[p].cur);
+    }
   }
-  if (D >= MIN_DEPTH) free_level(h, cur);
   HIPCHK(hipEventRecord(ev1, s));
   HIPCHK(hipEventSynchronize(ev1));
-  h->prof.collect(h->stats.t_class_ms, h->stats.n_class);
+  prof.collect(H[0]->stats.t_class_ms, H[0]->stats.n_class);
   float ms = 0;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   int err = 0;
-  HIPCHK(hipMemcpy(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&err, d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
-  h->stats.t_factor_ms = ms;
-  h->stats.flops_id = flops_id;
-  h->stats.flops_lu = flops_lu;
-  h->stats.flops_y = flops_y;
-  h->stats.flops_schur = flops_schur;
-  h->stats.factor_bytes = fbytes;
-  h->stats.kernel_evals = kevals;
-  h->d_gemm_desc = h->arena.alloc(sizeof(GemmDesc<R>));
+  for (int p = 0; p < np; ++p) {
+    rss_ctx* h = H[p];
+    Work& w = W[p];
+    h->stats.t_factor_ms = ms;
+    h->stats.flops_id = w.flops_id;
+    h->stats.flops_lu = w.flops_lu;
+    h->stats.flops_y = w.flops_y;
+    h->stats.flops_schur = w.flops_schur;
+    h->stats.factor_bytes = w.fbytes;
+    h->stats.kernel_evals = w.kevals;
+    h->stats.device_bytes = h->arena.bytes;
+  }
 }
 
-// z <- F^{-1} z for z (N x nrhs, complex<R>, ld N) on the handle's stream
+// z_p <- F_p^{-1} z_p for every handle of a batch (complex<R>, N_p x nrhs_p,
+// ld N_p), on stream s: one launch per (height, colour) and direction.
+template <class R>
+void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
+                 const std::vector<int>& nrhs, hipStream_t s) {
+  const int np = (int)H.size();
+  int tmax = -1, nrhs_max = 0;
+  for (int p = 0; p < np; ++p) {
+    tmax = std::max(tmax, (int)H[p]->recs.size() - 1);
+    nrhs_max = std::max(nrhs_max, nrhs[p]);
+  }
+  Scratch scr;
+  // per height: SolveProb array over the problems that have that height, and merged phases
+  struct HPhase {
+    SolveProb<R>* d_sp = nullptr;
+    Phase<R> ph[9];
+    int kmax = 0, rmax = 0;
+  };
+  std::vector<HPhase> HP(tmax + 1);
+  for (int t = 0; t <= tmax; ++t) {
+    std::vector<SolveProb<R>> sp;
+    std::vector<int> idxmap(np, -1);
+    for (int p = 0; p < np; ++p)
+      if (t < (int)H[p]->recs.size()) {
+        idxmap[p] = (int)sp.size();
+        SolveProb<R> q;
+        q.rec = dev_records<R>(H[p]->recs[t]);
+        q.z = Z[p];
+        q.ldz = H[p]->N;
+        q.nrhs = nrhs[p];
+        sp.push_back(q);
+        HP[t].kmax = std::max(HP[t].kmax, H[p]->recs[t].kmax);
+        HP[t].rmax = std::max(HP[t].rmax, H[p]->recs[t].rmax);
+      }
+    HP[t].d_sp = scr.up(sp, s);
+    for (int c = 0; c < 9; ++c) {
+      Phase<R>& ph = HP[t].ph[c];
+      ph = Phase<R>{};
+      if (sp.size() == 1) {
+        for (int p = 0; p < np; ++p)
+          if (idxmap[p] == 0) {
+            const PhaseHost& P = H[p]->recs[t].ph[c];
+            ph.nbox = (int)P.boxes.size();
+            ph.box = P.d_box;
+            ph.prob = P.d_prob;
+          }
+      } else {
+        std::vector<int> box, prob;
+        for (int p = 0; p < np; ++p)
+          if (idxmap[p] >= 0)
+            for (int b : H[p]->recs[t].ph[c].boxes) {
+              box.push_back(b);
+              prob.push_back(idxmap[p]);
+            }
+        ph.nbox = (int)box.size();
+        if (ph.nbox) {
+          ph.box = scr.up(box, s);
+          ph.prob = scr.up(prob, s);
+        }
+      }
+    }
+  }
+  for (int t = 0; t <= tmax; ++t)
+    for (int c = 0; c < 9; ++c)
+      launch_solve_fwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, s);
+  // roots
+  {
+    std::vector<RootApply<R>> ra;
+    int nmax = 0;
+    for (int p = 0; p < np; ++p) {
+      const int nr = H[p]->n_root;
+      if (nr == 0) continue;
+      RootApply<R> q;
+      q.Ainv = (const cx<R>*)H[p]->d_root_inv;
+      q.ids = H[p]->d_root_ids;
+      q.n = nr;
+      q.z = Z[p];
+      q.ldz = H[p]->N;
+      q.nrhs = nrhs[p];
+      q.ws = (cx<R>*)scr.alloc((size_t)nr * nrhs[p] * 2 * sizeof(cx<R>));
+      ra.push_back(q);
+      nmax = std::max(nmax, nr);
+    }
+    if (!ra.empty()) {
+      RootApply<R>* d_ra = scr.up(ra, s);
+      GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc(ra.size() * sizeof(GemmDesc<R>));
+      launch_root_apply<R>(d_ra, (int)ra.size(), nmax, nrhs_max, desc, s);
+    }
+  }
+  for (int t = tmax; t >= 0; --t)
+    for (int c = 8; c >= 0; --c)
+      launch_solve_bwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));  // scratch descriptors are freed on return
+}
+
 template <class R>
 void apply_impl(rss_ctx* h, cx<R>* z, int nrhs) {
-  hipStream_t s = h->stream;
-  const int64_t ldz = h->N;
-  const int npx = h->opt.n_proxy;
-  const double crad = h->opt.proxy_radius;
-  for (auto& dr : h->recs) {
-    Records<R> rec = dev_records<R>(dr);
-    for (int c = 0; c < 9; ++c) {
-      Phase<R> ph = dev_phase<R>(dr.ph[c], nullptr, nullptr, nullptr, npx, crad);
-      launch_solve_fwd<R>(ph, rec, z, ldz, nrhs, dr.kmax, dr.rmax, s);
-    }
-  }
-  const int nr = h->n_root;
-  if (nr > 0) {
-    const size_t need = (size_t)nr * nrhs * sizeof(cx<R>) * 2;
-    if (need > h->ws_root_bytes) {
-      h->arena.release(h->ws_root);
-      h->ws_root = h->arena.alloc(need);
-      h->ws_root_bytes = need;
-    }
-    cx<R>* a = (cx<R>*)h->ws_root;
-    cx<R>* b = a + (size_t)nr * nrhs;
-    launch_gather_rows<R>(z, ldz, h->d_root_ids, nr, nrhs, a, s);
-    GemmDesc<R> d;
-    d.C = b;
-    d.A = (const cx<R>*)h->d_root_inv;
-    d.B = a;
-    d.ldc = nr;
-    d.lda = nr;
-    d.ldb = nr;
-    d.M = nr;
-    d.N = nrhs;
-    d.K = nr;
-    d.beta = 0;
-    d.sign = 1;
-    HIPCHK(hipMemcpyAsync(h->d_gemm_desc, &d, sizeof(d), hipMemcpyHostToDevice, s));
-    launch_gemm<R>((GemmDesc<R>*)h->d_gemm_desc, 1, nr, nrhs, s);
-    launch_scatter_rows<R>(b, h->d_root_ids, nr, nrhs, z, ldz, s);
-    HIPCHK(hipStreamSynchronize(s));  // the descriptor lives on this stack frame
-  }
-  for (auto it = h->recs.rbegin(); it != h->recs.rend(); ++it) {
-    Records<R> rec = dev_records<R>(*it);
-    for (int c = 8; c >= 0; --c) {
-      Phase<R> ph = dev_phase<R>(it->ph[c], nullptr, nullptr, nullptr, npx, crad);
-      launch_solve_bwd<R>(ph, rec, z, ldz, nrhs, it->kmax, it->rmax, it->snmax, s);
-    }
-  }
-  HIPCHK(hipGetLastError());
+  apply_batch<R>(std::vector<rss_ctx*>{h}, std::vector<cx<R>*>{z}, std::vector<int>{nrhs}, h->stream);
 }
 
 int run(const std::function<void()>& f) {
@@ -796,6 +982,97 @@ int run(const std::function<void()>& f) {
   }
 }
 
+
+// validate the arguments and create a handle (no device work beyond the points)
+rss_ctx* make_ctx(const double* points, int64_t n, const rss_kernel* k, double tol, int leaf,
+                  const rss_options* opt, const rss_ctx* shared) {
+  validate(points, n, k, tol, leaf);
+  std::unique_ptr<rss_ctx> h(new rss_ctx());
+  h->N = n;
+  h->kern = *k;
+  h->kp = to_kp(*k);
+  h->tol = tol;
+  h->leaf = leaf;
+  if (opt) h->opt = *opt;
+  if (h->opt.n_proxy < 0) fail(RSS_EINVAL, "n_proxy must be >= 0");
+  if (h->opt.n_proxy == 0) h->opt.n_proxy = (k->kind == RSS_HELMHOLTZ2D) ? 128 : 64;
+  if (!(h->opt.proxy_radius >= 0) || !std::isfinite(h->opt.proxy_radius))
+    fail(RSS_EINVAL, "bad proxy_radius");
+  if (h->opt.proxy_radius == 0) h->opt.proxy_radius = 1.25;
+  if (h->opt.refine_tol == 0) h->opt.refine_tol = 1e-10;
+  if (h->opt.precision != RSS_FP64 && h->opt.precision != RSS_FP32_REFINE)
+    fail(RSS_EINVAL, "unknown precision");
+  // refinement steps after the first solve (-1: no refinement, plain apply)
+  if (h->opt.precision == RSS_FP32_REFINE)
+    h->refine_steps = h->opt.max_refine == 0 ? 10 : (h->opt.max_refine < 0 ? -1 : h->opt.max_refine);
+  else
+    h->refine_steps = h->opt.max_refine > 0 ? h->opt.max_refine : -1;
+  h->precision = h->opt.precision;
+  h->prof.on = h->opt.profile != 0;
+  h->stats.precision = h->precision;
+  h->stats.n = n;
+  h->stats.last_relres = -1.0;
+  if (h->opt.stream) {
+    h->stream = (hipStream_t)h->opt.stream;
+  } else if (shared) {
+    h->stream = shared->stream;
+    h->stream_owner = shared->stream_owner;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    hipStream_t st = h->stream;
+    h->stream_owner = std::shared_ptr<void>((void*)st, [](void* q) {
+      (void)hipStreamSynchronize((hipStream_t)q);
+      (void)hipStreamDestroy((hipStream_t)q);
+    });
+  }
+  if (h->opt.root[2] > 0) {
+    h->x0 = h->opt.root[0];
+    h->y0 = h->opt.root[1];
+    h->s0 = h->opt.root[2];
+  } else {
+    double lox = points[0], hix = points[0], loy = points[1], hiy = points[1];
+    for (int64_t i = 0; i < n; ++i) {
+      lox = std::min(lox, points[2 * i]);
+      hix = std::max(hix, points[2 * i]);
+      loy = std::min(loy, points[2 * i + 1]);
+      hiy = std::max(hiy, points[2 * i + 1]);
+    }
+    if (lox >= 0 && loy >= 0 && hix <= 1 && hiy <= 1) {
+      h->x0 = 0;
+      h->y0 = 0;
+      h->s0 = 1;
+    } else {
+      double side = std::max(hix - lox, hiy - loy) * (1.0 + 1e-12);
+      if (side == 0) side = 1.0;
+      h->x0 = lox;
+      h->y0 = loy;
+      h->s0 = side;
+    }
+  }
+  h->h_points.assign(points, points + 2 * n);
+  h->d_P = (double*)h->arena.alloc((size_t)n * 2 * sizeof(double));
+  HIPCHK(hipMemcpyAsync(h->d_P, points, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice,
+                        h->stream));
+  h->d_err = (int*)h->arena.alloc(sizeof(int));
+  HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->stream));
+  return h.release();
+}
+
+void destroy_ctx(rss_ctx* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  delete h;  // the arena frees device memory; the stream goes with its last handle
+}
+
+void factor_handles(std::vector<rss_ctx*>& H) {
+  hipStream_t s = H[0]->stream;
+  for (size_t p = 1; p < H.size(); ++p)
+    if (H[p]->stream != s) HIPCHK(hipStreamSynchronize(H[p]->stream));  // points uploaded
+  if (H[0]->precision == RSS_FP64) factor_batch<double>(H, s);
+  else factor_batch<float>(H, s);
+  for (auto* h : H) h->stats.device_bytes = h->arena.bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -806,84 +1083,69 @@ int rss_factor_ex(const double* points, int64_t n, const rss_kernel* k, double t
   rss_ctx* h = nullptr;
   const int rc = run([&] {
     if (!out) fail(RSS_EINVAL, "null output handle pointer");
-    validate(points, n, k, tol, leaf);
-    h = new rss_ctx();
-    h->N = n;
-    h->kern = *k;
-    h->kp = to_kp(*k);
-    h->tol = tol;
-    h->leaf = leaf;
-    if (opt) h->opt = *opt;
-    if (h->opt.n_proxy < 0) fail(RSS_EINVAL, "n_proxy must be >= 0");
-    if (h->opt.n_proxy == 0) h->opt.n_proxy = (k->kind == RSS_HELMHOLTZ2D) ? 128 : 64;
-    if (!(h->opt.proxy_radius >= 0) || !std::isfinite(h->opt.proxy_radius))
-      fail(RSS_EINVAL, "bad proxy_radius");
-    if (h->opt.proxy_radius == 0) h->opt.proxy_radius = 1.25;
-    if (h->opt.refine_tol == 0) h->opt.refine_tol = 1e-10;
-    // refinement steps after the first solve (-1: no refinement, plain apply)
-    if (h->opt.precision == RSS_FP32_REFINE)
-      h->refine_steps = h->opt.max_refine == 0 ? 10 : (h->opt.max_refine < 0 ? -1 : h->opt.max_refine);
-    else
-      h->refine_steps = h->opt.max_refine > 0 ? h->opt.max_refine : -1;
-    if (h->opt.precision != RSS_FP64 && h->opt.precision != RSS_FP32_REFINE)
-      fail(RSS_EINVAL, "unknown precision");
-    h->precision = h->opt.precision;
-    h->prof.on = h->opt.profile != 0;
-    h->stats.precision = h->precision;
-    h->stats.n = n;
-    h->stats.last_relres = -1.0;
-    if (h->opt.stream) {
-      h->stream = (hipStream_t)h->opt.stream;
-    } else {
-      HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-      h->own_stream = true;
-    }
-    // root square
-    if (h->opt.root[2] > 0) {
-      h->x0 = h->opt.root[0];
-      h->y0 = h->opt.root[1];
-      h->s0 = h->opt.root[2];
-    } else {
-      double lox = points[0], hix = points[0], loy = points[1], hiy = points[1];
-      for (int64_t i = 0; i < n; ++i) {
-        lox = std::min(lox, points[2 * i]);
-        hix = std::max(hix, points[2 * i]);
-        loy = std::min(loy, points[2 * i + 1]);
-        hiy = std::max(hiy, points[2 * i + 1]);
-      }
-      if (lox >= 0 && loy >= 0 && hix <= 1 && hiy <= 1) {
-        h->x0 = 0;
-        h->y0 = 0;
-        h->s0 = 1;
-      } else {
-        double side = std::max(hix - lox, hiy - loy) * (1.0 + 1e-12);
-        if (side == 0) side = 1.0;
-        h->x0 = lox;
-        h->y0 = loy;
-        h->s0 = side;
-      }
-    }
-    h->d_P = (double*)h->arena.alloc((size_t)n * 2 * sizeof(double));
-    HIPCHK(hipMemcpyAsync(h->d_P, points, (size_t)n * 2 * sizeof(double), hipMemcpyHostToDevice,
-                          h->stream));
-    h->d_err = (int*)h->arena.alloc(sizeof(int));
-    HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->stream));
-    if (h->precision == RSS_FP64) factor_impl<double>(h, points);
-    else factor_impl<float>(h, points);
-    h->stats.device_bytes = h->arena.bytes;
+    h = make_ctx(points, n, k, tol, leaf, opt, nullptr);
+    std::vector<rss_ctx*> H{h};
+    factor_handles(H);
   });
   if (rc != RSS_OK) {
-    if (h) {
-      if (h->own_stream && h->stream) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipStreamDestroy(h->stream);
-      }
-      delete h;
-    }
+    destroy_ctx(h);
     return rc;
   }
   *out = h;
   return RSS_OK;
+}
+
+int rss_factor_batch(int nprob, const double* const* points, const int64_t* n,
+                     const rss_kernel* kernels, double tol, int leaf, const rss_options* opt,
+                     rss_handle* out) {
+  std::vector<rss_ctx*> H;
+  const int rc = run([&] {
+    if (nprob < 1 || !points || !n || !kernels || !out) fail(RSS_EINVAL, "bad batch arguments");
+    for (int p = 0; p < nprob; ++p) out[p] = nullptr;
+    for (int p = 0; p < nprob; ++p)
+      H.push_back(make_ctx(points[p], n[p], &kernels[p], tol, leaf, opt, p ? H[0] : nullptr));
+    factor_handles(H);
+  });
+  if (rc != RSS_OK) {
+    for (auto* h : H) destroy_ctx(h);
+    return rc;
+  }
+  for (int p = 0; p < nprob; ++p) out[p] = H[p];
+  return RSS_OK;
+}
+
+int rss_apply_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
+  return run([&] {
+    if (nh < 1 || !hs || !B || !nrhs) fail(RSS_EINVAL, "bad batch arguments");
+    std::vector<rss_ctx*> H(hs, hs + nh);
+    for (int p = 0; p < nh; ++p) {
+      if (!H[p] || !B[p] || nrhs[p] < 1) fail(RSS_EINVAL, "bad batch entry");
+      if (H[p]->precision != H[0]->precision) fail(RSS_EINVAL, "mixed precisions in a batch");
+    }
+    hipStream_t s = H[0]->stream;
+    for (int p = 1; p < nh; ++p)
+      if (H[p]->stream != s) HIPCHK(hipStreamSynchronize(H[p]->stream));
+    std::vector<int> nr(nrhs, nrhs + nh);
+    if (H[0]->precision == RSS_FP64) {
+      std::vector<cx<double>*> Z;
+      for (int p = 0; p < nh; ++p) Z.push_back((cx<double>*)B[p]);
+      apply_batch<double>(H, Z, nr, s);
+    } else {
+      Scratch scr;
+      std::vector<cx<float>*> Z;
+      for (int p = 0; p < nh; ++p) {
+        const size_t tot = (size_t)H[p]->N * nr[p];
+        cx<float>* z = (cx<float>*)scr.alloc(tot * sizeof(cx<float>));
+        launch_cast_c64((const cx<double>*)B[p], H[p]->N, nr[p], z, s);
+        HIPCHK(hipMemsetAsync(B[p], 0, tot * sizeof(cx<double>), s));
+        Z.push_back(z);
+      }
+      apply_batch<float>(H, Z, nr, s);
+      for (int p = 0; p < nh; ++p)
+        launch_axpy_from_c64(Z[p], H[p]->N, nr[p], nullptr, (cx<double>*)B[p], s);
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  });
 }
 
 int rss_factor(const double* points, int64_t n, const rss_kernel* k, double tol, int leaf,
@@ -1001,14 +1263,7 @@ int rss_solve(rss_handle h, void* B, int nrhs) {
   return rc != RSS_OK ? rc : code;
 }
 
-void rss_free(rss_handle h) {
-  if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
-  const bool own = h->own_stream;
-  hipStream_t s = h->stream;
-  delete h;
-  if (own && s) (void)hipStreamDestroy(s);
-}
+void rss_free(rss_handle h) { destroy_ctx(h); }
 
 int rss_info(rss_handle h, rss_stats* s) {
   if (!h || !s) {

@@ -51,11 +51,34 @@ struct Records {
   int* G;
 };
 
-// One colour phase: the boxes eliminated concurrently, and per-slot workspace.
+// One problem at one depth of a (possibly batched) factorization.
+template <class R>
+struct Prob {
+  Level<R> L;
+  Records<R> rec;
+  KParams kp;
+  const double* P;  // device points (n x 2)
+  double tol;
+  int n_proxy;
+  double proxy_radius;
+};
+
+// One problem in a (possibly batched) solve sweep at one depth.
+template <class R>
+struct SolveProb {
+  Records<R> rec;
+  cx<R>* z;      // right-hand sides, column-major
+  int64_t ldz;   // = number of points
+  int nrhs;
+};
+
+// One colour phase: the boxes (of one or several problems) eliminated
+// concurrently, and per-slot workspace.
 template <class R>
 struct Phase {
   int nbox;
   const int* box;
+  const int* prob;     // problem index of each slot
   const int64_t* oC;   // compression matrix C (m x n, ld m) in W
   const int64_t* oX;   // X_RR (r x r) in W
   const int64_t* oZ;   // [X_RS X_RN] (r x (k+nN), ld r) in W
@@ -63,8 +86,6 @@ struct Phase {
   int* mrow;           // rows of C per slot
   cx<R>* W;
   int* Wi;
-  int n_proxy;
-  double proxy_radius;
 };
 
 template <class R>
@@ -81,10 +102,22 @@ struct GemmDesc {
 // Assembly of a dense block from the blocks of the depth below (Sec. 2.5,
 // Fig. f:merge): rows/cols are lists of (child box, local position, global id).
 struct PairDesc {
-  int64_t off;  // destination offset
+  void* dst;    // destination block (complex<R>, column-major, leading dimension ld)
   int ld;
   int nr, nc;
+  int prob;     // problem index (child level, kernel, points)
+  int have_child;
   int64_t roff, coff;  // into the entry list
+};
+
+// dense root of one problem: in-place Gauss-Jordan over A / tmp
+template <class R>
+struct RootDesc {
+  cx<R>* A;
+  cx<R>* tmp;
+  unsigned long long* keys;
+  int* perm;     // 2 n ints
+  int n;
 };
 struct ListEntry {
   int box, local, gid;
@@ -97,46 +130,49 @@ enum { ERRF_SINGULAR = 1 };
 // launchers (rss_kernels.hip); all enqueue on `s`
 // ---------------------------------------------------------------------------
 template <class R>
-void launch_leaf_assemble(const Level<R>& L, const KParams& kp, const double* P, hipStream_t s);
+void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStream_t s);
 template <class R>
-void launch_build_C(const Level<R>& L, const Phase<R>& ph, const KParams& kp, const double* P,
-                    int chunks, hipStream_t s);
+void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStream_t s);
 template <class R>
-void launch_cpqr(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, double tol,
-                 int nmax, int mmax, hipStream_t s);
+void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s);
 template <class R>
-void launch_sparsify(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s);
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
 template <class R>
-void launch_inverse(const Phase<R>& ph, const Records<R>& rec, int* errflag, int nmax,
+void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s);
 template <class R>
-void launch_plan_y(const Phase<R>& ph, const Records<R>& rec, GemmDesc<R>* desc, hipStream_t s);
+void launch_plan_y(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s);
 template <class R>
-void launch_compact(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s);
+void launch_compact(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
 template <class R>
-void launch_plan_schur(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec,
-                       GemmDesc<R>* desc, hipStream_t s);
+void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s);
 template <class R>
 void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipStream_t s);
 template <class R>
 void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
-                           int max_c, const Level<R>* child, cx<R>* dst, const KParams& kp,
-                           const double* P, hipStream_t s);
+                           int max_c, const Prob<R>* child, hipStream_t s);
 template <class R>
-int launch_root_inverse(cx<R>* A, cx<R>* tmp, int n, unsigned long long* keys, int* perm,
-                        int* errflag, hipStream_t s);
+void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errflag, hipStream_t s);
 template <class R>
-void launch_solve_fwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
-                      int kmax, int rmax, hipStream_t s);
+void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
+                      hipStream_t s);
 template <class R>
-void launch_solve_bwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
-                      int kmax, int rmax, int snmax, hipStream_t s);
+void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
+                      hipStream_t s);
+// batched root apply: z[ids] <- Ainv z[ids] per problem (ws: 2 n nrhs entries per problem)
 template <class R>
-void launch_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs, cx<R>* out,
-                        hipStream_t s);
+struct RootApply {
+  const cx<R>* Ainv;
+  const int* ids;
+  int n;
+  cx<R>* z;
+  int64_t ldz;
+  int nrhs;
+  cx<R>* ws;
+};
 template <class R>
-void launch_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z, int64_t ldz,
-                         hipStream_t s);
+void launch_root_apply(const RootApply<R>* ra, int nprob, int max_n, int max_nrhs, GemmDesc<R>* desc,
+                       hipStream_t s);
 
 void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64_t ni,
                          const int* J, int64_t nj, cx<double>* out, hipStream_t s);

@@ -41,8 +41,12 @@ __device__ __forceinline__ cx<R>* block_ptr(const Level<R>& L, int b, int b2) {
 // leaf stencil: A[b, b2] = a(I_b, I_b2) for every pair at distance <= 2
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_leaf_assemble(Level<R> L, KParams kp, const double* P) {
+__global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs) {
+  const Level<R> L = probs[blockIdx.y].L;
+  const KParams kp = probs[blockIdx.y].kp;
+  const double* P = probs[blockIdx.y].P;
   const int b = blockIdx.x / 25, s = blockIdx.x % 25;
+  if (b >= L.nb * L.nb) return;
   const int64_t off = L.boff[(int64_t)b * 25 + s];
   if (off < 0) return;
   const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
@@ -58,9 +62,9 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(Level<R> L, KParams kp, c
 }
 
 template <class R>
-void launch_leaf_assemble(const Level<R>& L, const KParams& kp, const double* P, hipStream_t s) {
-  const int nbox = L.nb * L.nb;
-  hipLaunchKernelGGL(k_leaf_assemble<R>, dim3(nbox * 25), dim3(256), 0, s, L, kp, P);
+void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStream_t s) {
+  if (nprob == 0) return;
+  hipLaunchKernelGGL(k_leaf_assemble<R>, dim3(max_boxes * 25, nprob), dim3(256), 0, s, probs);
 }
 
 // ---------------------------------------------------------------------------
@@ -69,10 +73,13 @@ void launch_leaf_assemble(const Level<R>& L, const KParams& kp, const double* P,
 // M boxes in ascending id order, rows of each in its active order.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_build_C(Level<R> L, Phase<R> ph, KParams kp,
-                                                 const double* P) {
+__global__ __launch_bounds__(256) void k_build_C(const Prob<R>* probs, Phase<R> ph) {
   __shared__ int mbox[16], moff[17];
   const int slot = blockIdx.x, b = ph.box[slot];
+  const Prob<R>& pr = probs[ph.prob[slot]];
+  const Level<R> L = pr.L;
+  const KParams kp = pr.kp;
+  const double* P = pr.P;
   const int n = L.cur[b];
   if (threadIdx.x == 0) {
     int c = 0, o = 0;
@@ -91,16 +98,16 @@ __global__ __launch_bounds__(256) void k_build_C(Level<R> L, Phase<R> ph, KParam
   }
   __syncthreads();
   const int sumM = moff[16];
-  const int npx = ph.n_proxy;
+  const int npx = pr.n_proxy;
   const int m = 2 * sumM + 2 * npx;
-  if (blockIdx.y == 0 && threadIdx.x == 0) ph.mrow[b] = m;
+  if (blockIdx.y == 0 && threadIdx.x == 0) ph.mrow[slot] = m;
   const int r0 = blockIdx.y * 64;
   if (r0 >= m || n == 0) return;
   cx<R>* C = ph.W + ph.oC[slot];
   const int* I = L.idx + L.ioff[b];
   const int bx = b % L.nb, by = b / L.nb;
   const double cxx = L.x0 + (bx + 0.5) * L.side, cyy = L.y0 + (by + 0.5) * L.side;
-  const double rad = ph.proxy_radius * L.side;
+  const double rad = pr.proxy_radius * L.side;
   const int n0b = L.n0[b];
   for (int e = threadIdx.x; e < 64 * n; e += blockDim.x) {
     const int row = r0 + (e & 63), j = e >> 6;
@@ -141,10 +148,9 @@ __global__ __launch_bounds__(256) void k_build_C(Level<R> L, Phase<R> ph, KParam
 }
 
 template <class R>
-void launch_build_C(const Level<R>& L, const Phase<R>& ph, const KParams& kp, const double* P,
-                    int chunks, hipStream_t s) {
+void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_build_C<R>, dim3(ph.nbox, chunks), dim3(256), 0, s, L, ph, kp, P);
+  hipLaunchKernelGGL(k_build_C<R>, dim3(ph.nbox, chunks), dim3(256), 0, s, probs, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,8 +161,7 @@ void launch_build_C(const Level<R>& L, const Phase<R>& ph, const KParams& kp, co
 // columns reordered to ascending ids.  One workgroup per box.
 // ---------------------------------------------------------------------------
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void k_cpqr(Level<R> L, Phase<R> ph, Records<R> rec, double tol,
-                                             int nmax, int vcap) {
+__global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, int nmax, int vcap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
   double* nrm = reinterpret_cast<double*>(smem_raw);               // nmax
@@ -168,7 +173,10 @@ __global__ __launch_bounds__(NT) void k_cpqr(Level<R> L, Phase<R> ph, Records<R>
   __shared__ double sh_nu0;
 
   const int slot = blockIdx.x, b = ph.box[slot];
-  const int n = L.cur[b], m = ph.mrow[b];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  const double tol = probs[ph.prob[slot]].tol;
+  const int n = L.cur[b], m = ph.mrow[slot];
   const bool vlds = m <= vcap;
   cx<R>* C = ph.W + ph.oC[slot];
   int* Sloc = ph.Wi + ph.oI[slot];
@@ -315,15 +323,14 @@ __global__ __launch_bounds__(NT) void k_cpqr(Level<R> L, Phase<R> ph, Records<R>
 }
 
 template <class R>
-void launch_cpqr(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, double tol,
-                 int nmax, int mmax, hipStream_t s) {
+void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s) {
   if (ph.nbox == 0) return;
   constexpr int NT = 512;
   const size_t head = ((size_t)nmax * 8 + (NT / 64) * 8 + (size_t)nmax * 8 + 15) & ~(size_t)15;
   // the Householder vector is staged in LDS when it fits in 48 KiB
   const int vcap = (int)((48 * 1024) / sizeof(cx<R>));
   const size_t shm = head + (size_t)(mmax < vcap ? mmax : vcap) * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_cpqr<R, NT>), dim3(ph.nbox), dim3(NT), shm, s, L, ph, rec, tol, nmax, vcap);
+  hipLaunchKernelGGL((k_cpqr<R, NT>), dim3(ph.nbox), dim3(NT), shm, s, probs, ph, nmax, vcap);
 }
 
 // ---------------------------------------------------------------------------
@@ -334,8 +341,10 @@ void launch_cpqr(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, d
 // part 0: the box's own block; part 1 + j: neighbour j (ascending id).
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_sparsify(Level<R> L, Phase<R> ph, Records<R> rec) {
+__global__ __launch_bounds__(256) void k_sparsify(const Prob<R>* probs, Phase<R> ph) {
   const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
   const int k = rec.k[b], r = rec.r[b];
   if (r == 0) return;
   const int part = blockIdx.y;
@@ -411,9 +420,9 @@ __global__ __launch_bounds__(256) void k_sparsify(Level<R> L, Phase<R> ph, Recor
 }
 
 template <class R>
-void launch_sparsify(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s) {
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(256), 0, s, L, ph, rec);
+  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(256), 0, s, probs, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,12 +430,13 @@ void launch_sparsify(const Level<R>& L, const Phase<R>& ph, const Records<R>& re
 // (the LU of eq. e:step, kept as an explicit inverse).  One workgroup per box.
 // ---------------------------------------------------------------------------
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void k_inverse(Phase<R> ph, Records<R> rec, int* errflag) {
+__global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> ph, int* errflag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double rv[NT];
   __shared__ int ri[NT];
   __shared__ int sh_p;
   const int slot = blockIdx.x, b = ph.box[slot];
+  const Records<R> rec = probs[ph.prob[slot]].rec;
   const int r = rec.r[b];
   if (r == 0) return;
   cx<R>* colk = reinterpret_cast<cx<R>*>(smem_raw);
@@ -507,21 +517,22 @@ __global__ __launch_bounds__(NT) void k_inverse(Phase<R> ph, Records<R> rec, int
 }
 
 template <class R>
-void launch_inverse(const Phase<R>& ph, const Records<R>& rec, int* errflag, int nmax,
+void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s) {
   if (ph.nbox == 0) return;
   const size_t shm = (size_t)nmax * (sizeof(cx<R>) + sizeof(int)) + 16;
-  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, ph, rec, errflag);
+  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, errflag);
 }
 
 // ---------------------------------------------------------------------------
 // GEMM descriptors
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ void k_plan_y(Phase<R> ph, Records<R> rec, GemmDesc<R>* desc) {
+__global__ void k_plan_y(const Prob<R>* probs, Phase<R> ph, GemmDesc<R>* desc) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= ph.nbox) return;
   const int b = ph.box[slot];
+  const Records<R>& rec = probs[ph.prob[slot]].rec;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
   GemmDesc<R> d;
   d.C = rec.F + rec.oY[b];
@@ -539,17 +550,19 @@ __global__ void k_plan_y(Phase<R> ph, Records<R> rec, GemmDesc<R>* desc) {
 }
 
 template <class R>
-void launch_plan_y(const Phase<R>& ph, const Records<R>& rec, GemmDesc<R>* desc, hipStream_t s) {
+void launch_plan_y(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_plan_y<R>, dim3((ph.nbox + 63) / 64), dim3(64), 0, s, ph, rec, desc);
+  hipLaunchKernelGGL(k_plan_y<R>, dim3((ph.nbox + 63) / 64), dim3(64), 0, s, probs, ph, desc);
 }
 
 // Schur complement update (eq. e:step, Rem. r:nn):
 //   block(t1, t2) -= [X_SR; X_NR](rows of t1) * Y(:, cols of t2)
 // for t1, t2 in {B} u N(B); B's own rows/columns are its skeletons.
 template <class R>
-__global__ void k_plan_schur(Level<R> L, Phase<R> ph, Records<R> rec, GemmDesc<R>* desc) {
+__global__ void k_plan_schur(const Prob<R>* probs, Phase<R> ph, GemmDesc<R>* desc) {
   const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
   const int t = threadIdx.x;
   if (t >= 81) return;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
@@ -591,10 +604,9 @@ __global__ void k_plan_schur(Level<R> L, Phase<R> ph, Records<R> rec, GemmDesc<R
 }
 
 template <class R>
-void launch_plan_schur(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec,
-                       GemmDesc<R>* desc, hipStream_t s) {
+void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_plan_schur<R>, dim3(ph.nbox), dim3(128), 0, s, L, ph, rec, desc);
+  hipLaunchKernelGGL(k_plan_schur<R>, dim3(ph.nbox), dim3(128), 0, s, probs, ph, desc);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,8 +677,10 @@ void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipSt
 // (in ascending order), and B's active ids shrink to S.
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_compact(Level<R> L, Phase<R> ph, Records<R> rec) {
+__global__ __launch_bounds__(256) void k_compact(const Prob<R>* probs, Phase<R> ph) {
   const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
   const int k = rec.k[b], r = rec.r[b];
   if (r == 0) return;
   const int s = blockIdx.y;
@@ -771,9 +785,9 @@ __global__ __launch_bounds__(256) void k_compact(Level<R> L, Phase<R> ph, Record
 }
 
 template <class R>
-void launch_compact(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec, hipStream_t s) {
+void launch_compact(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_compact<R>, dim3(ph.nbox, 25), dim3(256), 0, s, L, ph, rec);
+  hipLaunchKernelGGL(k_compact<R>, dim3(ph.nbox, 25), dim3(256), 0, s, probs, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,22 +797,24 @@ void launch_compact(const Level<R>& L, const Phase<R>& ph, const Records<R>& rec
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, const ListEntry* lists,
-                                                        int tiles_r, Level<R> child, int have_child,
-                                                        cx<R>* dst, KParams kp, const double* P) {
+                                                        int tiles_r, const Prob<R>* probs) {
   const PairDesc d = pd[blockIdx.x];
   const int tr = blockIdx.y % tiles_r, tc = blockIdx.y / tiles_r;
   const int i0 = tr * 64, j0 = tc * 64;
   if (i0 >= d.nr || j0 >= d.nc) return;
+  const Level<R> child = probs[d.prob].L;
+  const KParams kp = probs[d.prob].kp;
+  const double* P = probs[d.prob].P;
   const ListEntry* rows = lists + d.roff;
   const ListEntry* cols = lists + d.coff;
-  cx<R>* out = dst + d.off;
+  cx<R>* out = (cx<R>*)d.dst;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int i = i0 + (e & 63), j = j0 + (e >> 6);
     if (i >= d.nr || j >= d.nc) continue;
     const ListEntry ri = rows[i], cj = cols[j];
     cx<R> v;
     bool stored = false;
-    if (have_child) {
+    if (d.have_child) {
       const int dx = cj.box % child.nb - ri.box % child.nb;
       const int dy = cj.box / child.nb - ri.box / child.nb;
       if (abs(dx) <= 2 && abs(dy) <= 2) {
@@ -817,24 +833,19 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
 
 template <class R>
 void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
-                           int max_c, const Level<R>* child, cx<R>* dst, const KParams& kp,
-                           const double* P, hipStream_t s) {
+                           int max_c, const Prob<R>* child, hipStream_t s) {
   if (npairs == 0 || max_r <= 0 || max_c <= 0) return;
   const int tr = (max_r + 63) / 64, tc = (max_c + 63) / 64;
-  Level<R> c{};
-  int have = 0;
-  if (child) {
-    c = *child;
-    have = 1;
-  }
-  hipLaunchKernelGGL(k_assemble_pairs<R>, dim3(npairs, tr * tc), dim3(256), 0, s, pd, lists, tr, c,
-                     have, dst, kp, P);
+  hipLaunchKernelGGL(k_assemble_pairs<R>, dim3(npairs, tr * tc), dim3(256), 0, s, pd, lists, tr,
+                     child);
 }
 
 // ---------------------------------------------------------------------------
 // root: dense inverse by Gauss-Jordan elimination with partial pivoting, one
-// launch per pivot (ping-pong buffers); the next pivot is chosen by the
-// launch that produces its column (packed |a| / index keys, atomicMax).
+// launch per pivot step for all problems of a batch (ping-pong buffers); the
+// next pivot is chosen by the launch that produces its column (packed |a| /
+// index keys, atomicMax).  After n steps the result (before the final column
+// permutation) is in tmp for odd n and in A for even n.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long pivkey(double a2, int i) {
   const float f = (float)sqrt(a2);
@@ -842,12 +853,12 @@ __device__ __forceinline__ unsigned long long pivkey(double a2, int i) {
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_root_pivot0(const cx<R>* A, int n,
-                                                     unsigned long long* keys) {
+__global__ __launch_bounds__(256) void k_root_pivot0(const RootDesc<R>* rd) {
   __shared__ unsigned long long red[256];
+  const RootDesc<R> d = rd[blockIdx.x];
   unsigned long long best = 0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const unsigned long long kk = pivkey(abs2d(A[i]), i);
+  for (int i = threadIdx.x; i < d.n; i += 256) {
+    const unsigned long long kk = pivkey(abs2d(d.A[i]), i);
     best = kk > best ? kk : best;
   }
   red[threadIdx.x] = best;
@@ -856,21 +867,26 @@ __global__ __launch_bounds__(256) void k_root_pivot0(const cx<R>* A, int n,
     if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) keys[0] = red[0];
+  if (threadIdx.x == 0) d.keys[0] = red[0];
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_root_gj(const cx<R>* src, cx<R>* dst, int n, int kk,
-                                                 unsigned long long* keys, int* perm, int* errflag) {
-  const unsigned long long key = keys[kk];
-  const int p = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+__global__ __launch_bounds__(256) void k_root_gj(const RootDesc<R>* rd, int kk, int* errflag) {
+  const RootDesc<R> d = rd[blockIdx.z];
+  const int n = d.n;
+  if (kk >= n) return;
+  const cx<R>* src = (kk & 1) ? d.tmp : d.A;
+  cx<R>* dst = (kk & 1) ? d.A : d.tmp;
   const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  if (i0 >= n || j0 >= n) return;
+  const unsigned long long key = d.keys[kk];
+  const int p = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
   const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4);
   if (key == 0ull || p < kk || p >= n) {  // no pivot recorded (an earlier step was singular)
     if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(errflag, ERRF_SINGULAR);
     return;
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) perm[kk] = p;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) d.perm[kk] = p;
   const cx<R> akk = src[p + (int64_t)kk * n];
   const double dd = abs2d(akk);
   if (dd == 0.0) {
@@ -893,7 +909,6 @@ __global__ __launch_bounds__(256) void k_root_gj(const cx<R>* src, cx<R>* dst, i
     if (j == kk + 1 && i >= kk + 1) best = pivkey(abs2d(v), i);
   }
   if (j0 <= kk + 1 && kk + 1 < j0 + 16 && kk + 1 < n) {
-    // reduce the next pivot candidate over this tile's column kk+1
     __shared__ unsigned long long red[256];
     red[threadIdx.x] = best;
     __syncthreads();
@@ -901,74 +916,76 @@ __global__ __launch_bounds__(256) void k_root_gj(const cx<R>* src, cx<R>* dst, i
       if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
       __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0]) atomicMax(keys + kk + 1, red[0]);
+    if (threadIdx.x == 0 && red[0]) atomicMax(d.keys + kk + 1, red[0]);
   }
 }
 
-// undo the row interchanges: apply the column interchanges in reverse order
-__global__ void k_root_colperm(const int* perm, int n, int* cp) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int j = 0; j < n; ++j) cp[j] = j;
-  for (int kk = n - 1; kk >= 0; --kk) {
-    int p = perm[kk];
-    if (p < 0 || p >= n) p = kk;
-    const int t = cp[kk];
-    cp[kk] = cp[p];
-    cp[p] = t;
+// undo the row interchanges: the column interchanges in reverse order, then
+// gather the columns into the other buffer (result: A for odd n, tmp for even n)
+template <class R>
+__global__ __launch_bounds__(256) void k_root_finish(const RootDesc<R>* rd) {
+  const RootDesc<R> d = rd[blockIdx.y];
+  const int n = d.n;
+  int* cp = d.perm + n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = 0; j < n; ++j) cp[j] = j;
+    for (int kk = n - 1; kk >= 0; --kk) {
+      int p = d.perm[kk];
+      if (p < 0 || p >= n) p = kk;
+      const int t = cp[kk];
+      cp[kk] = cp[p];
+      cp[p] = t;
+    }
   }
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_gather_cols(const cx<R>* src, cx<R>* dst, int n,
-                                                     const int* cp) {
+__global__ __launch_bounds__(256) void k_root_gather(const RootDesc<R>* rd) {
+  const RootDesc<R> d = rd[blockIdx.y];
+  const int n = d.n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)n * n) return;
+  const cx<R>* src = (n & 1) ? d.tmp : d.A;
+  cx<R>* dst = (n & 1) ? d.A : d.tmp;
   const int i = (int)(e % n), j = (int)(e / n);
-  dst[e] = src[i + (int64_t)cp[j] * n];
+  dst[e] = src[i + (int64_t)d.perm[n + j] * n];
 }
 
 template <class R>
-int launch_root_inverse(cx<R>* A, cx<R>* tmp, int n, unsigned long long* keys, int* perm,
-                        int* errflag, hipStream_t s) {
-  if (n == 0) return 0;
-  launch_fill_u64(keys, n, 0ull, s);
-  hipLaunchKernelGGL(k_root_pivot0<R>, dim3(1), dim3(256), 0, s, A, n, keys);
-  const int t = (n + 15) / 16;
-  cx<R>* src = A;
-  cx<R>* dst = tmp;
-  for (int kk = 0; kk < n; ++kk) {
-    hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t), dim3(256), 0, s, src, dst, n, kk, keys, perm,
-                       errflag);
-    cx<R>* u = src;
-    src = dst;
-    dst = u;
-  }
-  // src holds the inverse up to column order; perm (n ints) is followed by n ints of space
-  hipLaunchKernelGGL(k_root_colperm, dim3(1), dim3(64), 0, s, perm, n, perm + n);
-  const int64_t tot = (int64_t)n * n;
-  hipLaunchKernelGGL(k_gather_cols<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src,
-                     dst, n, perm + n);
-  return dst == A ? 0 : 1;  // 0: result in A, 1: result in tmp
+void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errflag, hipStream_t s) {
+  if (nprob == 0 || nmax == 0) return;
+  hipLaunchKernelGGL(k_root_pivot0<R>, dim3(nprob), dim3(256), 0, s, rd);
+  const int t = (nmax + 15) / 16;
+  for (int kk = 0; kk < nmax; ++kk)
+    hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t, nprob), dim3(256), 0, s, rd, kk, errflag);
+  hipLaunchKernelGGL(k_root_finish<R>, dim3(1, nprob), dim3(64), 0, s, rd);
+  const int64_t tot = (int64_t)nmax * nmax;
+  hipLaunchKernelGGL(k_root_gather<R>, dim3((unsigned)((tot + 255) / 256), nprob), dim3(256), 0, s,
+                     rd);
 }
 
 // ---------------------------------------------------------------------------
-// solve sweeps (Sec. 2.6), NC right-hand-side columns per workgroup
+// solve sweeps (Sec. 2.6), up to 8 right-hand-side columns per workgroup
 //  forward : z_R -= T^* z_S;  w = X_RR^{-1} z_R;  z_{S,N} -= [X_SR; X_NR] w
 //  backward: x_R = X_RR^{-1} z_R - Y z_{S,N};  z_S -= T x_R;  z_R = x_R
 // ---------------------------------------------------------------------------
-
 template <class R>
-__global__ __launch_bounds__(256) void k_solve_fwd(Phase<R> ph, Records<R> rec, cx<R>* z, int64_t ldz,
-                                                   int nrhs, int kmax, int rmax, int SNC) {
+__global__ __launch_bounds__(256) void k_solve_fwd(const SolveProb<R>* sp, Phase<R> ph, int kmax,
+                                                   int rmax, int SNC) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<R>* zS = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* zR = zS + (int64_t)kmax * SNC;
   cx<R>* w = zR + (int64_t)rmax * SNC;
   const int b = ph.box[blockIdx.x];
+  const SolveProb<R> pr = sp[ph.prob[blockIdx.x]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
   if (r == 0) return;
   const int c0 = blockIdx.y * SNC;
-  const int nc = min(SNC, nrhs - c0);
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(SNC, pr.nrhs - c0);
   const int* gS = rec.G + rec.oS[b];
   const int* gR = rec.G + rec.oR[b];
   const int* gN = rec.G + rec.oN[b];
@@ -1019,8 +1036,8 @@ __global__ __launch_bounds__(256) void k_solve_fwd(Phase<R> ph, Records<R> rec, 
 }
 
 template <class R>
-void launch_solve_fwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
-                      int kmax, int rmax, hipStream_t s) {
+void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
+                      hipStream_t s) {
   if (ph.nbox == 0) return;
   // right-hand-side columns per workgroup: as many as fit in 64 KiB of LDS (<= 8)
   const size_t per = (size_t)(kmax + 2 * rmax) * sizeof(cx<R>);
@@ -1028,21 +1045,26 @@ void launch_solve_fwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64
   ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
   ncw = ncw > nrhs ? nrhs : ncw;
   hipLaunchKernelGGL(k_solve_fwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
-                     ph, rec, z, ldz, nrhs, kmax, rmax, ncw);
+                     sp, ph, kmax, rmax, ncw);
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_solve_bwd(Phase<R> ph, Records<R> rec, cx<R>* z, int64_t ldz,
-                                                   int nrhs, int rmax, int chunk, int SNC) {
+__global__ __launch_bounds__(256) void k_solve_bwd(const SolveProb<R>* sp, Phase<R> ph, int rmax,
+                                                   int chunk, int SNC) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<R>* zR = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* xR = zR + (int64_t)rmax * SNC;
   cx<R>* zq = xR + (int64_t)rmax * SNC;  // chunk x SNC
   const int b = ph.box[blockIdx.x];
+  const SolveProb<R> pr = sp[ph.prob[blockIdx.x]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
   if (r == 0) return;
   const int c0 = blockIdx.y * SNC;
-  const int nc = min(SNC, nrhs - c0);
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(SNC, pr.nrhs - c0);
   const int* gS = rec.G + rec.oS[b];
   const int* gR = rec.G + rec.oR[b];
   const int* gN = rec.G + rec.oN[b];
@@ -1092,10 +1114,9 @@ __global__ __launch_bounds__(256) void k_solve_bwd(Phase<R> ph, Records<R> rec, 
 }
 
 template <class R>
-void launch_solve_bwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64_t ldz, int nrhs,
-                      int kmax, int rmax, int snmax, hipStream_t s) {
+void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
+                      hipStream_t s) {
   (void)kmax;
-  (void)snmax;
   if (ph.nbox == 0) return;
   const int chunk = 128;
   const size_t per = (size_t)(2 * rmax + chunk) * sizeof(cx<R>);
@@ -1103,40 +1124,48 @@ void launch_solve_bwd(const Phase<R>& ph, const Records<R>& rec, cx<R>* z, int64
   ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
   ncw = ncw > nrhs ? nrhs : ncw;
   hipLaunchKernelGGL(k_solve_bwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
-                     ph, rec, z, ldz, nrhs, rmax, chunk, ncw);
+                     sp, ph, rmax, chunk, ncw);
 }
 
+// root apply for a batch: gather z[ids] -> ws, ws2 = Ainv ws (GEMM), scatter back
 template <class R>
-__global__ void k_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs,
-                              cx<R>* out) {
+__global__ void k_root_gather_rhs(const RootApply<R>* ra, GemmDesc<R>* desc) {
+  const RootApply<R> d = ra[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * nrhs) return;
-  const int i = (int)(e % n), c = (int)(e / n);
-  out[e] = z[ids[i] + (int64_t)c * ldz];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    GemmDesc<R> g;
+    g.C = d.ws + (int64_t)d.n * d.nrhs;
+    g.A = d.Ainv;
+    g.B = d.ws;
+    g.ldc = g.lda = g.ldb = d.n > 0 ? d.n : 1;
+    g.M = d.n;
+    g.N = d.n > 0 ? d.nrhs : 0;
+    g.K = d.n;
+    g.beta = 0;
+    g.sign = 1;
+    desc[blockIdx.y] = g;
+  }
+  if (e >= (int64_t)d.n * d.nrhs) return;
+  const int i = (int)(e % d.n), c = (int)(e / d.n);
+  d.ws[e] = d.z[d.ids[i] + (int64_t)c * d.ldz];
 }
 template <class R>
-__global__ void k_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z,
-                               int64_t ldz) {
+__global__ void k_root_scatter_rhs(const RootApply<R>* ra) {
+  const RootApply<R> d = ra[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * nrhs) return;
-  const int i = (int)(e % n), c = (int)(e / n);
-  z[ids[i] + (int64_t)c * ldz] = in[e];
+  if (e >= (int64_t)d.n * d.nrhs) return;
+  const int i = (int)(e % d.n), c = (int)(e / d.n);
+  d.z[d.ids[i] + (int64_t)c * d.ldz] = d.ws[(int64_t)d.n * d.nrhs + e];
 }
 template <class R>
-void launch_gather_rows(const cx<R>* z, int64_t ldz, const int* ids, int n, int nrhs, cx<R>* out,
-                        hipStream_t s) {
-  const int64_t tot = (int64_t)n * nrhs;
-  if (tot == 0) return;
-  hipLaunchKernelGGL(k_gather_rows<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, z, ldz,
-                     ids, n, nrhs, out);
-}
-template <class R>
-void launch_scatter_rows(const cx<R>* in, const int* ids, int n, int nrhs, cx<R>* z, int64_t ldz,
-                         hipStream_t s) {
-  const int64_t tot = (int64_t)n * nrhs;
-  if (tot == 0) return;
-  hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in,
-                     ids, n, nrhs, z, ldz);
+void launch_root_apply(const RootApply<R>* ra, int nprob, int max_n, int max_nrhs, GemmDesc<R>* desc,
+                       hipStream_t s) {
+  if (nprob == 0 || max_n == 0) return;
+  const int64_t tot = (int64_t)max_n * max_nrhs;
+  const dim3 g((unsigned)((tot + 255) / 256), nprob);
+  hipLaunchKernelGGL(k_root_gather_rhs<R>, g, dim3(256), 0, s, ra, desc);
+  launch_gemm<R>(desc, nprob, max_n, max_nrhs, s);
+  hipLaunchKernelGGL(k_root_scatter_rhs<R>, g, dim3(256), 0, s, ra);
 }
 
 // ---------------------------------------------------------------------------
@@ -1307,34 +1336,23 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
 // explicit instantiations
 // ---------------------------------------------------------------------------
 #define RSS_INST(R)                                                                                \
-  template void launch_leaf_assemble<R>(const Level<R>&, const KParams&, const double*,           \
-                                        hipStream_t);                                              \
-  template void launch_build_C<R>(const Level<R>&, const Phase<R>&, const KParams&, const double*, \
-                                  int, hipStream_t);                                               \
-  template void launch_cpqr<R>(const Level<R>&, const Phase<R>&, const Records<R>&, double, int,   \
-                               int, hipStream_t);                                                  \
-  template void launch_sparsify<R>(const Level<R>&, const Phase<R>&, const Records<R>&,            \
-                                   hipStream_t);                                                   \
-  template void launch_inverse<R>(const Phase<R>&, const Records<R>&, int*, int, hipStream_t);     \
-  template void launch_plan_y<R>(const Phase<R>&, const Records<R>&, GemmDesc<R>*, hipStream_t);   \
-  template void launch_compact<R>(const Level<R>&, const Phase<R>&, const Records<R>&,             \
-                                  hipStream_t);                                                    \
-  template void launch_plan_schur<R>(const Level<R>&, const Phase<R>&, const Records<R>&,          \
-                                     GemmDesc<R>*, hipStream_t);                                   \
+  template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t);                    \
+  template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);              \
+  template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t);            \
+  template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                  \
+  template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t);        \
+  template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);      \
+  template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                   \
+  template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);  \
   template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t);                    \
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
-                                         const Level<R>*, cx<R>*, const KParams&, const double*,   \
-                                         hipStream_t);                                             \
-  template int launch_root_inverse<R>(cx<R>*, cx<R>*, int, unsigned long long*, int*, int*,        \
-                                      hipStream_t);                                                \
-  template void launch_solve_fwd<R>(const Phase<R>&, const Records<R>&, cx<R>*, int64_t, int, int, \
-                                    int, hipStream_t);                                             \
-  template void launch_solve_bwd<R>(const Phase<R>&, const Records<R>&, cx<R>*, int64_t, int, int, \
-                                    int, int, hipStream_t);                                        \
-  template void launch_gather_rows<R>(const cx<R>*, int64_t, const int*, int, int, cx<R>*,         \
-                                      hipStream_t);                                                \
-  template void launch_scatter_rows<R>(const cx<R>*, const int*, int, int, cx<R>*, int64_t,        \
-                                       hipStream_t);
+                                         const Prob<R>*, hipStream_t);                             \
+  template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t);           \
+  template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int,           \
+                                    hipStream_t);                                                  \
+  template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int,           \
+                                    hipStream_t);                                                  \
+  template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
 
 RSS_INST(double)
 RSS_INST(float)

@@ -48,7 +48,8 @@ class rss_stats(ctypes.Structure):
                 ("n_class", ctypes.c_int64 * 12)]
 
 
-EXPORTS = ["rss_factor", "rss_factor_ex", "rss_solve", "rss_apply", "rss_free", "rss_info",
+EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_apply",
+           "rss_apply_batch", "rss_free", "rss_info",
            "rss_skeletons", "rss_kernel_block", "rss_residual", "rss_last_error",
            "rss_error_string"]
 
@@ -86,6 +87,9 @@ def load():
                                      ctypes.c_void_p]
     lib.rss_residual.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.rss_factor_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_int64), P(rss_kernel),
+                                     ctypes.c_double, ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
+    lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
     lib.rss_last_error.restype = ctypes.c_char_p
     lib.rss_error_string.restype = ctypes.c_char_p
     lib.rss_error_string.argtypes = [ctypes.c_int]
@@ -114,6 +118,21 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(int(stream))
 
 
+def make_options(precision="fp64", n_proxy=0, proxy_radius=0.0, refine_tol=0.0, max_refine=0,
+                 root=None, stream=None, profile=False) -> rss_options:
+    opt = rss_options()
+    opt.n_proxy = int(n_proxy)
+    opt.proxy_radius = float(proxy_radius)
+    opt.precision = RSS_FP32_REFINE if precision in ("fp32", "fp32_refine", RSS_FP32_REFINE) else RSS_FP64
+    opt.refine_tol = float(refine_tol)
+    opt.max_refine = int(max_refine)
+    if root is not None:
+        opt.root[0], opt.root[1], opt.root[2] = (float(v) for v in root)
+    opt.stream = _stream_ptr(stream).value
+    opt.profile = 1 if profile else 0
+    return opt
+
+
 class Factorization:
     """An RS-S factorization resident on the GPU (rss_factor_ex)."""
 
@@ -125,22 +144,22 @@ class Factorization:
         self.N = P.shape[0]
         self.kernel = kern
         self._k = make_kernel(kern)
-        opt = rss_options()
-        opt.n_proxy = int(n_proxy)
-        opt.proxy_radius = float(proxy_radius)
-        opt.precision = RSS_FP32_REFINE if precision in ("fp32", "fp32_refine", RSS_FP32_REFINE) else RSS_FP64
-        opt.refine_tol = float(refine_tol)
-        opt.max_refine = int(max_refine)
-        if root is not None:
-            opt.root[0], opt.root[1], opt.root[2] = (float(v) for v in root)
-        opt.stream = _stream_ptr(stream).value
-        opt.profile = 1 if profile else 0
+        opt = make_options(precision, n_proxy, proxy_radius, refine_tol, max_refine, root, stream, profile)
         self._stream = opt.stream
         h = ctypes.c_void_p()
         _check(lib.rss_factor_ex(P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,
                                  ctypes.byref(self._k), float(tol), int(leaf), ctypes.byref(opt),
                                  ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def _wrap(cls, handle, N, kern):
+        self = cls.__new__(cls)
+        self.N = N
+        self.kernel = kern
+        self._k = make_kernel(kern)
+        self._h = handle
+        return self
 
     def _b(self, B):
         import torch
@@ -204,6 +223,31 @@ class Factorization:
             self.close()
         except Exception:
             pass
+
+
+def factor_batch(points_list, kernels, tol: float, leaf: int, **opts):
+    """Factor several independent problems in one batched sweep
+    (rss_factor_batch); returns one Factorization per problem."""
+    lib = load()
+    arrs = [np.ascontiguousarray(P, dtype=np.float64) for P in points_list]
+    n = len(arrs)
+    ptrs = (ctypes.c_void_p * n)(*[a.ctypes.data for a in arrs])
+    ns = (ctypes.c_int64 * n)(*[a.shape[0] for a in arrs])
+    ks = (rss_kernel * n)(*[make_kernel(k) for k in kernels])
+    opt = make_options(**opts)
+    out = (ctypes.c_void_p * n)()
+    _check(lib.rss_factor_batch(n, ptrs, ns, ks, float(tol), int(leaf), ctypes.byref(opt), out))
+    return [Factorization._wrap(ctypes.c_void_p(out[i]), arrs[i].shape[0], kernels[i]) for i in range(n)]
+
+
+def apply_batch(facts, Bs):
+    """One application of each factorization to its own right-hand sides
+    (complex128 column-major CUDA tensors, overwritten), in one batched sweep."""
+    n = len(facts)
+    hs = (ctypes.c_void_p * n)(*[f._h.value for f in facts])
+    bs = (ctypes.c_void_p * n)(*[B.data_ptr() for B in Bs])
+    nr = (ctypes.c_int * n)(*[f._b(B) for f, B in zip(facts, Bs)])
+    _check(load().rss_apply_batch(n, hs, bs, nr))
 
 
 def kernel_block(kern, points_dev, I_dev, J_dev):

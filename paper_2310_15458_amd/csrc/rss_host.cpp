@@ -66,12 +66,16 @@ struct Arena {
     bytes += (double)n;
     return p;
   }
+  std::vector<size_t> sizes;
   void release(void* p) {
     if (!p) return;
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
     if (it != ptrs.end()) {
       (void)hipFree(p);
+      const size_t i = (size_t)(it - ptrs.begin());
+      bytes -= (double)sizes[i];
       ptrs.erase(it);
+      sizes.erase(sizes.begin() + (long)i);
     }
   }
   ~Arena() {

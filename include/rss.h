@@ -124,6 +124,16 @@ int rss_factor_ex(const double* points, int64_t n, const rss_kernel* k, double t
  */
 int rss_solve(rss_handle h, void* B, int nrhs);
 
+/*
+ * rss_solve_batch -- rss_solve for several factorizations at once: every
+ * application of the factored inverses is one batched sweep over all problems
+ * that are still refining.  All handles must share precision and refinement
+ * mode; work runs on the stream of hs[0].  B[p]: device complex128,
+ * n_p x nrhs[p], column-major, overwritten.  Returns RSS_ENOCONV if any
+ * problem missed its refine_tol (every B[p] holds the best iterate).
+ */
+int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs);
+
 /* rss_apply -- one application of the factored inverse, no refinement. */
 int rss_apply(rss_handle h, void* B, int nrhs);
 
@@ -211,6 +221,65 @@ int rss_kernel_block(const rss_kernel* k, const double* points, int64_t n, const
  */
 int rss_residual(const rss_kernel* k, const double* points, int64_t n, const void* X,
                  const void* B, void* R, int nrhs, void* stream);
+
+/*
+ * rss_set_stream -- move a handle's later work to another stream (hipStream_t;
+ * NULL is not allowed).  The caller orders it after work already queued.
+ */
+int rss_set_stream(rss_handle h, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Solve server: factorizations stay resident in device memory; factor and   */
+/* solve requests are served with continuous batching (a factor worker and a */
+/* solve worker on separate streams).                                        */
+/* ------------------------------------------------------------------------- */
+typedef struct rss_server* rss_server_t;
+
+typedef struct {
+  double budget_bytes;    /* device memory the resident factorizations may hold; new factor
+                             jobs wait for room, least-recently-used unpinned ones are evicted
+                             (the size of a job is estimated from the largest bytes per
+                             unknown seen so far; an empty server always admits a job) */
+  int precision;          /* rss_precision of every factorization */
+  double tol;             /* ID tolerance (Def. 1) */
+  int leaf;               /* points per leaf box */
+  int n_proxy;            /* 0 -> per-kernel default */
+  double refine_tol;      /* as rss_options */
+  int max_refine;         /* as rss_options */
+  int max_batch;          /* most solves in one batched sweep; 0 -> 64 */
+} rss_server_options;
+
+typedef struct {
+  int64_t req;            /* request id (for a factor request: the factorization id) */
+  int kind;               /* 0 factor, 1 solve */
+  int status;             /* rss_status of the request */
+  double t_submit, t_start, t_end;  /* seconds since the server started */
+  double relres;          /* refined solves: max column relative residual; else -1 */
+  int iters;              /* refinement steps */
+  int batch;              /* solves in the batched sweep that served it */
+} rss_completion;
+
+typedef struct {
+  int64_t factored, evictions, batches, batched_solves, max_batch_seen, resident, pending;
+  double used_bytes, peak_bytes;
+  double solved_unknowns; /* sum over completed solves of n * nrhs */
+} rss_server_stats;
+
+/* rss_server_create -- start the workers.  Returns RSS_EINVAL on bad options. */
+int rss_server_create(const rss_server_options* o, rss_server_t* out);
+/* rss_server_factor -- queue a factorization (points: host n x 2, copied); *id names it. */
+int rss_server_factor(rss_server_t s, const double* points, int64_t n, const rss_kernel* k,
+                      int64_t* id);
+/* rss_server_solve -- queue a solve against factorization id (queued or resident; it is
+ * pinned until the solve completes).  B: device complex128 n x nrhs column-major,
+ * overwritten with the solution; the caller must not touch it before completion. */
+int rss_server_solve(rss_server_t s, int64_t id, void* B, int nrhs, int64_t* req);
+/* rss_server_poll -- take up to cap completions, waiting up to wait_ms for the first. */
+int rss_server_poll(rss_server_t s, rss_completion* out, int cap, int wait_ms, int* count);
+/* rss_server_stats_get -- counters of the server. */
+int rss_server_stats_get(rss_server_t s, rss_server_stats* out);
+/* rss_server_destroy -- finish queued work, stop the workers, free everything. */
+int rss_server_destroy(rss_server_t s);
 
 /* rss_last_error -- message for the last failure on this thread ("" if none). */
 const char* rss_last_error(void);

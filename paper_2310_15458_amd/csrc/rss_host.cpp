@@ -1157,115 +1157,145 @@ int rss_factor(const double* points, int64_t n, const rss_kernel* k, double tol,
   return rss_factor_ex(points, n, k, tol, leaf, nullptr, out);
 }
 
-int rss_apply(rss_handle h, void* B, int nrhs) {
-  return run([&] {
-    if (!h || !B) fail(RSS_EINVAL, "null argument");
-    if (nrhs < 1) fail(RSS_EINVAL, "nrhs must be >= 1");
-    if (h->precision == RSS_FP64) {
-      apply_impl<double>(h, (cx<double>*)B, nrhs);
-    } else {
-      const size_t tot = (size_t)h->N * nrhs;
-      cx<float>* z = (cx<float>*)h->arena.alloc(tot * sizeof(cx<float>));
-      launch_cast_c64((const cx<double>*)B, h->N, nrhs, z, h->stream);
-      // B := 0 + 1 * z
-      HIPCHK(hipMemsetAsync(B, 0, tot * sizeof(cx<double>), h->stream));
-      apply_impl<float>(h, z, nrhs);
-      launch_axpy_from_c64(z, h->N, nrhs, nullptr, (cx<double>*)B, h->stream);
-      HIPCHK(hipStreamSynchronize(h->stream));
-      h->arena.release(z);
-    }
-    HIPCHK(hipStreamSynchronize(h->stream));
-  });
-}
+int rss_apply(rss_handle h, void* B, int nrhs) { return rss_apply_batch(1, &h, &B, &nrhs); }
 
-int rss_solve(rss_handle h, void* B, int nrhs) {
+int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
   int code = RSS_OK;
   const int rc = run([&] {
-    if (!h || !B) fail(RSS_EINVAL, "null argument");
-    if (nrhs < 1) fail(RSS_EINVAL, "nrhs must be >= 1");
-    hipStream_t s = h->stream;
-    const int64_t N = h->N;
-    const size_t tot = (size_t)N * nrhs;
+    if (nh < 1 || !hs || !B || !nrhs) fail(RSS_EINVAL, "bad batch arguments");
+    std::vector<rss_ctx*> H(hs, hs + nh);
+    for (int p = 0; p < nh; ++p) {
+      if (!H[p] || !B[p]) fail(RSS_EINVAL, "null argument");
+      if (nrhs[p] < 1) fail(RSS_EINVAL, "nrhs must be >= 1");
+      if (H[p]->precision != H[0]->precision || (H[p]->refine_steps >= 0) != (H[0]->refine_steps >= 0))
+        fail(RSS_EINVAL, "a batch must share precision and refinement mode");
+    }
+    hipStream_t s = H[0]->stream;
+    for (int p = 1; p < nh; ++p)
+      if (H[p]->stream != s) HIPCHK(hipStreamSynchronize(H[p]->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    const bool refine = h->refine_steps >= 0;
-    h->stats.last_iters = 0;
+    const bool fp32 = H[0]->precision == RSS_FP32_REFINE;
+    const bool refine = H[0]->refine_steps >= 0;
+    std::vector<int> nr(nrhs, nrhs + nh);
+    Scratch scr;
+    for (auto* h : H) h->stats.last_iters = 0;
     if (!refine) {
-      if (h->precision == RSS_FP64) {
-        apply_impl<double>(h, (cx<double>*)B, nrhs);
+      if (!fp32) {
+        std::vector<cx<double>*> Z;
+        for (int p = 0; p < nh; ++p) Z.push_back((cx<double>*)B[p]);
+        apply_batch<double>(H, Z, nr, s);
       } else {
-        cx<float>* z = (cx<float>*)h->arena.alloc(tot * sizeof(cx<float>));
-        launch_cast_c64((const cx<double>*)B, N, nrhs, z, s);
-        HIPCHK(hipMemsetAsync(B, 0, tot * sizeof(cx<double>), s));
-        apply_impl<float>(h, z, nrhs);
-        launch_axpy_from_c64(z, N, nrhs, nullptr, (cx<double>*)B, s);
-        HIPCHK(hipStreamSynchronize(s));
-        h->arena.release(z);
-      }
-      h->stats.last_relres = -1.0;
-    } else {
-      cx<double>* b = (cx<double>*)h->arena.alloc(tot * sizeof(cx<double>));
-      cx<double>* x = (cx<double>*)h->arena.alloc(tot * sizeof(cx<double>));
-      cx<double>* r = (cx<double>*)h->arena.alloc(tot * sizeof(cx<double>));
-      double* nrm = (double*)h->arena.alloc((size_t)nrhs * 2 * sizeof(double));
-      cx<float>* z = h->precision == RSS_FP32_REFINE
-                         ? (cx<float>*)h->arena.alloc(tot * sizeof(cx<float>))
-                         : nullptr;
-      HIPCHK(hipMemcpyAsync(b, B, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemsetAsync(x, 0, tot * sizeof(cx<double>), s));
-      HIPCHK(hipMemcpyAsync(r, B, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-      std::vector<double> bn(nrhs), rn(nrhs);
-      launch_colnorms(b, N, nrhs, nrm + nrhs, s);
-      HIPCHK(hipMemcpyAsync(bn.data(), nrm + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      double relres = 1.0;
-      int it = 0;
-      for (;; ++it) {
-        // correction d = F^{-1} r, x += d
-        if (h->precision == RSS_FP32_REFINE) {
-          launch_colnorms(r, N, nrhs, nrm, s);
-          launch_scale_to_c64(r, N, nrhs, nrm, z, s);
-          apply_impl<float>(h, z, nrhs);
-          launch_axpy_from_c64(z, N, nrhs, nrm, x, s);
-        } else {
-          apply_impl<double>(h, r, nrhs);
-          launch_add_c128(x, r, (int64_t)tot, s);
+        std::vector<cx<float>*> Z;
+        for (int p = 0; p < nh; ++p) {
+          const size_t tot = (size_t)H[p]->N * nr[p];
+          cx<float>* z = (cx<float>*)scr.alloc(tot * sizeof(cx<float>));
+          launch_cast_c64((const cx<double>*)B[p], H[p]->N, nr[p], z, s);
+          HIPCHK(hipMemsetAsync(B[p], 0, tot * sizeof(cx<double>), s));
+          Z.push_back(z);
         }
-        // r = b - A x (FP64, on the fly)
-        launch_residual(h->kp, h->d_P, N, x, b, r, nrhs, s);
-        launch_colnorms(r, N, nrhs, nrm, s);
-        HIPCHK(hipMemcpyAsync(rn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        relres = 0.0;
-        for (int j = 0; j < nrhs; ++j) relres = std::max(relres, bn[j] > 0 ? rn[j] / bn[j] : 0.0);
-        if (relres <= h->opt.refine_tol || it >= h->refine_steps) break;
+        apply_batch<float>(H, Z, nr, s);
+        for (int p = 0; p < nh; ++p)
+          launch_axpy_from_c64(Z[p], H[p]->N, nr[p], nullptr, (cx<double>*)B[p], s);
       }
-      h->stats.last_relres = relres;
-      h->stats.last_iters = it;
-      HIPCHK(hipMemcpyAsync(B, x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+      for (auto* h : H) h->stats.last_relres = -1.0;
+    } else {
+      // x = F^{-1} b, then x += F^{-1} (b - A x) with the FP64 on-the-fly residual,
+      // each problem until max_j ||r_j|| / ||b_j|| <= its refine_tol
+      struct St {
+        cx<double>*b, *x, *r;
+        double* nrm;
+        cx<float>* z;
+        std::vector<double> bn, rn;
+        double relres = 1.0;
+        int it = 0;
+        bool done = false;
+      };
+      std::vector<St> st(nh);
+      for (int p = 0; p < nh; ++p) {
+        const size_t tot = (size_t)H[p]->N * nr[p];
+        St& q = st[p];
+        q.b = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
+        q.x = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
+        q.r = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
+        q.nrm = (double*)scr.alloc((size_t)nr[p] * 2 * sizeof(double));
+        q.z = fp32 ? (cx<float>*)scr.alloc(tot * sizeof(cx<float>)) : nullptr;
+        HIPCHK(hipMemcpyAsync(q.b, B[p], tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemsetAsync(q.x, 0, tot * sizeof(cx<double>), s));
+        HIPCHK(hipMemcpyAsync(q.r, B[p], tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        q.bn.resize(nr[p]);
+        q.rn.resize(nr[p]);
+        launch_colnorms(q.b, H[p]->N, nr[p], q.nrm + nr[p], s);
+        HIPCHK(hipMemcpyAsync(q.bn.data(), q.nrm + nr[p], nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
+      }
       HIPCHK(hipStreamSynchronize(s));
-      h->arena.release(b);
-      h->arena.release(x);
-      h->arena.release(r);
-      h->arena.release(nrm);
-      if (z) h->arena.release(z);
-      if (relres > h->opt.refine_tol) {
-        g_err = "refinement did not reach refine_tol";
-        code = RSS_ENOCONV;
+      for (;;) {
+        std::vector<int> live;
+        for (int p = 0; p < nh; ++p)
+          if (!st[p].done) live.push_back(p);
+        if (live.empty()) break;
+        std::vector<rss_ctx*> LH;
+        std::vector<int> Lnr;
+        for (int p : live) {
+          LH.push_back(H[p]);
+          Lnr.push_back(nr[p]);
+        }
+        // corrections d = F^{-1} r for every live problem in one batched sweep
+        if (fp32) {
+          std::vector<cx<float>*> Z;
+          for (int p : live) {
+            launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
+            launch_scale_to_c64(st[p].r, H[p]->N, nr[p], st[p].nrm, st[p].z, s);
+            Z.push_back(st[p].z);
+          }
+          apply_batch<float>(LH, Z, Lnr, s);
+          for (int p : live) launch_axpy_from_c64(st[p].z, H[p]->N, nr[p], st[p].nrm, st[p].x, s);
+        } else {
+          std::vector<cx<double>*> Z;
+          for (int p : live) Z.push_back(st[p].r);
+          apply_batch<double>(LH, Z, Lnr, s);
+          for (int p : live) launch_add_c128(st[p].x, st[p].r, (int64_t)H[p]->N * nr[p], s);
+        }
+        // residuals r = b - A x (FP64, on the fly)
+        for (int p : live) {
+          launch_residual(H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p], s);
+          launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
+          HIPCHK(hipMemcpyAsync(st[p].rn.data(), st[p].nrm, nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        for (int p : live) {
+          St& q = st[p];
+          q.relres = 0.0;
+          for (int j = 0; j < nr[p]; ++j) q.relres = std::max(q.relres, q.bn[j] > 0 ? q.rn[j] / q.bn[j] : 0.0);
+          if (q.relres <= H[p]->opt.refine_tol || q.it >= H[p]->refine_steps) q.done = true;
+          else q.it++;
+        }
+      }
+      for (int p = 0; p < nh; ++p) {
+        const size_t tot = (size_t)H[p]->N * nr[p];
+        HIPCHK(hipMemcpyAsync(B[p], st[p].x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        H[p]->stats.last_relres = st[p].relres;
+        H[p]->stats.last_iters = st[p].it;
+        if (st[p].relres > H[p]->opt.refine_tol) {
+          g_err = "refinement did not reach refine_tol";
+          code = RSS_ENOCONV;
+        }
       }
     }
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    h->stats.t_solve_ms = ms;
+    for (auto* h : H) h->stats.t_solve_ms = ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   });
   return rc != RSS_OK ? rc : code;
 }
+
+int rss_solve(rss_handle h, void* B, int nrhs) { return rss_solve_batch(1, &h, &B, &nrhs); }
 
 void rss_free(rss_handle h) { destroy_ctx(h); }
 
@@ -1319,6 +1349,15 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   });
+}
+
+int rss_set_stream(rss_handle h, void* stream) {
+  if (!h || !stream) {
+    g_err = "null argument";
+    return RSS_EINVAL;
+  }
+  h->stream = (hipStream_t)stream;
+  return RSS_OK;
 }
 
 const char* rss_last_error(void) { return g_err.c_str(); }

@@ -48,10 +48,30 @@ class rss_stats(ctypes.Structure):
                 ("n_class", ctypes.c_int64 * 12)]
 
 
-EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_apply",
-           "rss_apply_batch", "rss_free", "rss_info",
-           "rss_skeletons", "rss_kernel_block", "rss_residual", "rss_last_error",
+EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
+           "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
+           "rss_set_stream", "rss_server_create", "rss_server_factor", "rss_server_solve",
+           "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
+
+
+class rss_server_options(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_double), ("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("leaf", ctypes.c_int), ("n_proxy", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("max_refine", ctypes.c_int), ("max_batch", ctypes.c_int)]
+
+
+class rss_completion(ctypes.Structure):
+    _fields_ = [("req", ctypes.c_int64), ("kind", ctypes.c_int), ("status", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("relres", ctypes.c_double), ("iters", ctypes.c_int), ("batch", ctypes.c_int)]
+
+
+class rss_server_stats(ctypes.Structure):
+    _fields_ = [("factored", ctypes.c_int64), ("evictions", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("batched_solves", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64),
+                ("resident", ctypes.c_int64), ("pending", ctypes.c_int64), ("used_bytes", ctypes.c_double),
+                ("peak_bytes", ctypes.c_double), ("solved_unknowns", ctypes.c_double)]
 
 _lib = None
 
@@ -90,6 +110,17 @@ def load():
     lib.rss_factor_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_int64), P(rss_kernel),
                                      ctypes.c_double, ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
     lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
+    lib.rss_solve_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
+    lib.rss_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.rss_server_create.argtypes = [P(rss_server_options), P(ctypes.c_void_p)]
+    lib.rss_server_factor.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, P(rss_kernel),
+                                      P(ctypes.c_int64)]
+    lib.rss_server_solve.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                     P(ctypes.c_int64)]
+    lib.rss_server_poll.argtypes = [ctypes.c_void_p, P(rss_completion), ctypes.c_int, ctypes.c_int,
+                                    P(ctypes.c_int)]
+    lib.rss_server_stats_get.argtypes = [ctypes.c_void_p, P(rss_server_stats)]
+    lib.rss_server_destroy.argtypes = [ctypes.c_void_p]
     lib.rss_last_error.restype = ctypes.c_char_p
     lib.rss_error_string.restype = ctypes.c_char_p
     lib.rss_error_string.argtypes = [ctypes.c_int]
@@ -274,3 +305,76 @@ def residual(kern, points_dev, X, B):
                                ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                                ctypes.c_void_p(R.data_ptr()), nrhs, _stream_ptr(None)))
     return R
+
+
+def solve_batch(facts, Bs):
+    """rss_solve_batch: refined (per handle settings) solves of several
+    factorizations, every application batched.  Returns the status code."""
+    n = len(facts)
+    hs = (ctypes.c_void_p * n)(*[f._h.value for f in facts])
+    bs = (ctypes.c_void_p * n)(*[B.data_ptr() for B in Bs])
+    nr = (ctypes.c_int * n)(*[f._b(B) for f, B in zip(facts, Bs)])
+    rc = load().rss_solve_batch(n, hs, bs, nr)
+    if rc not in (RSS_OK, RSS_ENOCONV):
+        _check(rc)
+    return rc
+
+
+class Server:
+    """The library's solve server (rss_server_*): resident factorizations,
+    continuous batching of solves, device-memory budget with LRU eviction."""
+
+    def __init__(self, budget_bytes: float, precision: str = "fp32", tol: float = 1e-6, leaf: int = 64,
+                 n_proxy: int = 0, refine_tol: float = 0.0, max_refine: int = 0, max_batch: int = 64):
+        o = rss_server_options(float(budget_bytes),
+                               RSS_FP32_REFINE if precision in ("fp32", "fp32_refine") else RSS_FP64,
+                               float(tol), int(leaf), int(n_proxy), float(refine_tol), int(max_refine),
+                               int(max_batch))
+        h = ctypes.c_void_p()
+        _check(load().rss_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._s = h
+        self._keep = {}
+
+    def factor(self, points, kern) -> int:
+        P = np.ascontiguousarray(points, dtype=np.float64)
+        k = make_kernel(kern)
+        out = ctypes.c_int64()
+        _check(load().rss_server_factor(self._s, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        P.shape[0], ctypes.byref(k), ctypes.byref(out)))
+        return out.value
+
+    def solve(self, fid: int, B) -> int:
+        """B: complex128 column-major CUDA tensor, overwritten on completion."""
+        nrhs = 1 if B.dim() == 1 else B.shape[1]
+        out = ctypes.c_int64()
+        _check(load().rss_server_solve(self._s, int(fid), ctypes.c_void_p(B.data_ptr()), nrhs,
+                                       ctypes.byref(out)))
+        self._keep[out.value] = B
+        return out.value
+
+    def poll(self, wait_ms: int = 0, cap: int = 256) -> list:
+        buf = (rss_completion * cap)()
+        cnt = ctypes.c_int()
+        _check(load().rss_server_poll(self._s, buf, cap, int(wait_ms), ctypes.byref(cnt)))
+        out = []
+        for i in range(cnt.value):
+            c = buf[i]
+            out.append({f: getattr(c, f) for f, _ in rss_completion._fields_})
+            self._keep.pop(c.req, None)
+        return out
+
+    def stats(self) -> dict:
+        st = rss_server_stats()
+        _check(load().rss_server_stats_get(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in rss_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            load().rss_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

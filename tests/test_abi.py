@@ -47,16 +47,20 @@ def _struct_fields(name):
     out = []
     for decl in body.split(";"):
         decl = decl.strip()
-        if not decl:
+        if not decl or "(" in decl:
             continue
-        if "(" in decl:
-            continue
-        ident = re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[\d+\])?\s*$", decl)
-        out.append(ident[0])
+        # "type a, b, c" or "type a[16]": every declarator's identifier
+        first, *rest = decl.split(",")
+        names = [re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[\d+\])?\s*$", first.strip())[0]]
+        names += [re.findall(r"([A-Za-z_][A-Za-z0-9_]*)", r)[0] for r in rest]
+        out.extend(names)
     return out
 
 
 @pytest.mark.parametrize("cname,py", [("rss_kernel", rss.rss_kernel), ("rss_options", rss.rss_options),
-                                      ("rss_stats", rss.rss_stats)])
+                                      ("rss_stats", rss.rss_stats),
+                                      ("rss_server_options", rss.rss_server_options),
+                                      ("rss_completion", rss.rss_completion),
+                                      ("rss_server_stats", rss.rss_server_stats)])
 def test_struct_mirrors(cname, py):
     assert _struct_fields(cname) == [f for f, _ in py._fields_]

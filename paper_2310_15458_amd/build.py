@@ -37,7 +37,8 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
-    cmd = [hipcc(), "-c", *FLAGS, "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), "-c", *FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-x", "hip",
+           os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

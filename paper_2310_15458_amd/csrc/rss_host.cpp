@@ -22,7 +22,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rss.h"
+#include "rss.h"
 #include "rss_internal.h"
 
 using namespace rss;
@@ -63,10 +63,11 @@ struct Arena {
       fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
     }
     ptrs.push_back(p);
+    sizes.push_back(n);
     bytes += (double)n;
     return p;
   }
-  std::vector<size_t> sizes;
+  std::vector<size_t> sizes;  // parallel to ptrs
   void release(void* p) {
     if (!p) return;
     auto it = std::find(ptrs.begin(), ptrs.end(), p);

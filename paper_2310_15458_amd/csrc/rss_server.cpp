@@ -25,7 +25,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/rss.h"
+#include "rss.h"
 
 namespace {
 

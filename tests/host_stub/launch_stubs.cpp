@@ -1,0 +1,44 @@
+// Kernel launchers replaced by no-ops: the host driver and the server run on
+// the CPU against hip/hip_runtime.h of this directory (host-logic test).
+#include "rss_internal.h"
+struct dim3s threadIdx, blockIdx, blockDim;
+namespace rss {
+template <class R> void launch_leaf_assemble(const Prob<R>*, int, int, hipStream_t) {}
+template <class R> void launch_build_C(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
+template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, hipStream_t) {}
+template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, hipStream_t) {}
+template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
+template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
+template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStream_t) {}
+template <class R> void launch_plan_schur(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
+template <class R> void launch_gemm(const GemmDesc<R>*, int, int, int, hipStream_t) {}
+template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
+template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, int*, hipStream_t) {}
+template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t) {}
+template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t) {}
+template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t) {}
+#define I(R) \
+template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
+template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
+template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
+template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
+template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
+template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
+template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
+template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
+template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
+template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \
+template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t); \
+template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t); \
+template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t); \
+template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
+I(double) I(float)
+void launch_kernel_block(const KParams&, const double*, const int*, int64_t, const int*, int64_t, cx<double>*, hipStream_t) {}
+void launch_residual(const KParams&, const double*, int64_t, const cx<double>*, const cx<double>*, cx<double>*, int, hipStream_t) {}
+void launch_colnorms(const cx<double>*, int64_t, int nrhs, double* out, hipStream_t) { for (int i = 0; i < nrhs; ++i) out[i] = 1.0; }
+void launch_scale_to_c64(const cx<double>*, int64_t, int, const double*, cx<float>*, hipStream_t) {}
+void launch_axpy_from_c64(const cx<float>*, int64_t, int, const double*, cx<double>*, hipStream_t) {}
+void launch_cast_c64(const cx<double>*, int64_t, int, cx<float>*, hipStream_t) {}
+void launch_fill_u64(unsigned long long*, int64_t, unsigned long long, hipStream_t) {}
+void launch_add_c128(cx<double>*, const cx<double>*, int64_t, hipStream_t) {}
+}

@@ -590,6 +590,15 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     }
     void* Wd = scr.alloc((size_t)Wmax * E);
     int* Wi = (int*)scr.alloc((size_t)Imax * sizeof(int));
+    // multi-workgroup ID for colours with few boxes: G workgroups per box
+    int Gc[9], Gmax = 1;
+    for (int c = 0; c < 9; ++c) {
+      Gc[c] = M[c].box.empty() ? 1 : cpqr_mg_groups<R>((int)M[c].box.size(), nmax, mmax);
+      Gmax = std::max(Gmax, Gc[c] * (int)M[c].box.size());
+    }
+    double* pnorm = (double*)scr.alloc((size_t)Gmax * nmax * sizeof(double));
+    double* pdot = (double*)scr.alloc((size_t)Gmax * nmax * 2 * sizeof(double));
+    unsigned* bars = (unsigned*)scr.alloc((size_t)std::max(1, maxph) * sizeof(unsigned));
     int* mrow = (int*)scr.alloc((size_t)std::max(1, maxph) * sizeof(int));
     GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
     std::vector<std::vector<int>> mrows(9);
@@ -609,7 +618,10 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       ph.W = (cx<R>*)Wd;
       ph.Wi = Wi;
       prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
-      prof.run(RSS_K_ID, s, [&] { launch_cpqr<R>(d_probs, ph, nmax, mmax, s); });
+      prof.run(RSS_K_ID, s, [&] {
+        if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
+          launch_cpqr<R>(d_probs, ph, nmax, mmax, s);
+      });
       prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(d_probs, ph, s); });
       prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(d_probs, ph, d_err, nmax, s); });
       launch_plan_y<R>(d_probs, ph, desc, s);
@@ -856,6 +868,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   int err = 0;
   HIPCHK(hipMemcpy(&err, d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
+  if (err & ERRF_TIMEOUT) fail(RSS_EHIP, "a per-box device barrier timed out");
   for (int p = 0; p < np; ++p) {
     rss_ctx* h = H[p];
     Work& w = W[p];

@@ -124,7 +124,7 @@ struct ListEntry {
 };
 
 // error flags written by kernels
-enum { ERRF_SINGULAR = 1 };
+enum { ERRF_SINGULAR = 1, ERRF_TIMEOUT = 2 };
 
 // ---------------------------------------------------------------------------
 // launchers (rss_kernels.hip); all enqueue on `s`
@@ -135,6 +135,12 @@ template <class R>
 void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStream_t s);
 template <class R>
 void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s);
+// multi-workgroup ID for phases with few boxes: groups per box (1 = use launch_cpqr)
+template <class R>
+int cpqr_mg_groups(int nbox, int nmax, int mmax);
+template <class R>
+bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
+                    double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s);
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
 template <class R>

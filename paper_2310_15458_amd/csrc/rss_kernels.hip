@@ -334,6 +334,259 @@ void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, h
 }
 
 // ---------------------------------------------------------------------------
+// The same interpolative decomposition with the rows of each box's C split
+// over G workgroups (for depths with few boxes per colour).  Each step the
+// workgroups combine partial dot products and partial column norms through
+// global memory between two per-box barriers; every workgroup then takes the
+// same pivot and truncation decisions from the same sums.  Columns are not
+// moved: a permutation (identical in every workgroup) maps positions to
+// physical columns.  Barriers spin on a per-box counter with a bounded wait
+// (timeout -> error flag, the kernel still exits).  The launch keeps all
+// G x boxes workgroups co-resident.
+// ---------------------------------------------------------------------------
+// bounded wait: ~seconds, long enough for concurrent work on other streams to drain
+constexpr unsigned MG_SPIN_LIMIT = 1u << 24;
+
+__device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > MG_SPIN_LIMIT) {
+        atomicOr(err, ERRF_TIMEOUT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> ph, int G, int nmax,
+                                                double* pnorm, double* pdot, unsigned* bars,
+                                                int* err) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NW = NT / 64;
+  double* nrm = reinterpret_cast<double*>(smem_raw);          // nmax
+  double* wre = nrm + nmax;                                     // nmax
+  double* wim = wre + nmax;                                     // nmax
+  int* perm = reinterpret_cast<int*>(wim + nmax);               // nmax (position -> column)
+  int* rankv = perm + nmax;                                     // nmax
+  __shared__ int sh_p;
+  __shared__ double sh_nu0;
+
+  const int slot = blockIdx.x / G, g = blockIdx.x % G;
+  const int b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  const double tol = probs[ph.prob[slot]].tol;
+  const int n = L.cur[b], m = ph.mrow[slot];
+  cx<R>* C = ph.W + ph.oC[slot];
+  int* Sloc = ph.Wi + ph.oI[slot];
+  const int n0b = L.n0[b];
+  int* Rloc = Sloc + n0b;
+  const int* gid = L.idx + L.ioff[b];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rows = (m + G - 1) / G;
+  const int r0 = min(m, g * rows), r1 = min(m, r0 + rows);
+  double* pn = pnorm + (size_t)slot * G * nmax;   // [g][column]
+  double* pd = pdot + (size_t)slot * G * nmax * 2;
+  unsigned* bar = bars + slot;
+  unsigned nbar = 0;
+
+  for (int c = wv; c < n; c += NW) {
+    const cx<R>* col = C + (int64_t)c * m;
+    double s = 0.0;
+    for (int i = r0 + lane; i < r1; i += 64) s += abs2d(col[i]);
+    s = wave_sum(s);
+    if (lane == 0) pn[(size_t)g * nmax + c] = s;
+  }
+  for (int c = threadIdx.x; c < n; c += NT) perm[c] = c;
+  mg_barrier(bar, (++nbar) * G, err);
+  int k = 0;
+  const int jmax = m < n ? m : n;
+  for (int j = 0; j < jmax; ++j) {
+    for (int c = j + threadIdx.x; c < n; c += NT) {
+      const int q = perm[c];
+      double s = 0.0;
+      for (int h = 0; h < G; ++h) s += pn[(size_t)h * nmax + q];
+      nrm[c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mx = 0.0;
+      for (int c = j; c < n; ++c) mx = fmax(mx, nrm[c]);
+      mx = sqrt(mx);
+      if (j == 0) sh_nu0 = mx;
+      int best = -1;
+      if (!(mx <= tol * sh_nu0)) {
+        const double thr = (1.0 - TIE) * mx;
+        for (int c = j; c < n; ++c)
+          if (sqrt(nrm[c]) >= thr && (best < 0 || gid[perm[c]] < gid[perm[best]])) best = c;
+      }
+      if (best >= 0 && best != j) {
+        const int t = perm[j];
+        perm[j] = perm[best];
+        perm[best] = t;
+        const double u = nrm[j];
+        nrm[j] = nrm[best];
+        nrm[best] = u;
+      }
+      sh_p = best;
+    }
+    __syncthreads();
+    if (sh_p < 0) break;
+    const int pc = perm[j];
+    const cx<R>* cj = C + (int64_t)pc * m;
+    const cx<R> x0 = cj[j];
+    const double ax0 = sqrt(abs2d(x0));
+    const double nrm2 = nrm[j];
+    const double t = fmax(0.0, nrm2 - ax0 * ax0);
+    const double xn = sqrt(nrm2);
+    const double phr = ax0 > 0.0 ? (double)x0.x / ax0 : 1.0;
+    const double phi = ax0 > 0.0 ? (double)x0.y / ax0 : 0.0;
+    const double alr = -phr * xn, ali = -phi * xn;
+    const double v0r = (double)x0.x - alr, v0i = (double)x0.y - ali;
+    const double vv = v0r * v0r + v0i * v0i + t;
+    const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
+    const int i0 = max(r0, j);
+    // partial dot products v^H C[:, q] over this workgroup's rows
+    for (int c = j + 1 + wv; c < n; c += NW) {
+      const int q = perm[c];
+      const cx<R>* col = C + (int64_t)q * m;
+      double dr = 0.0, di = 0.0;
+      for (int i = i0 + lane; i < r1; i += 64) {
+        const cx<R> a = col[i];
+        const double vr = (i == j) ? v0r : (double)cj[i].x;
+        const double vi = (i == j) ? v0i : (double)cj[i].y;
+        dr += vr * a.x + vi * a.y;
+        di += vr * a.y - vi * a.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      if (lane == 0) {
+        pd[((size_t)g * nmax + q) * 2] = dr;
+        pd[((size_t)g * nmax + q) * 2 + 1] = di;
+      }
+    }
+    mg_barrier(bar, (++nbar) * G, err);
+    for (int c = j + 1 + threadIdx.x; c < n; c += NT) {
+      const int q = perm[c];
+      double sr = 0.0, si = 0.0;
+      for (int h = 0; h < G; ++h) {
+        sr += pd[((size_t)h * nmax + q) * 2];
+        si += pd[((size_t)h * nmax + q) * 2 + 1];
+      }
+      wre[c] = beta * sr;
+      wim[c] = beta * si;
+    }
+    __syncthreads();
+    // update this workgroup's rows; partial norms of rows > j
+    for (int c = j + 1 + wv; c < n; c += NW) {
+      const int q = perm[c];
+      cx<R>* col = C + (int64_t)q * m;
+      const double sr = wre[c], si = wim[c];
+      double s2 = 0.0;
+      for (int i = i0 + lane; i < r1; i += 64) {
+        const double vr = (i == j) ? v0r : (double)cj[i].x;
+        const double vi = (i == j) ? v0i : (double)cj[i].y;
+        cx<R> a = col[i];
+        a.x -= (R)(vr * sr - vi * si);
+        a.y -= (R)(vr * si + vi * sr);
+        col[i] = a;
+        if (i > j) s2 += abs2d(a);
+      }
+      s2 = wave_sum(s2);
+      if (lane == 0) pn[(size_t)g * nmax + q] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && j >= r0 && j < r1) C[j + (int64_t)pc * m] = cx<R>{(R)alr, (R)ali};
+    mg_barrier(bar, (++nbar) * G, err);
+    k = j + 1;
+  }
+  if (g != 0) return;
+  const int r = n - k;
+  if (threadIdx.x == 0) {
+    rec.k[b] = k;
+    rec.r[b] = r;
+  }
+  // T = R11^{-1} R12 (R in rows 0..k-1, columns in pivot order via perm), one thread per column
+  cx<R>* Tout = rec.F + rec.oT[b];
+  cx<R>* Tw = C + (int64_t)perm[0] * m;  // unused column space is not touched: write T in place
+  (void)Tw;
+  for (int c = k + threadIdx.x; c < n; c += NT) {
+    cx<R>* col = C + (int64_t)perm[c] * m;
+    for (int i = k - 1; i >= 0; --i) {
+      double sr = col[i].x, si = col[i].y;
+      for (int l = i + 1; l < k; ++l) {
+        const cx<R> a = C[i + (int64_t)perm[l] * m], x = col[l];
+        sr -= (double)a.x * x.x - (double)a.y * x.y;
+        si -= (double)a.x * x.y + (double)a.y * x.x;
+      }
+      const cx<R> d = C[i + (int64_t)perm[i] * m];
+      const double dd = (double)d.x * d.x + (double)d.y * d.y;
+      col[i] = cx<R>{(R)((sr * d.x + si * d.y) / dd), (R)((si * d.x - sr * d.y) / dd)};
+    }
+  }
+  for (int a = threadIdx.x; a < n; a += NT) {
+    const int pa = perm[a];
+    const bool isS = a < k;
+    const int lo = isS ? 0 : k, hi = isS ? k : n;
+    int rk = 0;
+    for (int a2 = lo; a2 < hi; ++a2) rk += perm[a2] < pa;
+    rankv[a] = rk;
+    if (isS) Sloc[rk] = pa;
+    else Rloc[rk] = pa;
+  }
+  __syncthreads();
+  if (k > 0 && r > 0) {
+    for (int e = threadIdx.x; e < k * r; e += NT) {
+      const int a = e % k, c = e / k;
+      Tout[rankv[a] + (int64_t)k * rankv[k + c]] = C[a + (int64_t)perm[k + c] * m];
+    }
+  }
+}
+
+__global__ void k_fill_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+template <class R>
+int cpqr_mg_groups(int nbox, int nmax, int mmax) {
+  constexpr int NT = 512;
+  static int cap = -1;
+  if (cap < 0) {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int per = 0;
+    const size_t shm = (size_t)nmax * (8 * 3 + 8) + 64;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cpqr_mg<R, NT>, NT, shm);
+    cap = cus * (per > 0 ? 1 : 0);  // one workgroup per compute unit: always co-resident
+  }
+  int G = cap / (nbox > 0 ? nbox : 1);
+  G = min(G, max(1, mmax / 128));
+  return G;
+}
+
+template <class R>
+bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
+                    double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s) {
+  constexpr int NT = 512;
+  if (ph.nbox == 0 || G < 2) return false;
+  hipLaunchKernelGGL(k_fill_u32, dim3((ph.nbox + 255) / 256), dim3(256), 0, s, bars, ph.nbox);
+  const size_t shm = (size_t)nmax * (8 * 3 + 8) + 64;
+  hipLaunchKernelGGL((k_cpqr_mg<R, NT>), dim3(ph.nbox * G), dim3(NT), shm, s, probs, ph, G, nmax,
+                     pnorm, pdot, bars, err);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // sparsification (eq. e:s) with the ID of the box:
 //   X_SR = A_SR - A_SS T         X_RS = A_RS - T^* A_SS
 //   X_RR = (A_RR - A_RS T) - T^* X_SR
@@ -1352,7 +1605,10 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
                                     hipStream_t);                                                  \
   template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int,           \
                                     hipStream_t);                                                  \
-  template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
+  template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);  \
+  template int cpqr_mg_groups<R>(int, int, int);                                                     \
+  template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*,  \
+                                  unsigned*, int*, hipStream_t);
 
 RSS_INST(double)
 RSS_INST(float)

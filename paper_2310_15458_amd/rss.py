@@ -89,6 +89,12 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_2310_15458_amd.build")
+    # torch ships its own HIP runtime; loading it first makes the library bind to
+    # the same runtime (one set of devices, streams and allocations per process)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     lib.rss_factor.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(rss_kernel), ctypes.c_double,

@@ -6,6 +6,8 @@ namespace rss {
 template <class R> void launch_leaf_assemble(const Prob<R>*, int, int, hipStream_t) {}
 template <class R> void launch_build_C(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, hipStream_t) {}
+template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
+template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t) { return true; }
 template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, hipStream_t) {}
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
 template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
@@ -22,6 +24,8 @@ template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
 template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
 template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
+template int cpqr_mg_groups<R>(int, int, int); \
+template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t); \
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
 template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \

@@ -96,7 +96,8 @@ __device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0) {
     const double g = fma(t, bg1, cg[0] - bg2);
     y0 = fma(TWO_OVER_PI * log(0.5 * x), j0, g);
   } else {
-    const double u = 1.0 / (x * x);
+    const double ix = 1.0 / x;  // one division; u, Q / x and the amplitude reuse it
+    const double u = ix * ix;
     double P = rss_asym_p[RSS_BESSEL_NASYM_HALF - 1];
     double Q = rss_asym_q[RSS_BESSEL_NASYM_HALF - 1];
 #pragma unroll
@@ -104,12 +105,12 @@ __device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0) {
       P = fma(P, u, rss_asym_p[k]);
       Q = fma(Q, u, rss_asym_q[k]);
     }
-    Q = Q / x;
+    Q = Q * ix;
     double sn, cs;
     sincos(x, &sn, &cs);
     constexpr double RS2 = 0.70710678118654752440;
     const double er = (cs + sn) * RS2, ei = (sn - cs) * RS2;
-    const double amp = sqrt(TWO_OVER_PI / x);
+    const double amp = sqrt(TWO_OVER_PI * ix);
     j0 = amp * (er * P - ei * Q);
     y0 = amp * (er * Q + ei * P);
   }

@@ -160,7 +160,7 @@ void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStr
 // largest trailing norm is <= tol * nu0.  Then T = R11^{-1} R12, rows and
 // columns reordered to ascending ids.  One workgroup per box.
 // ---------------------------------------------------------------------------
-template <class R, int NT>
+template <class R, int NT, int RPL>
 __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, int nmax, int vcap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
@@ -253,25 +253,58 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
       __syncthreads();
       vp = vs;
     }
+    const bool cached = (m - j) <= 64 * RPL;
     for (int c = j + 1 + wv; c < n; c += NW) {
       cx<R>* col = C + (int64_t)c * m;
-      double dr = 0.0, di = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const cx<R> a = col[i], v = vp[i - j];
-        dr += (double)v.x * a.x + (double)v.y * a.y;
-        di += (double)v.x * a.y - (double)v.y * a.x;
-      }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      const double sr = beta * dr, si = beta * di;
-      double s2 = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const cx<R> v = vp[i - j];
-        cx<R> a = col[i];
-        a.x -= (R)((double)v.x * sr - (double)v.y * si);
-        a.y -= (R)((double)v.x * si + (double)v.y * sr);
-        col[i] = a;
-        if (i > j) s2 += abs2d(a);
+      double dr = 0.0, di = 0.0, s2 = 0.0;
+      if (cached) {
+        // one read and one write of the column: it stays in registers between
+        // the dot product and the update
+        cx<R> reg[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) {
+            const cx<R> a = col[i], v = vp[i - j];
+            reg[t] = a;
+            dr += (double)v.x * a.x + (double)v.y * a.y;
+            di += (double)v.x * a.y - (double)v.y * a.x;
+          }
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        const double sr = beta * dr, si = beta * di;
+        // re-read v from memory below instead of keeping a second register copy
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = j + lane + 64 * t;
+          if (i < m) {
+            const cx<R> v = vp[i - j];
+            cx<R> a = reg[t];
+            a.x -= (R)((double)v.x * sr - (double)v.y * si);
+            a.y -= (R)((double)v.x * si + (double)v.y * sr);
+            col[i] = a;
+            if (i > j) s2 += abs2d(a);
+          }
+        }
+      } else {
+        for (int i = j + lane; i < m; i += 64) {
+          const cx<R> a = col[i], v = vp[i - j];
+          dr += (double)v.x * a.x + (double)v.y * a.y;
+          di += (double)v.x * a.y - (double)v.y * a.x;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        const double sr = beta * dr, si = beta * di;
+        for (int i = j + lane; i < m; i += 64) {
+          const cx<R> v = vp[i - j];
+          cx<R> a = col[i];
+          a.x -= (R)((double)v.x * sr - (double)v.y * si);
+          a.y -= (R)((double)v.x * si + (double)v.y * sr);
+          col[i] = a;
+          if (i > j) s2 += abs2d(a);
+        }
       }
       s2 = wave_sum(s2);
       if (lane == 0) nrm[c] = s2;
@@ -325,12 +358,15 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
 template <class R>
 void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  constexpr int NT = 512;
+  // 256 threads: one wave per SIMD, so each lane can keep RPL rows of a
+  // column in registers between the dot product and the update
+  constexpr int NT = 256;
   const size_t head = ((size_t)nmax * 8 + (NT / 64) * 8 + (size_t)nmax * 8 + 15) & ~(size_t)15;
   // the Householder vector is staged in LDS when it fits in 48 KiB
   const int vcap = (int)((48 * 1024) / sizeof(cx<R>));
   const size_t shm = head + (size_t)(mmax < vcap ? mmax : vcap) * sizeof(cx<R>);
-  hipLaunchKernelGGL((k_cpqr<R, NT>), dim3(ph.nbox), dim3(NT), shm, s, probs, ph, nmax, vcap);
+  constexpr int RPL = sizeof(R) == 8 ? 24 : 36;  // the most rows per lane without register spills
+  hipLaunchKernelGGL((k_cpqr<R, NT, RPL>), dim3(ph.nbox), dim3(NT), shm, s, probs, ph, nmax, vcap);
 }
 
 // ---------------------------------------------------------------------------

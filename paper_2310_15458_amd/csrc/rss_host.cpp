@@ -50,24 +50,57 @@ void fail(int code, const std::string& msg) {
 constexpr int MAX_DEPTH = 15;
 constexpr int MIN_DEPTH = 2;  // compressed depths are D .. 2 (4 x 4 boxes and finer)
 
+// Requests up to SMALL bytes are carved from SLAB-byte blocks, one hipMalloc
+// per block; larger ones get their own allocation.  Carved pieces live as long
+// as their owner (release() ignores them).
+constexpr size_t SLAB = (size_t)2 << 20, SMALL = (size_t)64 << 10;
+
+void* dev_alloc(size_t n) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+  }
+  return p;
+}
+
+struct Carver {
+  std::vector<void*> slabs;
+  size_t used = SLAB;
+  void* take(size_t n, double& bytes) {
+    n = (n + 255) & ~(size_t)255;
+    if (used + n > SLAB) {
+      slabs.push_back(dev_alloc(SLAB));
+      bytes += (double)SLAB;
+      used = 0;
+    }
+    void* p = (char*)slabs.back() + used;
+    used += n;
+    return p;
+  }
+  void clear() {
+    for (void* p : slabs) (void)hipFree(p);
+    slabs.clear();
+    used = SLAB;
+  }
+};
+
 // device memory owned by a handle
 struct Arena {
-  std::vector<void*> ptrs;
+  std::vector<void*> ptrs;    // own allocations (large requests)
+  std::vector<size_t> sizes;  // parallel to ptrs
+  Carver small;
   double bytes = 0;
   void* alloc(size_t n) {
     if (n == 0) n = 16;
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
-    }
+    if (n <= SMALL) return small.take(n, bytes);
+    void* p = dev_alloc(n);
     ptrs.push_back(p);
     sizes.push_back(n);
     bytes += (double)n;
     return p;
   }
-  std::vector<size_t> sizes;  // parallel to ptrs
   void release(void* p) {
     if (!p) return;
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
@@ -81,6 +114,7 @@ struct Arena {
   }
   ~Arena() {
     for (void* p : ptrs) (void)hipFree(p);
+    small.clear();
   }
   template <class T>
   T* up(const std::vector<T>& v, hipStream_t s) {
@@ -286,16 +320,21 @@ void validate(const double* points, int64_t n, const rss_kernel* k, double tol, 
     if (!std::isfinite(points[i])) fail(RSS_EINVAL, "non-finite point coordinate");
 }
 
-void box_of(const double* P, int64_t n, double x0, double y0, double s0, int d, std::vector<int>& out) {
-  const int nb = 1 << d;
+// Box coordinates at depth MAX_DEPTH: floor((p - corner) / side) clamped to the
+// grid.  The rounded quotient at depth d is 2^d times the one at depth 0
+// exactly (a power-of-two scaling), so the box coordinate at depth d is this
+// value shifted right by MAX_DEPTH - d.
+void grid_coords(const double* P, int64_t n, double x0, double y0, double s0, std::vector<int>& gx,
+                 std::vector<int>& gy) {
+  const int nb = 1 << MAX_DEPTH;
   const double s = s0 / (double)nb;
-  out.resize(n);
+  gx.resize(n);
+  gy.resize(n);
   for (int64_t i = 0; i < n; ++i) {
     long bx = (long)std::floor((P[2 * i] - x0) / s);
     long by = (long)std::floor((P[2 * i + 1] - y0) / s);
-    bx = std::min<long>(std::max<long>(bx, 0), nb - 1);
-    by = std::min<long>(std::max<long>(by, 0), nb - 1);
-    out[i] = (int)(by * nb + bx);
+    gx[i] = (int)std::min<long>(std::max<long>(bx, 0), nb - 1);
+    gy[i] = (int)std::min<long>(std::max<long>(by, 0), nb - 1);
   }
 }
 
@@ -355,16 +394,26 @@ void free_level(rss_ctx* h, LevelHost& L) {
   L.d_A = nullptr;
 }
 
-// temporary device buffers of one batched operation
+// temporary device buffers of one batched operation; clear() (after the
+// stream has drained) frees the large ones and keeps the slabs for reuse
 struct Scratch {
   std::vector<void*> ptrs;
+  std::vector<void*> slabs;
+  size_t si = 0, used = 0;  // current slab and offset in it
   void* alloc(size_t n) {
     if (n == 0) n = 16;
-    void* p = nullptr;
-    if (hipMalloc(&p, n) != hipSuccess) {
-      (void)hipGetLastError();
-      fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    if (n <= SMALL) {
+      n = (n + 255) & ~(size_t)255;
+      if (si < slabs.size() && used + n > SLAB) {
+        ++si;
+        used = 0;
+      }
+      if (si == slabs.size()) slabs.push_back(dev_alloc(SLAB));
+      void* p = (char*)slabs[si] + used;
+      used += n;
+      return p;
     }
+    void* p = dev_alloc(n);
     ptrs.push_back(p);
     return p;
   }
@@ -377,8 +426,15 @@ struct Scratch {
   void clear() {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
+    si = 0;
+    used = 0;
   }
-  ~Scratch() { clear(); }
+  void release_all() {
+    clear();
+    for (void* p : slabs) (void)hipFree(p);
+    slabs.clear();
+  }
+  ~Scratch() { release_all(); }
 };
 
 // Per-problem state while a batch is being factored.
@@ -419,13 +475,19 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   for (int p = 0; p < np; ++p) {
     rss_ctx* h = H[p];
     W[p].h = h;
+    // grid coordinates at depth MAX_DEPTH once; a coarser depth is a shift of them
+    std::vector<int> gx, gy;
+    grid_coords(h->h_points.data(), h->N, h->x0, h->y0, h->s0, gx, gy);
     int D = 0;
     for (;; ++D) {
       if (D > MAX_DEPTH) fail(RSS_EUNSUPPORTED, "tree deeper than 15 levels");
-      box_of(h->h_points.data(), h->N, h->x0, h->y0, h->s0, D, W[p].bo);
+      std::vector<int>& bo = W[p].bo;
+      bo.resize(h->N);
+      const int sh = MAX_DEPTH - D;
+      for (int64_t i = 0; i < h->N; ++i) bo[i] = ((gy[i] >> sh) << D) + (gx[i] >> sh);
       std::vector<int> cnt((size_t)1 << (2 * D), 0);
       int mx = 0;
-      for (int64_t i = 0; i < h->N; ++i) mx = std::max(mx, ++cnt[W[p].bo[i]]);
+      for (int64_t i = 0; i < h->N; ++i) mx = std::max(mx, ++cnt[bo[i]]);
       if (mx <= h->leaf) break;
     }
     h->D = D;
@@ -599,9 +661,9 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     double* pnorm = (double*)scr.alloc((size_t)Gmax * nmax * sizeof(double));
     double* pdot = (double*)scr.alloc((size_t)Gmax * nmax * 2 * sizeof(double));
     unsigned* bars = (unsigned*)scr.alloc((size_t)std::max(1, maxph) * sizeof(unsigned));
-    int* mrow = (int*)scr.alloc((size_t)std::max(1, maxph) * sizeof(int));
+    // row counts of the ID matrices, one slice per colour, read back once per height
+    int* mrow = (int*)scr.alloc((size_t)9 * std::max(1, maxph) * sizeof(int));
     GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
-    std::vector<std::vector<int>> mrows(9);
     const int chunks = (mmax + 63) / 64;
     for (int c = 0; c < 9; ++c) {
       Merged& G = M[c];
@@ -614,7 +676,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       ph.oX = scr.up(G.oX, s);
       ph.oZ = scr.up(G.oZ, s);
       ph.oI = scr.up(G.oI, s);
-      ph.mrow = mrow;
+      ph.mrow = mrow + (size_t)c * std::max(1, maxph);
       ph.W = (cx<R>*)Wd;
       ph.Wi = Wi;
       prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
@@ -629,11 +691,9 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(d_probs, ph, s); });
       launch_plan_schur<R>(d_probs, ph, desc, s);
       prof.run(RSS_K_SCHUR, s, [&] { launch_gemm<R>(desc, ph.nbox * 81, nmax, nmax, s); });
-      mrows[c].resize(G.box.size());
-      HIPCHK(hipMemcpyAsync(mrows[c].data(), mrow, G.box.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-      // mrow is reused by the next colour: wait for this copy before it is overwritten
-      HIPCHK(hipStreamSynchronize(s));
     }
+    std::vector<int> mrow_h((size_t)9 * std::max(1, maxph));
+    HIPCHK(hipMemcpyAsync(mrow_h.data(), mrow, mrow_h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
     // read back ranks and surviving ids of every active problem
     std::vector<std::vector<int>> curk(act.size()), ids(act.size());
@@ -659,7 +719,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     prof.collect(H[0]->stats.t_class_ms, H[0]->stats.n_class);
     for (int c = 0; c < 9; ++c)
       for (size_t i = 0; i < M[c].box.size(); ++i)
-        H[act[M[c].prob[i]]]->recs.back().m[M[c].box[i]] = mrows[c][i];
+        H[act[M[c].prob[i]]]->recs.back().m[M[c].box[i]] = mrow_h[(size_t)c * std::max(1, maxph) + i];
     scr.clear();
 
     // ledger, skeleton export, parent lists and transition descriptors

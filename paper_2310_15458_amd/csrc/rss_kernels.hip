@@ -9,11 +9,22 @@
 // disjoint blocks (Rem. r:t, Rem. r:nn) and need no synchronisation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rss_internal.h"
 
 namespace rss {
 
 constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
+
+// rows per lane loaded per round in the column loops of the column-pivoted QR
+// (one workgroup per box / several workgroups per box)
+#ifndef RSS_CPQR_CH
+#define RSS_CPQR_CH 8
+#endif
+#ifndef RSS_CPQR_MG_CH
+#define RSS_CPQR_MG_CH 16
+#endif
 
 __device__ __forceinline__ int nb_dx(int j) {  // j-th of the 8 neighbour offsets, ascending id
   const int t = j < 4 ? j : j + 1;
@@ -160,7 +171,7 @@ void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStr
 // largest trailing norm is <= tol * nu0.  Then T = R11^{-1} R12, rows and
 // columns reordered to ascending ids.  One workgroup per box.
 // ---------------------------------------------------------------------------
-template <class R, int NT, int RPL>
+template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, int nmax, int vcap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
@@ -197,18 +208,32 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
   int k = 0;
   const int jmax = m < n ? m : n;
   for (int j = 0; j < jmax; ++j) {
-    if (threadIdx.x == 0) {
+    if (wv == 0) {
+      // largest trailing norm, then the smallest global id within the tie window
       double mx = 0.0;
-      for (int c = j; c < n; ++c) mx = fmax(mx, nrm[c]);
+      for (int c = j + lane; c < n; c += 64) mx = fmax(mx, nrm[c]);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
       mx = sqrt(mx);
-      if (j == 0) sh_nu0 = mx;
+      if (j == 0 && lane == 0) sh_nu0 = mx;
+      const double nu0 = j == 0 ? mx : sh_nu0;
       int best = -1;
-      if (!(mx <= tol * sh_nu0)) {
+      if (!(mx <= tol * nu0)) {
         const double thr = (1.0 - TIE) * mx;
-        for (int c = j; c < n; ++c)
-          if (sqrt(nrm[c]) >= thr && (best < 0 || gid[perm[c]] < gid[perm[best]])) best = c;
+        unsigned long long key = ~0ull;
+        for (int c = j + lane; c < n; c += 64)
+          if (sqrt(nrm[c]) >= thr) {
+            const unsigned long long kc = ((unsigned long long)(unsigned)gid[perm[c]] << 32) | (unsigned)c;
+            key = kc < key ? kc : key;
+          }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const unsigned long long ko = __shfl_xor(key, o, 64);
+          key = ko < key ? ko : key;
+        }
+        best = (int)(unsigned)(key & 0xffffffffu);
       }
-      sh_p = best;
+      if (lane == 0) sh_p = best;
     }
     __syncthreads();
     const int p = sh_p;
@@ -253,57 +278,43 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
       __syncthreads();
       vp = vs;
     }
-    const bool cached = (m - j) <= 64 * RPL;
+    // CH rows per lane per round: a wave keeps CH loads in flight
+    constexpr int CH = RSS_CPQR_CH;
     for (int c = j + 1 + wv; c < n; c += NW) {
       cx<R>* col = C + (int64_t)c * m;
-      double dr = 0.0, di = 0.0, s2 = 0.0;
-      if (cached) {
-        // one read and one write of the column: it stays in registers between
-        // the dot product and the update
-        cx<R> reg[RPL];
+      double dr = 0.0, di = 0.0;
+      for (int base = j + lane; base < m; base += 64 * CH) {
+        cx<R> a[CH];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int i = j + lane + 64 * t;
-          if (i < m) {
-            const cx<R> a = col[i], v = vp[i - j];
-            reg[t] = a;
-            dr += (double)v.x * a.x + (double)v.y * a.y;
-            di += (double)v.x * a.y - (double)v.y * a.x;
+        for (int t = 0; t < CH; ++t)
+          if (base + 64 * t < m) a[t] = col[base + 64 * t];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+          if (base + 64 * t < m) {
+            const cx<R> v = vp[base + 64 * t - j];
+            dr += (double)v.x * a[t].x + (double)v.y * a[t].y;
+            di += (double)v.x * a[t].y - (double)v.y * a[t].x;
           }
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        const double sr = beta * dr, si = beta * di;
-        // re-read v from memory below instead of keeping a second register copy
-        asm volatile("" ::: "memory");
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double sr = beta * dr, si = beta * di;
+      double s2 = 0.0;
+      for (int base = j + lane; base < m; base += 64 * CH) {
+        cx<R> a[CH];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int i = j + lane + 64 * t;
+        for (int t = 0; t < CH; ++t)
+          if (base + 64 * t < m) a[t] = col[base + 64 * t];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+          const int i = base + 64 * t;
           if (i < m) {
             const cx<R> v = vp[i - j];
-            cx<R> a = reg[t];
-            a.x -= (R)((double)v.x * sr - (double)v.y * si);
-            a.y -= (R)((double)v.x * si + (double)v.y * sr);
-            col[i] = a;
-            if (i > j) s2 += abs2d(a);
+            a[t].x -= (R)((double)v.x * sr - (double)v.y * si);
+            a[t].y -= (R)((double)v.x * si + (double)v.y * sr);
+            col[i] = a[t];
+            if (i > j) s2 += abs2d(a[t]);
           }
-        }
-      } else {
-        for (int i = j + lane; i < m; i += 64) {
-          const cx<R> a = col[i], v = vp[i - j];
-          dr += (double)v.x * a.x + (double)v.y * a.y;
-          di += (double)v.x * a.y - (double)v.y * a.x;
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        const double sr = beta * dr, si = beta * di;
-        for (int i = j + lane; i < m; i += 64) {
-          const cx<R> v = vp[i - j];
-          cx<R> a = col[i];
-          a.x -= (R)((double)v.x * sr - (double)v.y * si);
-          a.y -= (R)((double)v.x * si + (double)v.y * sr);
-          col[i] = a;
-          if (i > j) s2 += abs2d(a);
         }
       }
       s2 = wave_sum(s2);
@@ -358,15 +369,12 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
 template <class R>
 void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  // 256 threads: one wave per SIMD, so each lane can keep RPL rows of a
-  // column in registers between the dot product and the update
-  constexpr int NT = 256;
+  constexpr int NT = 512;
   const size_t head = ((size_t)nmax * 8 + (NT / 64) * 8 + (size_t)nmax * 8 + 15) & ~(size_t)15;
   // the Householder vector is staged in LDS when it fits in 48 KiB
   const int vcap = (int)((48 * 1024) / sizeof(cx<R>));
   const size_t shm = head + (size_t)(mmax < vcap ? mmax : vcap) * sizeof(cx<R>);
-  constexpr int RPL = sizeof(R) == 8 ? 24 : 36;  // the most rows per lane without register spills
-  hipLaunchKernelGGL((k_cpqr<R, NT, RPL>), dim3(ph.nbox), dim3(NT), shm, s, probs, ph, nmax, vcap);
+  hipLaunchKernelGGL((k_cpqr<R, NT>), dim3(ph.nbox), dim3(NT), shm, s, probs, ph, nmax, vcap);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,6 +390,15 @@ void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, h
 // ---------------------------------------------------------------------------
 // bounded wait: ~seconds, long enough for concurrent work on other streams to drain
 constexpr unsigned MG_SPIN_LIMIT = 1u << 24;
+
+// LDS of k_cpqr_mg before the staged Householder vector: three double and two
+// int arrays of nmax entries, 16-byte aligned
+__host__ __device__ constexpr size_t mg_head_bytes(int nmax) {
+  return ((size_t)nmax * (8 * 3 + 8) + 15) & ~(size_t)15;
+}
+// the staged Householder vector takes up to 48 KiB
+template <class R>
+constexpr int mg_vcap() { return (int)((48 * 1024) / sizeof(cx<R>)); }
 
 __device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* err) {
   __syncthreads();
@@ -403,8 +420,9 @@ __device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* 
 
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> ph, int G, int nmax,
-                                                double* pnorm, double* pdot, unsigned* bars,
-                                                int* err) {
+                                                int vcap, double* pnorm, double* pdot,
+                                                unsigned* bars, int* err) {
+  constexpr int CH = RSS_CPQR_MG_CH;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
   double* nrm = reinterpret_cast<double*>(smem_raw);          // nmax
@@ -412,6 +430,8 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
   double* wim = wre + nmax;                                     // nmax
   int* perm = reinterpret_cast<int*>(wim + nmax);               // nmax (position -> column)
   int* rankv = perm + nmax;                                     // nmax
+  // this workgroup's rows of the current Householder vector (when they fit)
+  cx<R>* vsh = reinterpret_cast<cx<R>*>(smem_raw + mg_head_bytes(nmax));
   __shared__ int sh_p;
   __shared__ double sh_nu0;
 
@@ -453,26 +473,42 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
       nrm[c] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wv == 0) {
+      // largest trailing norm, then the smallest global id within the tie window
       double mx = 0.0;
-      for (int c = j; c < n; ++c) mx = fmax(mx, nrm[c]);
+      for (int c = j + lane; c < n; c += 64) mx = fmax(mx, nrm[c]);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
       mx = sqrt(mx);
-      if (j == 0) sh_nu0 = mx;
+      if (j == 0 && lane == 0) sh_nu0 = mx;
+      const double nu0 = j == 0 ? mx : sh_nu0;
       int best = -1;
-      if (!(mx <= tol * sh_nu0)) {
+      if (!(mx <= tol * nu0)) {
         const double thr = (1.0 - TIE) * mx;
-        for (int c = j; c < n; ++c)
-          if (sqrt(nrm[c]) >= thr && (best < 0 || gid[perm[c]] < gid[perm[best]])) best = c;
+        unsigned long long key = ~0ull;
+        for (int c = j + lane; c < n; c += 64)
+          if (sqrt(nrm[c]) >= thr) {
+            const unsigned long long kc = ((unsigned long long)(unsigned)gid[perm[c]] << 32) | (unsigned)c;
+            key = kc < key ? kc : key;
+          }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const unsigned long long ko = __shfl_xor(key, o, 64);
+          key = ko < key ? ko : key;
+        }
+        best = (int)(unsigned)(key & 0xffffffffu);
       }
-      if (best >= 0 && best != j) {
-        const int t = perm[j];
-        perm[j] = perm[best];
-        perm[best] = t;
-        const double u = nrm[j];
-        nrm[j] = nrm[best];
-        nrm[best] = u;
+      if (lane == 0) {
+        if (best >= 0 && best != j) {
+          const int t = perm[j];
+          perm[j] = perm[best];
+          perm[best] = t;
+          const double u = nrm[j];
+          nrm[j] = nrm[best];
+          nrm[best] = u;
+        }
+        sh_p = best;
       }
-      sh_p = best;
     }
     __syncthreads();
     if (sh_p < 0) break;
@@ -490,17 +526,36 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
     const double vv = v0r * v0r + v0i * v0i + t;
     const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
     const int i0 = max(r0, j);
-    // partial dot products v^H C[:, q] over this workgroup's rows
+    // v below the diagonal is the pivot column itself: stage this workgroup's rows
+    const bool vl = r1 - i0 <= vcap;
+    // row i of v is vsrc[i - i0]: both bases point inside their buffers
+    const cx<R>* vsrc = vl ? vsh : cj + i0;
+    if (vl) {
+      for (int i = i0 + threadIdx.x; i < r1; i += NT) vsh[i - i0] = cj[i];
+      __syncthreads();
+    }
+    // partial dot products v^H C[:, q] over this workgroup's rows, CH rows per
+    // lane per round so that a wave keeps CH loads in flight
     for (int c = j + 1 + wv; c < n; c += NW) {
       const int q = perm[c];
       const cx<R>* col = C + (int64_t)q * m;
       double dr = 0.0, di = 0.0;
-      for (int i = i0 + lane; i < r1; i += 64) {
-        const cx<R> a = col[i];
-        const double vr = (i == j) ? v0r : (double)cj[i].x;
-        const double vi = (i == j) ? v0i : (double)cj[i].y;
-        dr += vr * a.x + vi * a.y;
-        di += vr * a.y - vi * a.x;
+      for (int base = i0 + lane; base < r1; base += 64 * CH) {
+        cx<R> a[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+          if (base + 64 * t < r1) a[t] = col[base + 64 * t];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+          const int i = base + 64 * t;
+          if (i < r1) {
+            const cx<R> vv = vsrc[i - i0];
+            const double vr = (i == j) ? v0r : (double)vv.x;
+            const double vi = (i == j) ? v0i : (double)vv.y;
+            dr += vr * a[t].x + vi * a[t].y;
+            di += vr * a[t].y - vi * a[t].x;
+          }
+        }
       }
       dr = wave_sum(dr);
       di = wave_sum(di);
@@ -527,14 +582,24 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
       cx<R>* col = C + (int64_t)q * m;
       const double sr = wre[c], si = wim[c];
       double s2 = 0.0;
-      for (int i = i0 + lane; i < r1; i += 64) {
-        const double vr = (i == j) ? v0r : (double)cj[i].x;
-        const double vi = (i == j) ? v0i : (double)cj[i].y;
-        cx<R> a = col[i];
-        a.x -= (R)(vr * sr - vi * si);
-        a.y -= (R)(vr * si + vi * sr);
-        col[i] = a;
-        if (i > j) s2 += abs2d(a);
+      for (int base = i0 + lane; base < r1; base += 64 * CH) {
+        cx<R> a[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+          if (base + 64 * t < r1) a[t] = col[base + 64 * t];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+          const int i = base + 64 * t;
+          if (i < r1) {
+            const cx<R> vv = vsrc[i - i0];
+            const double vr = (i == j) ? v0r : (double)vv.x;
+            const double vi = (i == j) ? v0i : (double)vv.y;
+            a[t].x -= (R)(vr * sr - vi * si);
+            a[t].y -= (R)(vr * si + vi * sr);
+            col[i] = a[t];
+            if (i > j) s2 += abs2d(a[t]);
+          }
+        }
       }
       s2 = wave_sum(s2);
       if (lane == 0) pn[(size_t)g * nmax + q] = s2;
@@ -601,7 +666,7 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per = 0;
-    const size_t shm = (size_t)nmax * (8 * 3 + 8) + 64;
+    const size_t shm = mg_head_bytes(nmax) + (size_t)mg_vcap<R>() * sizeof(cx<R>);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cpqr_mg<R, NT>, NT, shm);
     cap = cus * (per > 0 ? 1 : 0);  // one workgroup per compute unit: always co-resident
   }
@@ -616,9 +681,10 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
   constexpr int NT = 512;
   if (ph.nbox == 0 || G < 2) return false;
   hipLaunchKernelGGL(k_fill_u32, dim3((ph.nbox + 255) / 256), dim3(256), 0, s, bars, ph.nbox);
-  const size_t shm = (size_t)nmax * (8 * 3 + 8) + 64;
+  const int vcap = std::min(mg_vcap<R>(), (mmax + G - 1) / G);
+  const size_t shm = mg_head_bytes(nmax) + (size_t)vcap * sizeof(cx<R>);
   hipLaunchKernelGGL((k_cpqr_mg<R, NT>), dim3(ph.nbox * G), dim3(NT), shm, s, probs, ph, G, nmax,
-                     pnorm, pdot, bars, err);
+                     vcap, pnorm, pdot, bars, err);
   return true;
 }
 
@@ -719,7 +785,8 @@ void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
 // (the LU of eq. e:step, kept as an explicit inverse).  One workgroup per box.
 // ---------------------------------------------------------------------------
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> ph, int* errflag) {
+__global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> ph, int* errflag,
+                                                size_t lds_off, size_t lds_cap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double rv[NT];
   __shared__ int ri[NT];
@@ -730,8 +797,12 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
   if (r == 0) return;
   cx<R>* colk = reinterpret_cast<cx<R>*>(smem_raw);
   int* piv = reinterpret_cast<int*>(colk + r);
-  cx<R>* A = rec.F + rec.oXi[b];
+  cx<R>* Aout = rec.F + rec.oXi[b];
   const cx<R>* X = ph.W + ph.oX[slot];
+  // work in LDS when the r x r block fits behind the column and pivot arrays
+  cx<R>* Alds = reinterpret_cast<cx<R>*>(smem_raw + lds_off);
+  const bool in_lds = (size_t)r * r <= lds_cap;
+  cx<R>* A = in_lds ? Alds : Aout;
   for (int e = threadIdx.x; e < r * r; e += NT) A[e] = X[e];
   __syncthreads();
   for (int kk = 0; kk < r; ++kk) {
@@ -803,14 +874,23 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
       }
     __syncthreads();
   }
+  if (in_lds)
+    for (int e = threadIdx.x; e < r * r; e += NT) Aout[e] = A[e];
 }
 
 template <class R>
 void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s) {
   if (ph.nbox == 0) return;
-  const size_t shm = (size_t)nmax * (sizeof(cx<R>) + sizeof(int)) + 16;
-  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, errflag);
+  const size_t head = ((size_t)nmax * (sizeof(cx<R>) + sizeof(int)) + 15) & ~(size_t)15;
+  // the block itself in LDS up to 96 KiB (r <= 78 in c128, r <= 110 in c64), within
+  // 150 KiB of dynamic LDS in total
+  const size_t room = head < (size_t)(150 * 1024) ? (size_t)(150 * 1024) - head : 0;
+  const size_t cap = std::min({(size_t)nmax * nmax, (size_t)(96 * 1024) / sizeof(cx<R>),
+                               room / sizeof(cx<R>)});
+  const size_t shm = head + cap * sizeof(cx<R>);
+  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, errflag, head,
+                     cap);
 }
 
 // ---------------------------------------------------------------------------

@@ -248,7 +248,7 @@ struct Prof {
 
 struct DepthRecords {
   int d = 0, nb = 0;
-  int kmax = 0, rmax = 0, snmax = 0;
+  int kmax = 0, rmax = 0, qmax = 0, snmax = 0;
   int* d_k = nullptr;
   int* d_r = nullptr;
   int* d_nN = nullptr;
@@ -716,6 +716,14 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         HIPCHK(hipMemcpyAsync(ids[a].data(), cur.d_idx, ids[a].size() * sizeof(int), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    for (size_t a = 0; a < act.size(); ++a) {
+      // the solve sizes its LDS panels by the ranks the level actually has
+      DepthRecords& dr = H[act[a]]->recs.back();
+      dr.kmax = dr.rmax = dr.qmax = 1;
+      for (int v : dr.k) dr.kmax = std::max(dr.kmax, v);
+      for (int v : dr.r) dr.rmax = std::max(dr.rmax, v);
+      for (size_t b = 0; b < dr.k.size(); ++b) dr.qmax = std::max(dr.qmax, dr.k[b] + dr.nN[b]);
+    }
     prof.collect(H[0]->stats.t_class_ms, H[0]->stats.n_class);
     for (int c = 0; c < 9; ++c)
       for (size_t i = 0; i < M[c].box.size(); ++i)
@@ -959,7 +967,7 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
   struct HPhase {
     SolveProb<R>* d_sp = nullptr;
     Phase<R> ph[9];
-    int kmax = 0, rmax = 0;
+    int kmax = 0, rmax = 0, qmax = 0;
   };
   std::vector<HPhase> HP(tmax + 1);
   for (int t = 0; t <= tmax; ++t) {
@@ -976,6 +984,7 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
         sp.push_back(q);
         HP[t].kmax = std::max(HP[t].kmax, H[p]->recs[t].kmax);
         HP[t].rmax = std::max(HP[t].rmax, H[p]->recs[t].rmax);
+        HP[t].qmax = std::max(HP[t].qmax, H[p]->recs[t].qmax);
       }
     HP[t].d_sp = scr.up(sp, s);
     for (int c = 0; c < 9; ++c) {
@@ -1005,9 +1014,19 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
       }
     }
   }
+  size_t wel = 1;
+  for (int t = 0; t <= tmax; ++t) {
+    if (solve_group<R>(HP[t].kmax, HP[t].rmax, nrhs_max) == 0)
+      fail(RSS_EUNSUPPORTED, "ranks too large for the solve's LDS panels");
+    for (int c = 0; c < 9; ++c)
+      if (HP[t].ph[c].nbox)
+        wel = std::max(wel, solve_work_elems<R>(HP[t].ph[c].nbox, HP[t].rmax, HP[t].qmax, nrhs_max));
+  }
+  // partial products between the two launches of each sweep step
+  cx<R>* Wk = (cx<R>*)scr.alloc(wel * sizeof(cx<R>));
   for (int t = 0; t <= tmax; ++t)
     for (int c = 0; c < 9; ++c)
-      launch_solve_fwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, s);
+      launch_solve_fwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax, Wk, s);
   // roots
   {
     std::vector<RootApply<R>> ra;
@@ -1034,7 +1053,7 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
   }
   for (int t = tmax; t >= 0; --t)
     for (int c = 8; c >= 0; --c)
-      launch_solve_bwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, s);
+      launch_solve_bwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax, Wk, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));  // scratch descriptors are freed on return
 }

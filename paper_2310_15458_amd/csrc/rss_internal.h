@@ -138,6 +138,10 @@ void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, h
 // multi-workgroup ID for phases with few boxes: groups per box (1 = use launch_cpqr)
 template <class R>
 int cpqr_mg_groups(int nbox, int nmax, int mmax);
+// right-hand sides per solve workgroup for the given largest skeleton and
+// redundant counts of a level (0: the level's panels do not fit in LDS)
+template <class R>
+int solve_group(int kmax, int rmax, int nrhs);
 template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
                     double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s);
@@ -159,12 +163,16 @@ void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* list
                            int max_c, const Prob<R>* child, hipStream_t s);
 template <class R>
 void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errflag, hipStream_t s);
+// solve sweeps of one colour phase; W: scratch of solve_work_elems entries
+// (qmax: largest k + |N| of the phase's level)
 template <class R>
 void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      hipStream_t s);
+                      int qmax, cx<R>* W, hipStream_t s);
 template <class R>
 void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      hipStream_t s);
+                      int qmax, cx<R>* W, hipStream_t s);
+template <class R>
+size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs);
 // batched root apply: z[ids] <- Ainv z[ids] per problem (ws: 2 n nrhs entries per problem)
 template <class R>
 struct RootApply {

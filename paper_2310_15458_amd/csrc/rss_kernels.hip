@@ -23,7 +23,7 @@ constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
 #define RSS_CPQR_CH 8
 #endif
 #ifndef RSS_CPQR_MG_CH
-#define RSS_CPQR_MG_CH 16
+#define RSS_CPQR_MG_CH 8
 #endif
 
 __device__ __forceinline__ int nb_dx(int j) {  // j-th of the 8 neighbour offsets, ascending id
@@ -1334,166 +1334,376 @@ void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errfla
 }
 
 // ---------------------------------------------------------------------------
-// solve sweeps (Sec. 2.6), up to 8 right-hand-side columns per workgroup
+// solve sweeps (Sec. 2.6)
 //  forward : z_R -= T^* z_S;  w = X_RR^{-1} z_R;  z_{S,N} -= [X_SR; X_NR] w
 //  backward: x_R = X_RR^{-1} z_R - Y z_{S,N};  z_S -= T x_R;  z_R = x_R
+// One workgroup per (box, group of up to SNC right-hand sides).  The sweeps
+// stream small factor blocks and are bound by memory latency: each product
+// gives every thread a task (row a, slice p of the summation index) that
+// loads SU entries of its row at once, coalesced across the lanes of a wave,
+// and uses each for all columns of the group (kept in registers).  Products
+// with few rows split the summation over P = 256 / rows slices and reduce the
+// slices in a fixed order through LDS.  Right-hand-side panels sit in LDS,
+// row-major with stride sld = group + 1.
 // ---------------------------------------------------------------------------
+constexpr int SNC = 16;  // most right-hand sides per workgroup (registers per thread)
+constexpr int SU = 16;   // factor entries loaded per thread per round
+constexpr size_t SOLVE_LDS = 96 * 1024;
+constexpr int SRED = 256;  // rows of the slice-reduction buffer
+
+// right-hand sides per workgroup so that both sweeps' LDS fits the budget
+// (0: not even one fits)
 template <class R>
-__global__ __launch_bounds__(256) void k_solve_fwd(const SolveProb<R>* sp, Phase<R> ph, int kmax,
-                                                   int rmax, int SNC) {
+int solve_group(int kmax, int rmax, int nrhs) {
+  const size_t rows = (size_t)std::max(kmax + 2 * rmax, 2 * rmax + 16) + SRED;
+  for (int g = std::min(SNC, std::max(nrhs, 1)); g >= 1; --g)
+    if (rows * (g + 1) * sizeof(cx<R>) <= SOLVE_LDS) return g;
+  return 0;
+}
+
+template <class R>
+__device__ __forceinline__ void zero_acc(cx<R> (&acc)[SNC]) {
+#pragma unroll
+  for (int c = 0; c < SNC; ++c) acc[c] = czero<R>();
+}
+
+// acc[c] += sum op(A)(a, s) Bz[(s - s_lo) sld + c] over the slice p of P of
+// s in [s_lo, s_hi) (rounds of SU consecutive s, dealt round-robin);
+// op(A)(a, s) = A[a + s lda], or conj(A[s + a lda]) when CT
+template <class R, bool CT>
+__device__ __forceinline__ void mm_slice(const cx<R>* __restrict__ A, int64_t lda, int a, int s_lo,
+                                         int s_hi, int p, int P, const cx<R>* Bz, int sld, int nc,
+                                         cx<R> (&acc)[SNC]) {
+  for (int s0 = s_lo + p * SU; s0 < s_hi; s0 += P * SU) {
+    cx<R> x[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int s = s0 + u;
+      if (s < s_hi) x[u] = CT ? conj(A[s + (int64_t)a * lda]) : A[a + (int64_t)s * lda];
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      if (s0 + u < s_hi) {
+        const cx<R>* b = Bz + (s0 + u - s_lo) * sld;
+#pragma unroll
+        for (int c = 0; c < SNC; ++c)
+          if (c < nc) fma_(acc[c], x[u], b[c]);
+      }
+    }
+  }
+}
+
+// row a of op(A) Bz over s in [s_lo, s_hi) for every a < M, handed to
+// emit(a, v) with v[c] for c < nc exactly once per row.  All threads of the
+// workgroup call it (it synchronizes when M <= 128).  red: SRED * sld entries.
+template <class R, bool CT, class Emit>
+__device__ __forceinline__ void blk_mm(const cx<R>* __restrict__ A, int64_t lda, int M, int s_lo,
+                                       int s_hi, const cx<R>* Bz, int sld, int nc, cx<R>* red,
+                                       Emit emit) {
+  if (M <= 0) return;
+  const int Mb = M < 256 ? M : 256;
+  const int P = 256 / Mb;
+  const int t = threadIdx.x;
+  cx<R> acc[SNC];
+  for (int m0 = 0; m0 < M; m0 += Mb) {
+    const int i = t % Mb, p = t / Mb, a = m0 + i;
+    const bool act = p < P && a < M;
+    zero_acc(acc);
+    if (act) mm_slice<R, CT>(A, lda, a, s_lo, s_hi, p, P, Bz, sld, nc, acc);
+    if (P == 1) {
+      if (act) emit(a, acc);
+    } else {
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < SNC; ++c)
+          if (c < nc) red[(p * Mb + i) * sld + c] = acc[c];
+      }
+      __syncthreads();
+      // slices summed in a fixed order into the rows of slice 0
+      for (int e = t; e < Mb * nc; e += 256) {
+        const int ii = e % Mb, c = e / Mb;
+        cx<R> v = red[ii * sld + c];
+        for (int q = 1; q < P; ++q) v = v + red[(q * Mb + ii) * sld + c];
+        red[ii * sld + c] = v;
+      }
+      __syncthreads();
+      if (t < Mb) {
+#pragma unroll
+        for (int c = 0; c < SNC; ++c) acc[c] = c < nc ? red[t * sld + c] : czero<R>();
+        emit(m0 + t, acc);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// z[g + (c0 + c) ldz] -= v[c] for c < nc: every load before any store
+template <class R>
+__device__ __forceinline__ void sub_row(cx<R>* z, int64_t ldz, int64_t g, int c0, int nc,
+                                        const cx<R> (&v)[SNC]) {
+  cx<R> o[SNC];
+  cx<R>* p = z + g + (int64_t)c0 * ldz;
+#pragma unroll
+  for (int c = 0; c < SNC; ++c)
+    if (c < nc) o[c] = p[c * ldz];
+#pragma unroll
+  for (int c = 0; c < SNC; ++c)
+    if (c < nc) p[c * ldz] = o[c] - v[c];
+}
+
+// LDS panel P[i * sld + c] = z[g(i) + (c0 + c) ldz] for i < n, c < nc, eight
+// loads in flight per thread
+template <class R, class Idx>
+__device__ __forceinline__ void gather(cx<R>* P, int sld, const cx<R>* z, int64_t ldz, int c0, int n,
+                                       int nc, Idx g) {
+  constexpr int GU = 8;
+  const int tot = n * nc;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * GU) {
+    cx<R> v[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int e = e0 + 256 * u;
+      if (e < tot) v[u] = z[g(e % n) + (int64_t)(c0 + e / n) * ldz];
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int e = e0 + 256 * u;
+      if (e < tot) P[(e % n) * sld + e / n] = v[u];
+    }
+  }
+}
+
+// Slices per box for the two wide products of a phase ([X_SR; X_NR] w by
+// rows, Y z_{S,N} by columns): enough workgroups for the whole chip when a
+// colour holds few boxes.
+int solve_slices(int nbox, int qmax) {
+  int S = (512 + nbox - 1) / std::max(nbox, 1);
+  S = std::min(S, std::max(1, (qmax + 47) / 48));
+  return std::max(S, 1);
+}
+
+template <class R>
+size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs) {
+  return (size_t)nbox * solve_slices(nbox, qmax) * rmax * nrhs;
+}
+
+// forward, part 1 (one workgroup per box and column group):
+// z_R -= T^* z_S;  w = X_RR^{-1} z_R -> W[slot];  z_R written back
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_fwd_a(const SolveProb<R>* sp, Phase<R> ph, int kmax,
+                                                     int rmax, int ncg, cx<R>* W, int ldw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sld = ncg + 1;
   cx<R>* zS = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* zR = zS + (int64_t)kmax * SNC;
-  cx<R>* w = zR + (int64_t)rmax * SNC;
-  const int b = ph.box[blockIdx.x];
-  const SolveProb<R> pr = sp[ph.prob[blockIdx.x]];
+  cx<R>* zR = zS + (int64_t)kmax * sld;
+  cx<R>* red = zR + (int64_t)rmax * sld;
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
+  const int k = rec.k[b], r = rec.r[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * ncg;
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(ncg, pr.nrhs - c0);
+  const int* gS = rec.G + rec.oS[b];
+  const int* gR = rec.G + rec.oR[b];
+  const cx<R>* T = rec.F + rec.oT[b];
+  const cx<R>* Xi = rec.F + rec.oXi[b];
+  gather(zS, sld, z, ldz, c0, k, nc, [&](int i) { return gS[i]; });
+  gather(zR, sld, z, ldz, c0, r, nc, [&](int i) { return gR[i]; });
+  __syncthreads();
+  blk_mm<R, true>(T, k, r, 0, k, zS, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) zR[a * sld + c] = zR[a * sld + c] - v[c];
+  });
+  __syncthreads();
+  cx<R>* Wb = W + (int64_t)slot * rmax * ldw + c0;
+  blk_mm<R, false>(Xi, r, r, 0, r, zR, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) Wb[(int64_t)a * ldw + c] = v[c];
+  });
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = zR[a * sld + c];
+  }
+}
+
+// forward, part 2 (S workgroups per box, each a slice of rows):
+// z_{S,N} -= [X_SR; X_NR] w
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_fwd_b(const SolveProb<R>* sp, Phase<R> ph, int rmax,
+                                                     int ncg, int S, const cx<R>* W, int ldw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sld = ncg + 1;
+  cx<R>* w = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* red = w + (int64_t)rmax * sld;
+  const int slot = blockIdx.x / S, j = blockIdx.x % S, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
   const Records<R>& rec = pr.rec;
   cx<R>* z = pr.z;
   const int64_t ldz = pr.ldz;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
   if (r == 0) return;
-  const int c0 = blockIdx.y * SNC;
+  const int c0 = blockIdx.y * ncg;
   if (c0 >= pr.nrhs) return;
-  const int nc = min(SNC, pr.nrhs - c0);
+  const int nc = min(ncg, pr.nrhs - c0);
+  const int q = k + nN, qs = (q + S - 1) / S, a_lo = j * qs, a_hi = min(q, a_lo + qs);
+  if (a_lo >= a_hi) return;
   const int* gS = rec.G + rec.oS[b];
-  const int* gR = rec.G + rec.oR[b];
   const int* gN = rec.G + rec.oN[b];
-  const cx<R>* T = rec.F + rec.oT[b];
-  const cx<R>* Xi = rec.F + rec.oXi[b];
   const cx<R>* XS = rec.F + rec.oXSNR[b];
-  for (int e = threadIdx.x; e < k * nc; e += 256) {
-    const int a = e % k, c = e / k;
-    zS[a + k * c] = z[gS[a] + (int64_t)(c0 + c) * ldz];
-  }
+  const cx<R>* Wb = W + (int64_t)slot * rmax * ldw + c0;
   for (int e = threadIdx.x; e < r * nc; e += 256) {
     const int a = e % r, c = e / r;
-    zR[a + r * c] = z[gR[a] + (int64_t)(c0 + c) * ldz];
+    w[a * sld + c] = Wb[(int64_t)a * ldw + c];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int a = e % r, c = e / r;
-    cx<R> v = zR[a + r * c];
-    for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)a * k], zS[s + k * c]);
-    w[a + r * c] = v;  // temporarily the sparsified z_R
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int a = e % r, c = e / r;
-    zR[a + r * c] = w[a + r * c];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int a = e % r, c = e / r;
-    cx<R> v = czero<R>();
-    for (int s = 0; s < r; ++s) fma_(v, Xi[a + (int64_t)s * r], zR[s + r * c]);
-    w[a + r * c] = v;
-  }
-  __syncthreads();
-  const int q = k + nN;
-  for (int e = threadIdx.x; e < q * nc; e += 256) {
-    const int a = e % q, c = e / q;
-    cx<R> v = czero<R>();
-    for (int s = 0; s < r; ++s) fma_(v, XS[a + (int64_t)s * q], w[s + r * c]);
-    const int g = a < k ? gS[a] : gN[a - k];
-    cx<R>* p = z + g + (int64_t)(c0 + c) * ldz;
-    *p = *p - v;
-  }
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int a = e % r, c = e / r;
-    z[gR[a] + (int64_t)(c0 + c) * ldz] = zR[a + r * c];
-  }
+  blk_mm<R, false>(XS + a_lo, q, a_hi - a_lo, 0, r, w, sld, nc, red,
+                   [&](int a, const cx<R>(&v)[SNC]) {
+                     const int row = a_lo + a;
+                     sub_row(z, ldz, row < k ? gS[row] : gN[row - k], c0, nc, v);
+                   });
 }
 
 template <class R>
 void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      hipStream_t s) {
-  if (ph.nbox == 0) return;
-  // right-hand-side columns per workgroup: as many as fit in 64 KiB of LDS (<= 8)
-  const size_t per = (size_t)(kmax + 2 * rmax) * sizeof(cx<R>);
-  int ncw = (int)((64 * 1024) / (per > 0 ? per : 1));
-  ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
-  ncw = ncw > nrhs ? nrhs : ncw;
-  hipLaunchKernelGGL(k_solve_fwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
-                     sp, ph, kmax, rmax, ncw);
+                      int qmax, cx<R>* W, hipStream_t s) {
+  const int ncg = solve_group<R>(kmax, rmax, nrhs);
+  if (ph.nbox == 0 || ncg == 0) return;  // ncg == 0 is rejected by the caller
+  const int S = solve_slices(ph.nbox, qmax);
+  const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
+  const dim3 groups((nrhs + ncg - 1) / ncg);
+  hipLaunchKernelGGL(k_solve_fwd_a<R>, dim3(ph.nbox, groups.x), dim3(256),
+                     (size_t)(kmax + rmax + SRED) * row, s, sp, ph, kmax, rmax, ncg, W, nrhs);
+  hipLaunchKernelGGL(k_solve_fwd_b<R>, dim3(ph.nbox * S, groups.x), dim3(256),
+                     (size_t)(rmax + SRED) * row, s, sp, ph, rmax, ncg, S, (const cx<R>*)W, nrhs);
 }
 
+// backward, part 1 (S workgroups per box, each a slice of the columns of Y):
+// W[slot, j] = Y[:, slice j] z_{S,N}[slice j]
 template <class R>
-__global__ __launch_bounds__(256) void k_solve_bwd(const SolveProb<R>* sp, Phase<R> ph, int rmax,
-                                                   int chunk, int SNC) {
+__global__ __launch_bounds__(256) void k_solve_bwd_a(const SolveProb<R>* sp, Phase<R> ph, int rmax,
+                                                     int chunk, int ncg, int S, cx<R>* W, int ldw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* zR = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* xR = zR + (int64_t)rmax * SNC;
-  cx<R>* zq = xR + (int64_t)rmax * SNC;  // chunk x SNC
-  const int b = ph.box[blockIdx.x];
-  const SolveProb<R> pr = sp[ph.prob[blockIdx.x]];
+  const int sld = ncg + 1;
+  cx<R>* xp = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* red = xp + (int64_t)rmax * sld;
+  cx<R>* zq = red + (int64_t)SRED * sld;  // chunk rows of z_{S,N}
+  const int slot = blockIdx.x / S, j = blockIdx.x % S, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
   const Records<R>& rec = pr.rec;
   cx<R>* z = pr.z;
   const int64_t ldz = pr.ldz;
   const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
   if (r == 0) return;
-  const int c0 = blockIdx.y * SNC;
+  const int c0 = blockIdx.y * ncg;
   if (c0 >= pr.nrhs) return;
-  const int nc = min(SNC, pr.nrhs - c0);
+  const int nc = min(ncg, pr.nrhs - c0);
+  const int q = k + nN, qs = (q + S - 1) / S, s_lo = min(q, j * qs), s_hi = min(q, s_lo + qs);
+  const int* gS = rec.G + rec.oS[b];
+  const int* gN = rec.G + rec.oN[b];
+  const cx<R>* Y = rec.F + rec.oY[b];
+  for (int e = threadIdx.x; e < r * sld; e += 256) xp[e] = czero<R>();
+  for (int q0 = s_lo; q0 < s_hi; q0 += chunk) {
+    const int nq = min(chunk, s_hi - q0);
+    __syncthreads();
+    gather(zq, sld, z, ldz, c0, nq, nc,
+           [&](int i) { return (q0 + i) < k ? gS[q0 + i] : gN[q0 + i - k]; });
+    __syncthreads();
+    blk_mm<R, false>(Y, r, r, q0, q0 + nq, zq, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+      for (int c = 0; c < SNC; ++c)
+        if (c < nc) xp[a * sld + c] = xp[a * sld + c] + v[c];
+    });
+  }
+  __syncthreads();
+  cx<R>* Wb = W + ((int64_t)slot * S + j) * rmax * ldw + c0;
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    Wb[(int64_t)a * ldw + c] = xp[a * sld + c];
+  }
+}
+
+// backward, part 2 (one workgroup per box and column group):
+// x_R = X_RR^{-1} z_R - sum_j W[slot, j];  z_S -= T x_R;  z_R = x_R
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_bwd_b(const SolveProb<R>* sp, Phase<R> ph, int rmax,
+                                                     int ncg, int S, const cx<R>* W, int ldw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sld = ncg + 1;
+  cx<R>* zR = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* xR = zR + (int64_t)rmax * sld;
+  cx<R>* red = xR + (int64_t)rmax * sld;
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
+  const int k = rec.k[b], r = rec.r[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * ncg;
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(ncg, pr.nrhs - c0);
   const int* gS = rec.G + rec.oS[b];
   const int* gR = rec.G + rec.oR[b];
-  const int* gN = rec.G + rec.oN[b];
   const cx<R>* T = rec.F + rec.oT[b];
   const cx<R>* Xi = rec.F + rec.oXi[b];
-  const cx<R>* Y = rec.F + rec.oY[b];
-  const int q = k + nN;
+  gather(zR, sld, z, ldz, c0, r, nc, [&](int i) { return gR[i]; });
+  __syncthreads();
+  blk_mm<R, false>(Xi, r, r, 0, r, zR, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) xR[a * sld + c] = v[c];
+  });
+  __syncthreads();
+  const cx<R>* Wb = W + (int64_t)slot * S * rmax * ldw + c0;
   for (int e = threadIdx.x; e < r * nc; e += 256) {
     const int a = e % r, c = e / r;
-    zR[a + r * c] = z[gR[a] + (int64_t)(c0 + c) * ldz];
+    cx<R> v = xR[a * sld + c];
+    const cx<R>* wp = Wb + (int64_t)a * ldw + c;
+    const int64_t js = (int64_t)rmax * ldw;
+    // slices in order, eight loads in flight
+    for (int j0 = 0; j0 < S; j0 += 8) {
+      cx<R> t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < S) t[u] = wp[(j0 + u) * js];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < S) v = v - t[u];
+    }
+    xR[a * sld + c] = v;
   }
   __syncthreads();
+  blk_mm<R, false>(T, k, k, 0, r, xR, sld, nc, red,
+                   [&](int a, const cx<R>(&v)[SNC]) { sub_row(z, ldz, gS[a], c0, nc, v); });
   for (int e = threadIdx.x; e < r * nc; e += 256) {
     const int a = e % r, c = e / r;
-    cx<R> v = czero<R>();
-    for (int s = 0; s < r; ++s) fma_(v, Xi[a + (int64_t)s * r], zR[s + r * c]);
-    xR[a + r * c] = v;
-  }
-  for (int q0 = 0; q0 < q; q0 += chunk) {
-    const int nq = min(chunk, q - q0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nq * nc; e += 256) {
-      const int a = e % nq, c = e / nq;
-      const int g = (q0 + a) < k ? gS[q0 + a] : gN[q0 + a - k];
-      zq[a + chunk * c] = z[g + (int64_t)(c0 + c) * ldz];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < r * nc; e += 256) {
-      const int a = e % r, c = e / r;
-      cx<R> v = xR[a + r * c];
-      for (int s = 0; s < nq; ++s) v = v - Y[a + (int64_t)(q0 + s) * r] * zq[s + chunk * c];
-      xR[a + r * c] = v;
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < k * nc; e += 256) {
-    const int a = e % k, c = e / k;
-    cx<R> v = czero<R>();
-    for (int s = 0; s < r; ++s) fma_(v, T[a + (int64_t)s * k], xR[s + r * c]);
-    cx<R>* p = z + gS[a] + (int64_t)(c0 + c) * ldz;
-    *p = *p - v;
-  }
-  for (int e = threadIdx.x; e < r * nc; e += 256) {
-    const int a = e % r, c = e / r;
-    z[gR[a] + (int64_t)(c0 + c) * ldz] = xR[a + r * c];
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = xR[a * sld + c];
   }
 }
 
 template <class R>
 void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      hipStream_t s) {
+                      int qmax, cx<R>* W, hipStream_t s) {
   (void)kmax;
-  if (ph.nbox == 0) return;
-  const int chunk = 128;
-  const size_t per = (size_t)(2 * rmax + chunk) * sizeof(cx<R>);
-  int ncw = (int)((64 * 1024) / per);
-  ncw = ncw < 1 ? 1 : (ncw > 8 ? 8 : ncw);
-  ncw = ncw > nrhs ? nrhs : ncw;
-  hipLaunchKernelGGL(k_solve_bwd<R>, dim3(ph.nbox, (nrhs + ncw - 1) / ncw), dim3(256), per * ncw, s,
-                     sp, ph, rmax, chunk, ncw);
+  const int ncg = solve_group<R>(kmax, rmax, nrhs);
+  if (ph.nbox == 0 || ncg == 0) return;  // ncg == 0 is rejected by the caller
+  const int S = solve_slices(ph.nbox, qmax);
+  const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
+  const dim3 groups((nrhs + ncg - 1) / ncg);
+  // z_{S,N} chunk: one slice's rows if they fit, else what is left of the budget (>= 16 rows)
+  const int qs = (qmax + S - 1) / S;
+  const int chunk = (int)std::min<size_t>(std::max(qs, 16), SOLVE_LDS / row - (size_t)rmax - SRED);
+  hipLaunchKernelGGL(k_solve_bwd_a<R>, dim3(ph.nbox * S, groups.x), dim3(256),
+                     (size_t)(rmax + SRED + chunk) * row, s, sp, ph, rmax, chunk, ncg, S, W, nrhs);
+  hipLaunchKernelGGL(k_solve_bwd_b<R>, dim3(ph.nbox, groups.x), dim3(256),
+                     (size_t)(2 * rmax + SRED) * row, s, sp, ph, rmax, ncg, S, (const cx<R>*)W,
+                     nrhs);
 }
 
 // root apply for a batch: gather z[ids] -> ws, ws2 = Ainv ws (GEMM), scatter back
@@ -1717,12 +1927,14 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
                                          const Prob<R>*, hipStream_t);                             \
   template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t);           \
-  template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int,           \
-                                    hipStream_t);                                                  \
-  template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int,           \
-                                    hipStream_t);                                                  \
+  template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \
+                                    cx<R>*, hipStream_t);                                          \
+  template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \
+                                    cx<R>*, hipStream_t);                                          \
+  template size_t solve_work_elems<R>(int, int, int, int);                                           \
   template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);  \
   template int cpqr_mg_groups<R>(int, int, int);                                                     \
+  template int solve_group<R>(int, int, int);                                                        \
   template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*,  \
                                   unsigned*, int*, hipStream_t);
 

@@ -7,6 +7,7 @@ template <class R> void launch_leaf_assemble(const Prob<R>*, int, int, hipStream
 template <class R> void launch_build_C(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, hipStream_t) {}
 template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
+template <class R> int solve_group(int, int, int nrhs) { return nrhs < 16 ? nrhs : 16; }
 template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t) { return true; }
 template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, hipStream_t) {}
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
@@ -16,8 +17,9 @@ template <class R> void launch_plan_schur(const Prob<R>*, const Phase<R>&, GemmD
 template <class R> void launch_gemm(const GemmDesc<R>*, int, int, int, hipStream_t) {}
 template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
 template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, int*, hipStream_t) {}
-template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t) {}
-template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t) {}
+template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
+template <class R> size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs) { return (size_t)nbox * rmax * nrhs + qmax; }
+template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
 template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t) {}
 #define I(R) \
 template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
@@ -25,6 +27,7 @@ template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
 template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
 template int cpqr_mg_groups<R>(int, int, int); \
+template int solve_group<R>(int, int, int); \
 template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t); \
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
@@ -33,8 +36,9 @@ template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*
 template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
 template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \
 template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t); \
-template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t); \
-template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, hipStream_t); \
+template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \
+template size_t solve_work_elems<R>(int, int, int, int); \
+template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \
 template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
 I(double) I(float)
 void launch_kernel_block(const KParams&, const double*, const int*, int64_t, const int*, int64_t, cx<double>*, hipStream_t) {}

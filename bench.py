@@ -32,6 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 SOLVE_REPS = 20
+# HBM bytes per k_residual launch at this workload: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by the counts of a 1 GiB elementwise copy.  Valid for
+# the kernel as measured; None when the kernel changes until measured again.
+RESIDUAL_TRAFFIC_B = 9.408e9
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TF = 78.6
 FP32_MFMA_PEAK_TF = 157.3
@@ -91,12 +95,49 @@ def batched_sweep(torch, rss, W, reps=2):
             "apply_ms": float(np.median(ta) * 1e3), "apply_unknowns_per_s": tot / float(np.median(ta))}
 
 
+def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
+    """A scaled request stream through the solve server (rss_server_*): the
+    generator and mix of the serving workload (Poisson arrivals, 20% factor
+    jobs, Helmholtz kappa ~ U[10,60], FP32+refine to 1e-10, 200 GB budget, LRU),
+    with fewer requests, sides {128, 256} and nrhs <= 16 so that it runs in
+    seconds (every solve pays O(N^2) FP64 residuals).  The arrival rate is
+    `load` times the capacity measured on one factor and one solve per side."""
+    from paper_2310_15458_amd import serve
+    t_f, t_s = [], []
+    for n in sides:
+        P = W.grid_points(n)
+        k = W.grid_kernel("helmholtz", n, 35.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rss.Factorization(P, k, 1e-6, 64, precision="fp32")
+        t1 = time.perf_counter()
+        Bh = W.rhs(n * n, max_nrhs // 2, 5)
+        B = torch.from_numpy(np.ascontiguousarray(Bh.T)).cuda().t()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F.solve(B)
+        t3 = time.perf_counter()
+        F.close()
+        t_f.append(t1 - t0)
+        t_s.append(t3 - t2)
+    mean_service = 0.2 * float(np.mean(t_f)) + 0.8 * float(np.mean(t_s))
+    rate = load / mean_service
+    reqs = W.request_stream(count, rate, seed=4, sides=sides, max_nrhs=max_nrhs)
+    res, *_ = serve.run_stream(reqs, 200e9, precision="fp32")
+    res["rate_per_s"] = rate
+    res["stream"] = (f"{count} requests, Poisson rate {rate:.2f}/s (= {load} x measured capacity), "
+                     f"sides {list(sides)}, nrhs U{{1..{max_nrhs}}}, 20% factor jobs, seed 4, "
+                     f"FP32+refine to 1e-10, budget 200 GB")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the path is single-device); "
@@ -203,7 +244,7 @@ def main():
     res_flops = 8.0 * N * N * nrhs          # the complex multiply-adds of A x (8 flops each)
     roofline = {"kernel": "k_residual (FP64 on-the-fly b - A x, 16 RHS)", "bound": "alu",
                 "achieved": res_flops / t_res / 1e12, "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
-                "frac": res_flops / t_res / 1e12 / FP64_PEAK_TF, "traffic": None,
+                "frac": res_flops / t_res / 1e12 / FP64_PEAK_TF, "traffic": RESIDUAL_TRAFFIC_B,
                 "t_launch_ms": t_res * 1e3, "pair_evals_per_s": N * N / t_res,
                 "algorithmic": "8 N^2 nrhs flops per launch (kernel evaluations not counted)"}
 
@@ -271,6 +312,8 @@ def main():
         "cpu_baseline": None,
     }
     out["batched"] = batched_sweep(torch, rss, W)
+    if not args.no_serving:
+        out["serving"] = serving(torch, rss, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -456,6 +456,51 @@ std::vector<ListEntry> sorted_union(const std::vector<int>& boxes, const std::ve
   return out;
 }
 
+// r_p = b_p - A_p x_p for every problem in one batched launch per 16 columns
+struct ResProblem {
+  KParams kp;
+  const double* P;
+  int64_t n;
+  const cx<double>* X;
+  const cx<double>* B;
+  cx<double>* R;
+  int nrhs;
+};
+
+void residual_batch(const std::vector<ResProblem>& rp, Scratch& scr, hipStream_t s) {
+  int64_t tblocks = 0;
+  int max_nrhs = 0;
+  for (const auto& q : rp) {
+    tblocks += (q.n + 255) / 256;
+    max_nrhs = std::max(max_nrhs, q.nrhs);
+  }
+  const int S = residual_slices(tblocks);
+  std::vector<ResDesc> d(rp.size());
+  std::vector<ResBlock> blk, sum_blk;
+  for (size_t p = 0; p < rp.size(); ++p) {
+    const ResProblem& q = rp[p];
+    const int64_t nt = (q.n + 255) / 256;
+    ResDesc& e = d[p];
+    e.kp = q.kp;
+    e.P = q.P;
+    e.n = q.n;
+    e.X = q.X;
+    e.B = q.B;
+    e.R = q.R;
+    e.nrhs = q.nrhs;
+    e.S = (int)std::min<int64_t>(S, nt);
+    e.part = e.S > 1 ? (cx<double>*)scr.alloc((size_t)e.S * 16 * q.n * sizeof(cx<double>)) : nullptr;
+    for (int64_t tb = 0; tb < nt; ++tb) {
+      for (int sp = 0; sp < e.S; ++sp) blk.push_back({(int)p, (int)tb, sp});
+      if (e.S > 1) sum_blk.push_back({(int)p, (int)tb, 0});
+    }
+  }
+  const ResDesc* dd = scr.up(d, s);
+  const ResBlock* db = scr.up(blk, s);
+  const ResBlock* ds = sum_blk.empty() ? nullptr : scr.up(sum_blk, s);
+  launch_residual(dd, db, (int)blk.size(), ds, (int)sum_blk.size(), max_nrhs, s);
+}
+
 // Batched RS-S factorization (Alg. a:fact) of every handle in H, all on stream s.
 // Heights above the leaves are aligned: at height t every problem with
 // D - t >= 2 eliminates its boxes of depth D - t, colour by colour, and each
@@ -1324,6 +1369,7 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
         HIPCHK(hipMemcpyAsync(q.bn.data(), q.nrm + nr[p], nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
       }
       HIPCHK(hipStreamSynchronize(s));
+      Scratch rscr;  // residual partial sums, reused every iteration
       for (;;) {
         std::vector<int> live;
         for (int p = 0; p < nh; ++p)
@@ -1351,13 +1397,19 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
           apply_batch<double>(LH, Z, Lnr, s);
           for (int p : live) launch_add_c128(st[p].x, st[p].r, (int64_t)H[p]->N * nr[p], s);
         }
-        // residuals r = b - A x (FP64, on the fly)
+        // residuals r = b - A x (FP64, on the fly), every live problem in one launch
+        {
+          std::vector<ResProblem> rp;
+          for (int p : live)
+            rp.push_back({H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p]});
+          residual_batch(rp, rscr, s);
+        }
         for (int p : live) {
-          launch_residual(H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p], s);
           launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
           HIPCHK(hipMemcpyAsync(st[p].rn.data(), st[p].nrm, nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipStreamSynchronize(s));
+        rscr.clear();
         for (int p : live) {
           St& q = st[p];
           q.relres = 0.0;
@@ -1437,8 +1489,9 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
     if (!k || !points || !X || !B || !R) fail(RSS_EINVAL, "null argument");
     if (n < 1 || nrhs < 1) fail(RSS_EINVAL, "bad sizes");
     const KParams kp = to_kp(*k);
-    launch_residual(kp, points, n, (const cx<double>*)X, (const cx<double>*)B, (cx<double>*)R, nrhs,
-                    (hipStream_t)stream);
+    Scratch scr;
+    residual_batch({{kp, points, n, (const cx<double>*)X, (const cx<double>*)B, (cx<double>*)R, nrhs}},
+                   scr, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   });

@@ -190,8 +190,27 @@ void launch_root_apply(const RootApply<R>* ra, int nprob, int max_n, int max_nrh
 
 void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64_t ni,
                          const int* J, int64_t nj, cx<double>* out, hipStream_t s);
-void launch_residual(const KParams& kp, const double* P, int64_t n, const cx<double>* X,
-                     const cx<double>* B, cx<double>* Rout, int nrhs, hipStream_t s);
+// r = b - A x for several problems (FP64, on the fly)
+struct ResDesc {
+  KParams kp;
+  const double* P;     // points, n x 2
+  int64_t n;
+  const cx<double>* X;  // n x nrhs, column-major (ld n), likewise B and R
+  const cx<double>* B;
+  cx<double>* R;
+  cx<double>* part;     // S x 16 x n partial sums when S > 1
+  int nrhs;
+  int S;                // source slices
+};
+struct ResBlock {
+  int prob, tb, sp;     // problem, block of 256 targets, source slice
+};
+// source slices for a launch with this many 256-target blocks in total
+int residual_slices(int64_t target_blocks);
+// blk: every (problem, target block, slice); sum_blk: slice 0 of the target
+// blocks of problems with S > 1
+void launch_residual(const ResDesc* d, const ResBlock* blk, int nblk, const ResBlock* sum_blk,
+                     int nsum, int max_nrhs, hipStream_t s);
 // refinement helpers
 void launch_colnorms(const cx<double>* V, int64_t n, int nrhs, double* out, hipStream_t s);
 void launch_scale_to_c64(const cx<double>* V, int64_t n, int nrhs, const double* norms,

@@ -1767,29 +1767,42 @@ void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64
                      ni, J, nj, out);
 }
 
+// r = b - A x for several problems at once (FP64, entries evaluated on the
+// fly).  Workgroup = (problem, block of 256 targets, source slice): sources
+// stream through LDS 256 at a time with their NC right-hand-side values; a
+// problem with one slice writes r directly, otherwise each slice writes its
+// partial sums (16 columns per slice) and k_residual_sum subtracts them from b
+// in slice order.
 template <int NC>
-__global__ __launch_bounds__(256) void k_residual(KParams kp, const double* P, int64_t n,
-                                                  const cx<double>* X, const cx<double>* B,
-                                                  cx<double>* Rout, int c0) {
+__global__ __launch_bounds__(256) void k_residual(const ResDesc* dd, const ResBlock* blk, int c0) {
   __shared__ double sx[256], sy[256];
   __shared__ cx<double> xs[256 * NC];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const ResBlock bb = blk[blockIdx.x];
+  const ResDesc D = dd[bb.prob];
+  if (c0 >= D.nrhs) return;
+  const int nc = min(NC, D.nrhs - c0);
+  const int64_t n = D.n;
+  const int64_t i = (int64_t)bb.tb * 256 + threadIdx.x;
   const bool live = i < n;
-  const double xi = live ? P[2 * i] : 0.0, yi = live ? P[2 * i + 1] : 0.0;
+  const double xi = live ? D.P[2 * i] : 0.0, yi = live ? D.P[2 * i + 1] : 0.0;
+  const int64_t ntile = (n + 255) / 256, per = (ntile + D.S - 1) / D.S;
+  const int64_t lo = (int64_t)bb.sp * per * 256, hi = min(n, lo + per * 256);
+  const KParams kp = D.kp;
   cx<double> acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = czero<double>();
-  for (int64_t t0 = 0; t0 < n; t0 += 256) {
+  for (int64_t t0 = lo; t0 < hi; t0 += 256) {
     const int64_t sj = t0 + threadIdx.x;
     __syncthreads();
-    if (sj < n) {
-      sx[threadIdx.x] = P[2 * sj];
-      sy[threadIdx.x] = P[2 * sj + 1];
+    if (sj < hi) {
+      sx[threadIdx.x] = D.P[2 * sj];
+      sy[threadIdx.x] = D.P[2 * sj + 1];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) xs[threadIdx.x * NC + c] = X[sj + (int64_t)(c0 + c) * n];
+      for (int c = 0; c < NC; ++c)
+        xs[threadIdx.x * NC + c] = c < nc ? D.X[sj + (int64_t)(c0 + c) * n] : czero<double>();
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)256, n - t0);
+    const int cnt = (int)min((int64_t)256, hi - t0);
     if (live) {
       for (int s = 0; s < cnt; ++s) {
         cx<double> a;
@@ -1804,37 +1817,63 @@ __global__ __launch_bounds__(256) void k_residual(KParams kp, const double* P, i
       }
     }
   }
-  if (live) {
+  if (!live) return;
+  if (D.S == 1) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const cx<double> bb = B[i + (int64_t)(c0 + c) * n];
-      Rout[i + (int64_t)(c0 + c) * n] = bb - acc[c];
-    }
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) {
+        const int64_t e = i + (int64_t)(c0 + c) * n;
+        D.R[e] = D.B[e] - acc[c];
+      }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) D.part[((int64_t)bb.sp * 16 + c) * n + i] = acc[c];
   }
 }
 
-void launch_residual(const KParams& kp, const double* P, int64_t n, const cx<double>* X,
-                     const cx<double>* B, cx<double>* Rout, int nrhs, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256));
+// r = b - (sum of the slices' partials, in slice order) for the columns
+// c0 .. c0 + width - 1; one workgroup per block of 256 targets of a sliced problem
+__global__ __launch_bounds__(256) void k_residual_sum(const ResDesc* dd, const ResBlock* blk, int c0,
+                                                     int width) {
+  const ResBlock bb = blk[blockIdx.x];
+  const ResDesc D = dd[bb.prob];
+  if (c0 >= D.nrhs) return;
+  const int nc = min(width, D.nrhs - c0);  // the columns of this chunk
+  const int64_t n = D.n;
+  const int64_t i = (int64_t)bb.tb * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nc; ++c) {
+    cx<double> v = D.B[i + (int64_t)(c0 + c) * n];
+    for (int sp = 0; sp < D.S; ++sp) v = v - D.part[((int64_t)sp * 16 + c) * n + i];
+    D.R[i + (int64_t)(c0 + c) * n] = v;
+  }
+}
+
+int residual_slices(int64_t target_blocks) {
+  if (target_blocks >= 1024) return 1;
+  return (int)std::min<int64_t>(16, (1024 + target_blocks - 1) / std::max<int64_t>(target_blocks, 1));
+}
+
+void launch_residual(const ResDesc* d, const ResBlock* blk, int nblk, const ResBlock* sum_blk,
+                     int nsum, int max_nrhs, hipStream_t s) {
   int c0 = 0;
-  while (c0 < nrhs) {
-    const int left = nrhs - c0;
-    if (left >= 16) {
-      hipLaunchKernelGGL(k_residual<16>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
-      c0 += 16;
-    } else if (left >= 8) {
-      hipLaunchKernelGGL(k_residual<8>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
-      c0 += 8;
-    } else if (left >= 4) {
-      hipLaunchKernelGGL(k_residual<4>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
-      c0 += 4;
-    } else if (left >= 2) {
-      hipLaunchKernelGGL(k_residual<2>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
-      c0 += 2;
-    } else {
-      hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, P, n, X, B, Rout, c0);
-      c0 += 1;
-    }
+  while (c0 < max_nrhs) {
+    const int left = max_nrhs - c0;
+    const int nc = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    if (nc == 16)
+      hipLaunchKernelGGL(k_residual<16>, dim3(nblk), dim3(256), 0, s, d, blk, c0);
+    else if (nc == 8)
+      hipLaunchKernelGGL(k_residual<8>, dim3(nblk), dim3(256), 0, s, d, blk, c0);
+    else if (nc == 4)
+      hipLaunchKernelGGL(k_residual<4>, dim3(nblk), dim3(256), 0, s, d, blk, c0);
+    else if (nc == 2)
+      hipLaunchKernelGGL(k_residual<2>, dim3(nblk), dim3(256), 0, s, d, blk, c0);
+    else
+      hipLaunchKernelGGL(k_residual<1>, dim3(nblk), dim3(256), 0, s, d, blk, c0);
+    if (nsum > 0)
+      hipLaunchKernelGGL(k_residual_sum, dim3(nsum), dim3(256), 0, s, d, sum_blk, c0, nc);
+    c0 += nc;
   }
 }
 

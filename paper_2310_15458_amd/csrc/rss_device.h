@@ -57,6 +57,11 @@ __device__ __forceinline__ cx<R> czero() { return {R(0), R(0)}; }
 
 template <class R>
 __device__ __forceinline__ cx<R> from_d(double re, double im) { return {(R)re, (R)im}; }
+// widen to / round from complex FP64
+template <class R>
+__device__ __forceinline__ cx<double> to_d(cx<R> a) { return {(double)a.x, (double)a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> from_cd(cx<double> a) { return {(R)a.x, (R)a.y}; }
 
 // ---------------------------------------------------------------------------
 // kernel parameters (mirror of the C ABI struct, plain data)

@@ -653,10 +653,10 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     // merged colour phases over all active problems, and one shared workspace
     struct Merged {
       std::vector<int> box, prob;
-      std::vector<int64_t> oC, oX, oZ, oI;
-      int64_t tot = 0, itot = 0;
+      std::vector<int64_t> oC, oX, oZ, oI, oD;
+      int64_t tot = 0, itot = 0, dtot = 0;
     } M[9];
-    int64_t Wmax = 0, Imax = 0;
+    int64_t Wmax = 0, Imax = 0, Dmax = 0;
     int maxph = 0;
     for (int c = 0; c < 9; ++c) {
       Merged& G = M[c];
@@ -682,6 +682,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
           Z += (int64_t)n * (n + nN0);
           G.oI.push_back(I);
           I += 3 * n;
+          G.oD.push_back(G.dtot);
+          G.dtot += (int64_t)n * n;
         }
       }
       for (size_t i = 0; i < G.box.size(); ++i) {
@@ -693,10 +695,13 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       G.itot = I;
       Wmax = std::max(Wmax, G.tot);
       Imax = std::max(Imax, I);
+      Dmax = std::max(Dmax, G.dtot);
       maxph = std::max(maxph, (int)G.box.size());
     }
     void* Wd = scr.alloc((size_t)Wmax * E);
     int* Wi = (int*)scr.alloc((size_t)Imax * sizeof(int));
+    // FP64 work for the redundant-block inverses too large for LDS
+    cx<double>* Wdd = (cx<double>*)scr.alloc((size_t)std::max<int64_t>(1, Dmax) * sizeof(cx<double>));
     // multi-workgroup ID for colours with few boxes: G workgroups per box
     int Gc[9], Gmax = 1;
     for (int c = 0; c < 9; ++c) {
@@ -724,6 +729,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       ph.mrow = mrow + (size_t)c * std::max(1, maxph);
       ph.W = (cx<R>*)Wd;
       ph.Wi = Wi;
+      ph.Wd = Wdd;
+      ph.oD = scr.up(G.oD, s);
       prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
       prof.run(RSS_K_ID, s, [&] {
         if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
@@ -903,6 +910,10 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     std::vector<ListEntry> lists;
     std::vector<Prob<R>> cprobs;
     std::vector<RootDesc<R>> rds;
+    // complex64 form: the root is inverted in FP64 (A64/tmp64) and rounded into A
+    std::vector<RootDesc<double>> rds64;
+    std::vector<cx<R>*> root_out;
+    constexpr bool f32 = sizeof(R) != sizeof(double);
     int nrmax = 0;
     for (int p = 0; p < np; ++p) {
       rss_ctx* h = H[p];
@@ -917,15 +928,29 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       const size_t bytes = (size_t)nr * nr * E;
       RootDesc<R> rd;
       rd.A = (cx<R>*)h->arena.alloc(bytes);
-      rd.tmp = (cx<R>*)h->arena.alloc(bytes);
       rd.keys = (unsigned long long*)scr.alloc((size_t)nr * 8);
       HIPCHK(hipMemsetAsync(rd.keys, 0, (size_t)nr * 8, s));
       rd.perm = (int*)scr.alloc((size_t)nr * 2 * sizeof(int));
       rd.n = nr;
+      if (f32) {
+        RootDesc<double> r64;
+        r64.A = (cx<double>*)scr.alloc((size_t)nr * nr * sizeof(cx<double>));
+        r64.tmp = (cx<double>*)scr.alloc((size_t)nr * nr * sizeof(cx<double>));
+        r64.keys = rd.keys;
+        r64.perm = rd.perm;
+        r64.n = nr;
+        rds64.push_back(r64);
+        root_out.push_back(rd.A);
+        rd.tmp = nullptr;
+        h->d_root_inv = rd.A;
+        h->root_spare = nullptr;
+      } else {
+        rd.tmp = (cx<R>*)h->arena.alloc(bytes);
+        // the inverse ends in A for odd n, in tmp for even n
+        h->d_root_inv = (nr & 1) ? (void*)rd.A : (void*)rd.tmp;
+        h->root_spare = (nr & 1) ? (void*)rd.tmp : (void*)rd.A;
+      }
       rds.push_back(rd);
-      // the inverse ends in A for odd n, in tmp for even n
-      h->d_root_inv = (nr & 1) ? (void*)rd.A : (void*)rd.tmp;
-      h->root_spare = (nr & 1) ? (void*)rd.tmp : (void*)rd.A;
       Prob<R> cp{};
       const bool have = h->D >= MIN_DEPTH;
       if (have) cp.L = dev_level<R>(w.cur, h->x0, h->y0, h->s0);
@@ -957,7 +982,24 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       prof.run(RSS_K_ASSEMBLE, s, [&] {
         launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, nrmax, nrmax, d_cp, s);
       });
-      prof.run(RSS_K_ROOT, s, [&] { launch_root_inverse<R>(d_rd, (int)rds.size(), nrmax, d_err, s); });
+      prof.run(RSS_K_ROOT, s, [&] {
+        if (f32) {
+          for (size_t i = 0; i < rds64.size(); ++i) {
+            const int64_t nn = (int64_t)rds64[i].n * rds64[i].n;
+            HIPCHK(hipMemsetAsync(rds64[i].A, 0, (size_t)nn * sizeof(cx<double>), s));
+            launch_axpy_from_c64((const cx<float>*)rds[i].A, nn, 1, nullptr, rds64[i].A, s);
+          }
+          RootDesc<double>* d_rd64 = scr.up(rds64, s);
+          launch_root_inverse<double>(d_rd64, (int)rds64.size(), nrmax, d_err, s);
+          for (size_t i = 0; i < rds64.size(); ++i) {
+            const int nn = rds64[i].n;
+            const cx<double>* res = (nn & 1) ? rds64[i].A : rds64[i].tmp;
+            launch_cast_c64(res, (int64_t)nn * nn, 1, (cx<float>*)root_out[i], s);
+          }
+        } else {
+          launch_root_inverse<R>(d_rd, (int)rds.size(), nrmax, d_err, s);
+        }
+      });
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(s));
     }

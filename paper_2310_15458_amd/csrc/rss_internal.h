@@ -86,6 +86,9 @@ struct Phase {
   int* mrow;           // rows of C per slot
   cx<R>* W;
   int* Wi;
+  // r x r complex128 work for X_RR^{-1} when it does not fit in LDS
+  const int64_t* oD;
+  cx<double>* Wd;
 };
 
 template <class R>

@@ -23,7 +23,11 @@ constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
 #define RSS_CPQR_CH 8
 #endif
 #ifndef RSS_CPQR_MG_CH
-#define RSS_CPQR_MG_CH 8
+#define RSS_CPQR_MG_CH 4
+#endif
+// columns a wave of the multi-workgroup QR updates together
+#ifndef RSS_CPQR_MG_CB
+#define RSS_CPQR_MG_CB 4
 #endif
 
 __device__ __forceinline__ int nb_dx(int j) {  // j-th of the 8 neighbour offsets, ascending id
@@ -422,7 +426,7 @@ template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> ph, int G, int nmax,
                                                 int vcap, double* pnorm, double* pdot,
                                                 unsigned* bars, int* err) {
-  constexpr int CH = RSS_CPQR_MG_CH;
+  constexpr int CH = RSS_CPQR_MG_CH, CB = RSS_CPQR_MG_CB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
   double* nrm = reinterpret_cast<double*>(smem_raw);          // nmax
@@ -534,17 +538,23 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
       for (int i = i0 + threadIdx.x; i < r1; i += NT) vsh[i - i0] = cj[i];
       __syncthreads();
     }
-    // partial dot products v^H C[:, q] over this workgroup's rows, CH rows per
-    // lane per round so that a wave keeps CH loads in flight
-    for (int c = j + 1 + wv; c < n; c += NW) {
-      const int q = perm[c];
-      const cx<R>* col = C + (int64_t)q * m;
-      double dr = 0.0, di = 0.0;
-      for (int base = i0 + lane; base < r1; base += 64 * CH) {
-        cx<R> a[CH];
+    // partial dot products v^H C[:, q] over this workgroup's rows: a wave takes
+    // CB columns at a time and CH rows of each per lane per round, so that
+    // CB * CH loads are in flight
+    for (int c0 = j + 1 + wv; c0 < n; c0 += NW * CB) {
+      int q[CB];
 #pragma unroll
-        for (int t = 0; t < CH; ++t)
-          if (base + 64 * t < r1) a[t] = col[base + 64 * t];
+      for (int u = 0; u < CB; ++u) q[u] = c0 + NW * u < n ? perm[c0 + NW * u] : -1;
+      double dr[CB], di[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) dr[u] = di[u] = 0.0;
+      for (int base = i0 + lane; base < r1; base += 64 * CH) {
+        cx<R> a[CB][CH];
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+#pragma unroll
+          for (int t = 0; t < CH; ++t)
+            if (q[u] >= 0 && base + 64 * t < r1) a[u][t] = C[(int64_t)q[u] * m + base + 64 * t];
 #pragma unroll
         for (int t = 0; t < CH; ++t) {
           const int i = base + 64 * t;
@@ -552,16 +562,23 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
             const cx<R> vv = vsrc[i - i0];
             const double vr = (i == j) ? v0r : (double)vv.x;
             const double vi = (i == j) ? v0i : (double)vv.y;
-            dr += vr * a[t].x + vi * a[t].y;
-            di += vr * a[t].y - vi * a[t].x;
+#pragma unroll
+            for (int u = 0; u < CB; ++u)
+              if (q[u] >= 0) {
+                dr[u] += vr * a[u][t].x + vi * a[u][t].y;
+                di[u] += vr * a[u][t].y - vi * a[u][t].x;
+              }
           }
         }
       }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      if (lane == 0) {
-        pd[((size_t)g * nmax + q) * 2] = dr;
-        pd[((size_t)g * nmax + q) * 2 + 1] = di;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        dr[u] = wave_sum(dr[u]);
+        di[u] = wave_sum(di[u]);
+        if (lane == 0 && q[u] >= 0) {
+          pd[((size_t)g * nmax + q[u]) * 2] = dr[u];
+          pd[((size_t)g * nmax + q[u]) * 2 + 1] = di[u];
+        }
       }
     }
     mg_barrier(bar, (++nbar) * G, err);
@@ -576,17 +593,25 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
       wim[c] = beta * si;
     }
     __syncthreads();
-    // update this workgroup's rows; partial norms of rows > j
-    for (int c = j + 1 + wv; c < n; c += NW) {
-      const int q = perm[c];
-      cx<R>* col = C + (int64_t)q * m;
-      const double sr = wre[c], si = wim[c];
-      double s2 = 0.0;
-      for (int base = i0 + lane; base < r1; base += 64 * CH) {
-        cx<R> a[CH];
+    // update this workgroup's rows; partial norms of rows > j (columns batched as above)
+    for (int c0 = j + 1 + wv; c0 < n; c0 += NW * CB) {
+      int q[CB];
+      double sr[CB], si[CB], s2[CB];
 #pragma unroll
-        for (int t = 0; t < CH; ++t)
-          if (base + 64 * t < r1) a[t] = col[base + 64 * t];
+      for (int u = 0; u < CB; ++u) {
+        const int c = c0 + NW * u;
+        q[u] = c < n ? perm[c] : -1;
+        sr[u] = c < n ? wre[c] : 0.0;
+        si[u] = c < n ? wim[c] : 0.0;
+        s2[u] = 0.0;
+      }
+      for (int base = i0 + lane; base < r1; base += 64 * CH) {
+        cx<R> a[CB][CH];
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+#pragma unroll
+          for (int t = 0; t < CH; ++t)
+            if (q[u] >= 0 && base + 64 * t < r1) a[u][t] = C[(int64_t)q[u] * m + base + 64 * t];
 #pragma unroll
         for (int t = 0; t < CH; ++t) {
           const int i = base + 64 * t;
@@ -594,15 +619,23 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
             const cx<R> vv = vsrc[i - i0];
             const double vr = (i == j) ? v0r : (double)vv.x;
             const double vi = (i == j) ? v0i : (double)vv.y;
-            a[t].x -= (R)(vr * sr - vi * si);
-            a[t].y -= (R)(vr * si + vi * sr);
-            col[i] = a[t];
-            if (i > j) s2 += abs2d(a[t]);
+#pragma unroll
+            for (int u = 0; u < CB; ++u)
+              if (q[u] >= 0) {
+                cx<R> x = a[u][t];
+                x.x -= (R)(vr * sr[u] - vi * si[u]);
+                x.y -= (R)(vr * si[u] + vi * sr[u]);
+                C[(int64_t)q[u] * m + i] = x;
+                if (i > j) s2[u] += abs2d(x);
+              }
           }
         }
       }
-      s2 = wave_sum(s2);
-      if (lane == 0) pn[(size_t)g * nmax + q] = s2;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        s2[u] = wave_sum(s2[u]);
+        if (lane == 0 && q[u] >= 0) pn[(size_t)g * nmax + q[u]] = s2[u];
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0 && j >= r0 && j < r1) C[j + (int64_t)pc * m] = cx<R>{(R)alr, (R)ali};
@@ -689,7 +722,7 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 }
 
 // ---------------------------------------------------------------------------
-// sparsification (eq. e:s) with the ID of the box:
+// sparsification (eq. e:s) with the ID of the box, accumulated in FP64:
 //   X_SR = A_SR - A_SS T         X_RS = A_RS - T^* A_SS
 //   X_RR = (A_RR - A_RS T) - T^* X_SR
 //   X_NR = A_NR - A_NS T         X_RN = A_RN - T^* A_SN
@@ -727,24 +760,24 @@ __global__ __launch_bounds__(256) void k_sparsify(const Prob<R>* probs, Phase<R>
     const int ld = n0b;
     for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
       const int a = e % k, c = e / k;
-      cx<R> v = A[Sl[a] + (int64_t)Rl[c] * ld];
-      for (int s = 0; s < k; ++s) v = v - A[Sl[a] + (int64_t)Sl[s] * ld] * T[s + (int64_t)c * k];
-      XSNR[a + (int64_t)c * ldx] = v;
+      cx<double> v = to_d(A[Sl[a] + (int64_t)Rl[c] * ld]);
+      for (int s = 0; s < k; ++s) v = v - to_d(A[Sl[a] + (int64_t)Sl[s] * ld]) * to_d(T[s + (int64_t)c * k]);
+      XSNR[a + (int64_t)c * ldx] = from_cd<R>(v);
     }
     for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
       const int c = e % r, a = e / r;
-      cx<R> v = A[Rl[c] + (int64_t)Sl[a] * ld];
-      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c * k], A[Sl[s] + (int64_t)Sl[a] * ld]);
-      Z[c + (int64_t)a * r] = v;
+      cx<double> v = to_d(A[Rl[c] + (int64_t)Sl[a] * ld]);
+      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c * k]), to_d(A[Sl[s] + (int64_t)Sl[a] * ld]));
+      Z[c + (int64_t)a * r] = from_cd<R>(v);
     }
     __syncthreads();
     cx<R>* X = ph.W + ph.oX[slot];
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
       const int c1 = e % r, c2 = e / r;
-      cx<R> v = A[Rl[c1] + (int64_t)Rl[c2] * ld];
-      for (int s = 0; s < k; ++s) v = v - A[Rl[c1] + (int64_t)Sl[s] * ld] * T[s + (int64_t)c2 * k];
-      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c1 * k], XSNR[s + (int64_t)c2 * ldx]);
-      X[c1 + (int64_t)c2 * r] = v;
+      cx<double> v = to_d(A[Rl[c1] + (int64_t)Rl[c2] * ld]);
+      for (int s = 0; s < k; ++s) v = v - to_d(A[Rl[c1] + (int64_t)Sl[s] * ld]) * to_d(T[s + (int64_t)c2 * k]);
+      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c1 * k]), to_d(XSNR[s + (int64_t)c2 * ldx]));
+      X[c1 + (int64_t)c2 * r] = from_cd<R>(v);
     }
     int* gS = rec.G + rec.oS[b];
     int* gR = rec.G + rec.oR[b];
@@ -757,16 +790,16 @@ __global__ __launch_bounds__(256) void k_sparsify(const Prob<R>* probs, Phase<R>
     const int ld1 = L.n0[nbj];
     for (int e = threadIdx.x; e < cn * r; e += blockDim.x) {
       const int i = e % cn, c = e / cn;
-      cx<R> v = A1[i + (int64_t)Rl[c] * ld1];
-      for (int s = 0; s < k; ++s) v = v - A1[i + (int64_t)Sl[s] * ld1] * T[s + (int64_t)c * k];
-      XSNR[(k + offj + i) + (int64_t)c * ldx] = v;
+      cx<double> v = to_d(A1[i + (int64_t)Rl[c] * ld1]);
+      for (int s = 0; s < k; ++s) v = v - to_d(A1[i + (int64_t)Sl[s] * ld1]) * to_d(T[s + (int64_t)c * k]);
+      XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(v);
     }
     const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
     for (int e = threadIdx.x; e < r * cn; e += blockDim.x) {
       const int c = e % r, i = e / r;
-      cx<R> v = A2[Rl[c] + (int64_t)i * n0b];
-      for (int s = 0; s < k; ++s) v = v - cmulc(T[s + (int64_t)c * k], A2[Sl[s] + (int64_t)i * n0b]);
-      Z[c + (int64_t)(k + offj + i) * r] = v;
+      cx<double> v = to_d(A2[Rl[c] + (int64_t)i * n0b]);
+      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c * k]), to_d(A2[Sl[s] + (int64_t)i * n0b]));
+      Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(v);
     }
     int* gN = rec.G + rec.oN[b];
     const int* gid2 = L.idx + L.ioff[nbj];
@@ -781,31 +814,39 @@ void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// X_RR^{-1} by in-place Gauss-Jordan elimination with partial pivoting
-// (the LU of eq. e:step, kept as an explicit inverse).  One workgroup per box.
+// X_RR^{-1} by Gauss-Jordan elimination with partial pivoting (the LU of
+// eq. e:step, kept as an explicit inverse), in FP64 in both forms: X_RR is as
+// ill-conditioned as 1 + |T|^2, and an explicit inverse in FP32 costs the
+// complex64 form most of its accuracy.  The block is worked on in LDS when it
+// fits, else in the phase's FP64 workspace; the result is rounded to the
+// record's precision.  One workgroup per box; four barriers per pivot step.
 // ---------------------------------------------------------------------------
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> ph, int* errflag,
                                                 size_t lds_off, size_t lds_cap) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double rv[NT];
-  __shared__ int ri[NT];
-  __shared__ int sh_p;
+  constexpr int NW = NT / 64;
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
   const int slot = blockIdx.x, b = ph.box[slot];
   const Records<R> rec = probs[ph.prob[slot]].rec;
   const int r = rec.r[b];
   if (r == 0) return;
-  cx<R>* colk = reinterpret_cast<cx<R>*>(smem_raw);
-  int* piv = reinterpret_cast<int*>(colk + r);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // LDS: pivot column, scaled pivot row, pivot rows, column map; then the block if it fits
+  cx<double>* colk = reinterpret_cast<cx<double>*>(smem_raw);
+  cx<double>* rowk = colk + r;
+  int* piv = reinterpret_cast<int*>(rowk + r);
+  int* src = piv + r;
   cx<R>* Aout = rec.F + rec.oXi[b];
   const cx<R>* X = ph.W + ph.oX[slot];
-  // work in LDS when the r x r block fits behind the column and pivot arrays
-  cx<R>* Alds = reinterpret_cast<cx<R>*>(smem_raw + lds_off);
-  const bool in_lds = (size_t)r * r <= lds_cap;
-  cx<R>* A = in_lds ? Alds : Aout;
-  for (int e = threadIdx.x; e < r * r; e += NT) A[e] = X[e];
+  cx<double>* A = (size_t)r * r <= lds_cap ? reinterpret_cast<cx<double>*>(smem_raw + lds_off)
+                                          : ph.Wd + ph.oD[slot];
+  for (int e = threadIdx.x; e < r * r; e += NT) A[e] = to_d(X[e]);
+  const int i0 = threadIdx.x % r, j0 = threadIdx.x / r, di = NT % r, dj = NT / r;
   __syncthreads();
   for (int kk = 0; kk < r; ++kk) {
+    // pivot: largest |A(i, kk)| for i >= kk, smallest i on ties
     double best = -1.0;
     int bi = kk;
     for (int i = kk + threadIdx.x; i < r; i += NT) {
@@ -815,80 +856,90 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
         bi = i;
       }
     }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) {
-        const double v2 = rv[threadIdx.x + o];
-        const int i2 = ri[threadIdx.x + o];
-        if (v2 > rv[threadIdx.x] || (v2 == rv[threadIdx.x] && i2 < ri[threadIdx.x])) {
-          rv[threadIdx.x] = v2;
-          ri[threadIdx.x] = i2;
-        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double v2 = __shfl_xor(best, o, 64);
+      const int i2 = __shfl_xor(bi, o, 64);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      sh_p = rv[0] > 0.0 ? ri[0] : -1;
-      piv[kk] = ri[0];
+    if (lane == 0) {
+      rv[wv] = best;
+      ri[wv] = bi;
     }
     __syncthreads();
-    const int p = sh_p;
-    if (p < 0) {
+    best = rv[0];
+    bi = ri[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > best || (rv[w] == best && ri[w] < bi)) {
+        best = rv[w];
+        bi = ri[w];
+      }
+    if (!(best > 0.0)) {
       if (threadIdx.x == 0) atomicOr(errflag, ERRF_SINGULAR);
-      return;
+      return;  // uniform: every thread reached the same decision
     }
+    const int p = bi;
+    if (threadIdx.x == 0) piv[kk] = p;
     if (p != kk)
       for (int j = threadIdx.x; j < r; j += NT) {
-        const cx<R> t = A[kk + (int64_t)j * r];
+        const cx<double> t = A[kk + (int64_t)j * r];
         A[kk + (int64_t)j * r] = A[p + (int64_t)j * r];
         A[p + (int64_t)j * r] = t;
       }
     __syncthreads();
-    for (int i = threadIdx.x; i < r; i += NT) colk[i] = A[i + (int64_t)kk * r];
-    __syncthreads();
-    const cx<R> d = colk[kk];
+    const cx<double> d = A[kk + (int64_t)kk * r];
     const double dd = abs2d(d);
-    const cx<R> pinv{(R)(d.x / dd), (R)(-d.y / dd)};
-    for (int j = threadIdx.x; j < r; j += NT) {
-      if (j == kk) A[kk + (int64_t)kk * r] = pinv;
-      else A[kk + (int64_t)j * r] = A[kk + (int64_t)j * r] * pinv;
+    const cx<double> pinv{d.x / dd, -d.y / dd};
+    for (int i = threadIdx.x; i < r; i += NT) {
+      colk[i] = A[i + (int64_t)kk * r];
+      rowk[i] = i == kk ? pinv : A[kk + (int64_t)i * r] * pinv;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r * r; e += NT) {
-      const int i = e % r, j = e / r;
-      if (i == kk) continue;
-      if (j == kk) A[i + (int64_t)kk * r] = czero<R>() - colk[i] * pinv;
-      else A[i + (int64_t)j * r] = A[i + (int64_t)j * r] - colk[i] * A[kk + (int64_t)j * r];
-    }
-    __syncthreads();
-  }
-  for (int kk = r - 1; kk >= 0; --kk) {
-    const int p = piv[kk];  // set for every step (the loop above ran to completion)
-    if (p != kk)
-      for (int i = threadIdx.x; i < r; i += NT) {
-        const cx<R> t = A[i + (int64_t)kk * r];
-        A[i + (int64_t)kk * r] = A[i + (int64_t)p * r];
-        A[i + (int64_t)p * r] = t;
+    // every entry once; (i, j) of e = tid + NT t advanced without a division
+    for (int e = threadIdx.x, i = i0, j = j0; e < r * r; e += NT) {
+      if (i == kk) A[e] = rowk[j];
+      else if (j == kk) A[e] = czero<double>() - colk[i] * pinv;
+      else A[e] = A[e] - colk[i] * rowk[j];
+      i += di;
+      j += dj;
+      if (i >= r) {
+        i -= r;
+        ++j;
       }
+    }
     __syncthreads();
   }
-  if (in_lds)
-    for (int e = threadIdx.x; e < r * r; e += NT) Aout[e] = A[e];
+  // undo the row interchanges as column interchanges in reverse order: final
+  // column c is column src[c] of the eliminated block
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < r; ++c) src[c] = c;
+    for (int kk = r - 1; kk >= 0; --kk) {
+      const int p = piv[kk], t = src[kk];
+      src[kk] = src[p];
+      src[p] = t;
+    }
+  }
+  __syncthreads();
+  for (int c = wv; c < r; c += NW) {
+    const cx<double>* Ac = A + (int64_t)src[c] * r;
+    for (int i = lane; i < r; i += 64) Aout[i + (int64_t)c * r] = from_cd<R>(Ac[i]);
+  }
 }
 
 template <class R>
 void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s) {
   if (ph.nbox == 0) return;
-  const size_t head = ((size_t)nmax * (sizeof(cx<R>) + sizeof(int)) + 15) & ~(size_t)15;
-  // the block itself in LDS up to 96 KiB (r <= 78 in c128, r <= 110 in c64), within
-  // 150 KiB of dynamic LDS in total
+  const size_t E = sizeof(cx<double>);
+  const size_t head = ((size_t)nmax * (2 * E + 2 * sizeof(int)) + 15) & ~(size_t)15;
+  // the block itself in LDS up to 96 KiB (r <= 78), within 150 KiB of dynamic LDS in total
   const size_t room = head < (size_t)(150 * 1024) ? (size_t)(150 * 1024) - head : 0;
-  const size_t cap = std::min({(size_t)nmax * nmax, (size_t)(96 * 1024) / sizeof(cx<R>),
-                               room / sizeof(cx<R>)});
-  const size_t shm = head + cap * sizeof(cx<R>);
+  const size_t cap = std::min({(size_t)nmax * nmax, (size_t)(96 * 1024) / E, room / E});
+  const size_t shm = head + cap * E;
   hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, errflag, head,
                      cap);
 }
@@ -981,6 +1032,9 @@ void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* de
 // ---------------------------------------------------------------------------
 // batched ragged complex GEMM: C = (beta C) + sign * A B, 64 x 64 tiles,
 // 256 threads each owning a 4 x 4 patch (rows tx + 16 a, cols ty + 16 b).
+// In the complex64 form each 16-deep slice of the sum is accumulated in FP32
+// and the slices are added in FP64, which keeps the rounding error of long
+// sums near that of one slice.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles_m) {
@@ -992,10 +1046,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
   if (i0 >= d.M || j0 >= d.N) return;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   cx<R> acc[4][4];
+  cx<double> accd[4][4];  // complex64 form: FP64 sum of the per-tile FP32 sums
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = czero<R>();
+    for (int c = 0; c < 4; ++c) {
+      acc[a][c] = czero<R>();
+      accd[a][c] = czero<double>();
+    }
   for (int k0 = 0; k0 < d.K; k0 += 16) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
       const int i = e & 63, kk = e >> 6;
@@ -1019,6 +1077,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
         for (int c = 0; c < 4; ++c) fma_(acc[a][c], av[a], bv[c]);
     }
     __syncthreads();
+    if constexpr (sizeof(R) != sizeof(double)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          accd[a][c] = accd[a][c] + to_d(acc[a][c]);
+          acc[a][c] = czero<R>();
+        }
+    }
   }
   const R sg = (R)d.sign;
 #pragma unroll
@@ -1028,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
       const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * c;
       if (gi < d.M && gj < d.N) {
         cx<R>* p = d.C + gi + (int64_t)gj * d.ldc;
-        const cx<R> v = sg * acc[a][c];
+        const cx<R> v = sizeof(R) == sizeof(double) ? sg * acc[a][c] : from_cd<R>((double)sg * accd[a][c]);
         *p = d.beta ? (*p + v) : v;
       }
     }

@@ -73,8 +73,9 @@ struct KParams {
 };
 
 // H0^(1)(x) = J0(x) + i Y0(x) for x > 0.
-// x < XA: Chebyshev interpolants of J0 and G = Y0 - (2/pi) log(x/2) J0 (both
-// entire); x >= XA: Hankel's large-argument expansion with the phase factor
+// x < XA: polynomial interpolants (Horner form in t in [-1, 1]) of J0 and of
+// G = Y0 - (2/pi) log(x/2) J0 (both entire) on intervals of width XA / NSEG;
+// x >= XA: Hankel's large-argument expansion with the phase factor
 // e^{i(x - pi/4)} = (cos x + i sin x)(1 - i)/sqrt(2).
 __device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0) {
   constexpr double W = RSS_BESSEL_XA / RSS_BESSEL_NSEG;
@@ -82,24 +83,18 @@ __device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0) {
   if (x < RSS_BESSEL_XA) {
     int s = (int)(x * (1.0 / W));
     s = s < RSS_BESSEL_NSEG - 1 ? s : RSS_BESSEL_NSEG - 1;
-    const double a = s * W;
-    const double t = (2.0 * (x - a) - W) * (1.0 / W);
-    const double* cj = rss_cheb_j0 + s * (RSS_BESSEL_DEG + 1);
-    const double* cg = rss_cheb_g + s * (RSS_BESSEL_DEG + 1);
-    double bj1 = 0.0, bj2 = 0.0, bg1 = 0.0, bg2 = 0.0;
-    const double t2 = 2.0 * t;
+    // local variable of interval s (exact when W is a power of two)
+    const double t = (x - (s + 0.5) * W) * (2.0 / W);
+    const double* cj = rss_poly_j0 + s * (RSS_BESSEL_DEG + 1);
+    const double* cg = rss_poly_g + s * (RSS_BESSEL_DEG + 1);
+    double pj = cj[RSS_BESSEL_DEG], pg = cg[RSS_BESSEL_DEG];
 #pragma unroll
-    for (int k = RSS_BESSEL_DEG; k >= 1; --k) {
-      double nj = fma(t2, bj1, cj[k] - bj2);
-      double ng = fma(t2, bg1, cg[k] - bg2);
-      bj2 = bj1;
-      bj1 = nj;
-      bg2 = bg1;
-      bg1 = ng;
+    for (int k = RSS_BESSEL_DEG - 1; k >= 0; --k) {
+      pj = fma(pj, t, cj[k]);
+      pg = fma(pg, t, cg[k]);
     }
-    j0 = fma(t, bj1, cj[0] - bj2);
-    const double g = fma(t, bg1, cg[0] - bg2);
-    y0 = fma(TWO_OVER_PI * log(0.5 * x), j0, g);
+    j0 = pj;
+    y0 = fma(TWO_OVER_PI * log(0.5 * x), pj, pg);
   } else {
     const double ix = 1.0 / x;  // one division; u, Q / x and the amplitude reuse it
     const double u = ix * ix;

@@ -25,6 +25,13 @@ constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
 #ifndef RSS_CPQR_MG_CH
 #define RSS_CPQR_MG_CH 4
 #endif
+// threads per workgroup of the sparsification and of the redundant-block inverse
+#ifndef RSS_SPARSIFY_NT
+#define RSS_SPARSIFY_NT 1024
+#endif
+#ifndef RSS_INVERSE_NT
+#define RSS_INVERSE_NT 512
+#endif
 // columns a wave of the multi-workgroup QR updates together
 #ifndef RSS_CPQR_MG_CB
 #define RSS_CPQR_MG_CB 4
@@ -729,7 +736,7 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 // part 0: the box's own block; part 1 + j: neighbour j (ascending id).
 // ---------------------------------------------------------------------------
 template <class R>
-__global__ __launch_bounds__(256) void k_sparsify(const Prob<R>* probs, Phase<R> ph) {
+__global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph) {
   const int slot = blockIdx.x, b = ph.box[slot];
   const Level<R> L = probs[ph.prob[slot]].L;
   const Records<R> rec = probs[ph.prob[slot]].rec;
@@ -810,7 +817,7 @@ __global__ __launch_bounds__(256) void k_sparsify(const Prob<R>* probs, Phase<R>
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(256), 0, s, probs, ph);
+  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(RSS_SPARSIFY_NT), 0, s, probs, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -940,7 +947,8 @@ void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int 
   const size_t room = head < (size_t)(150 * 1024) ? (size_t)(150 * 1024) - head : 0;
   const size_t cap = std::min({(size_t)nmax * nmax, (size_t)(96 * 1024) / E, room / E});
   const size_t shm = head + cap * E;
-  hipLaunchKernelGGL((k_inverse<R, 256>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, errflag, head,
+  hipLaunchKernelGGL((k_inverse<R, RSS_INVERSE_NT>), dim3(ph.nbox), dim3(RSS_INVERSE_NT), shm, s, probs, ph,
+                     errflag, head,
                      cap);
 }
 

@@ -1038,29 +1038,59 @@ void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* de
 }
 
 // ---------------------------------------------------------------------------
-// batched ragged complex GEMM: C = (beta C) + sign * A B, 64 x 64 tiles,
-// 256 threads each owning a 4 x 4 patch (rows tx + 16 a, cols ty + 16 b).
-// In the complex64 form each 16-deep slice of the sum is accumulated in FP32
-// and the slices are added in FP64, which keeps the rounding error of long
-// sums near that of one slice.
+// batched ragged complex GEMM on the matrix cores: C = (beta C) + sign * A B.
+// 64 x 64 tiles, 16-deep K slices staged in LDS; each of the 4 waves owns a
+// 32 x 32 quarter as 2 x 2 blocks of 16 x 16 and computes the transposed
+// block B^T A^T with the 16x16x4 MFMA (so that consecutive lanes hold
+// consecutive rows of the column-major C).  Complex products take four real
+// MFMAs: re += br ar - bi ai, im += bi ar + br ai.  In the complex64 form each
+// K slice is accumulated in FP32 and the slices are added in FP64.
 // ---------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef mf_d4 acc;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in slot v of lane l
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef mf_f4 acc;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
 template <class R>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles_m) {
+  using M = Mfma<R>;
+  using acc_t = typename M::acc;
   __shared__ cx<R> As[16][64];
   __shared__ cx<R> Bs[16][65];
   const GemmDesc<R> d = desc[blockIdx.x];
   const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
   const int i0 = tm * 64, j0 = tn * 64;
   if (i0 >= d.M || j0 >= d.N) return;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  cx<R> acc[4][4];
-  cx<double> accd[4][4];  // complex64 form: FP64 sum of the per-tile FP32 sums
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+  acc_t cr[2][2], ci[2][2];
+  double fr[2][2][4], fi[2][2][4];  // complex64 form: FP64 sum of the slices
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      acc[a][c] = czero<R>();
-      accd[a][c] = czero<double>();
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = acc_t{0, 0, 0, 0};
+      ci[a][b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) fr[a][b][v] = fi[a][b][v] = 0.0;
     }
   for (int k0 = 0; k0 < d.K; k0 += 16) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -1073,40 +1103,56 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      cx<R> av[4], bv[4];
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const int kk = k4 + (l >> 4);
+      cx<R> av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wi + 16 * a + (l & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][ty + 16 * c];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wj + 16 * b + (l & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fma_(acc[a][c], av[a], bv[c]);
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = M::mac(bv[b].x, av[a].x, cr[a][b]);
+          cr[a][b] = M::mac(-bv[b].y, av[a].y, cr[a][b]);
+          ci[a][b] = M::mac(bv[b].y, av[a].x, ci[a][b]);
+          ci[a][b] = M::mac(bv[b].x, av[a].y, ci[a][b]);
+        }
     }
     __syncthreads();
     if constexpr (sizeof(R) != sizeof(double)) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          accd[a][c] = accd[a][c] + to_d(acc[a][c]);
-          acc[a][c] = czero<R>();
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            fr[a][b][v] += (double)cr[a][b][v];
+            fi[a][b][v] += (double)ci[a][b][v];
+          }
+          cr[a][b] = acc_t{0, 0, 0, 0};
+          ci[a][b] = acc_t{0, 0, 0, 0};
         }
     }
   }
-  const R sg = (R)d.sign;
+  // block (a, b) holds rows wi + 16 a + (l & 15) of C and columns wj + 16 b + M::row(l, v)
+  const double sg = (double)d.sign;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * c;
-      if (gi < d.M && gj < d.N) {
-        cx<R>* p = d.C + gi + (int64_t)gj * d.ldc;
-        const cx<R> v = sizeof(R) == sizeof(double) ? sg * acc[a][c] : from_cd<R>((double)sg * accd[a][c]);
-        *p = d.beta ? (*p + v) : v;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wi + 16 * a + (l & 15), gj = j0 + wj + 16 * b + M::row(l, v);
+        if (gi < d.M && gj < d.N) {
+          const double re = sizeof(R) == sizeof(double) ? (double)cr[a][b][v] : fr[a][b][v];
+          const double im = sizeof(R) == sizeof(double) ? (double)ci[a][b][v] : fi[a][b][v];
+          cx<R>* p = d.C + gi + (int64_t)gj * d.ldc;
+          const cx<R> val{(R)(sg * re), (R)(sg * im)};
+          *p = d.beta ? (*p + val) : val;
+        }
       }
-    }
 }
 
 template <class R>

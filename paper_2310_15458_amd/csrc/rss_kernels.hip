@@ -32,6 +32,10 @@ constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
 #ifndef RSS_INVERSE_NT
 #define RSS_INVERSE_NT 512
 #endif
+// most workgroups per box in the multi-workgroup QR
+#ifndef RSS_CPQR_MG_GMAX
+#define RSS_CPQR_MG_GMAX 8
+#endif
 // columns a wave of the multi-workgroup QR updates together
 #ifndef RSS_CPQR_MG_CB
 #define RSS_CPQR_MG_CB 4
@@ -712,7 +716,7 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax) {
   }
   int G = cap / (nbox > 0 ? nbox : 1);
   G = min(G, max(1, mmax / 128));
-  return G;
+  return min(G, RSS_CPQR_MG_GMAX);
 }
 
 template <class R>

@@ -217,6 +217,43 @@ def test_fp32_refinement_matches_oracle(torch_cuda):
     assert _rel(x, xo) <= 1e-10
 
 
+def test_fp32_factor_accuracy(torch_cuda):
+    """The complex64 form's factors: one application leaves relres <= 2e-4 on
+    Helmholtz kappa=50, n=96 (leaf 64), and refinement reaches 1e-10 within 3
+    steps (the redundant-block and root inverses are formed in FP64)."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n, leaf = 96, 64
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, 50.0)
+    B = W.rhs(n * n, 4, 0)
+    F = rss.Factorization(P, k, 1e-6, leaf, precision="fp32", n_proxy=128)
+    Bd = _dev(torch, B)
+    F.apply(Bd)
+    rr = omv.relres(omv.fft_matvec(k, n, _host(Bd)), B)
+    print(f"single application relres {rr:.2e}", flush=True)
+    assert rr <= 2e-4
+    Bd = _dev(torch, B)
+    assert F.solve(Bd) == 0
+    info = F.info()
+    assert info["last_relres"] <= 1e-10 and info["last_iters"] <= 3, info["last_iters"]
+
+
+def test_residual_column_chunks(torch_cuda):
+    """nrhs = 21 runs as column chunks of 16, 4 and 1; every column equals the
+    FFT product to 1e-13."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n = 24
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, 20.0)
+    X = W.rhs(n * n, 21, 5)
+    B = W.rhs(n * n, 21, 6)
+    R = _host(rss.residual(k, torch.from_numpy(P).cuda(), _dev(torch, X), _dev(torch, B)))
+    ref = B - omv.fft_matvec(k, n, X)
+    assert np.abs(R - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_fp64_refinement(torch_cuda):
     torch = torch_cuda
     from paper_2310_15458_amd import rss

@@ -20,6 +20,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "rss.h"
@@ -124,6 +125,61 @@ struct Arena {
   }
 };
 
+// Gathers small host arrays into one staging buffer (256-byte aligned pieces)
+// that flush() uploads with a single copy into one device block from the given
+// allocator, then points every registered destination into that block.
+// Destinations must stay where they are until flush().
+struct Packer {
+  std::vector<char> buf;
+  std::vector<std::pair<void**, size_t>> refs;
+  size_t reserve(size_t bytes) {
+    const size_t off = (buf.size() + 255) & ~(size_t)255;
+    buf.resize(off + std::max<size_t>(bytes, 16), 0);
+    return off;
+  }
+  template <class T, class U>
+  void add(T*& dst, const std::vector<U>& v) {
+    static_assert(std::is_same<typename std::remove_const<T>::type, U>::value, "element type");
+    const size_t off = reserve(v.size() * sizeof(U));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(U));
+    refs.emplace_back((void**)&dst, off);
+  }
+  template <class T>
+  void zeros(T*& dst, size_t n) {
+    refs.emplace_back((void**)&dst, reserve(n * sizeof(T)));
+  }
+  template <class A>
+  void* flush(A& alloc, hipStream_t s) {
+    if (refs.empty()) return nullptr;
+    char* d = (char*)alloc.alloc(buf.size());
+    HIPCHK(hipMemcpyAsync(d, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+    for (auto& r : refs) *r.first = d + r.second;
+    buf.clear();
+    refs.clear();
+    return d;
+  }
+};
+
+// page-locked host buffer for readbacks; grows on demand
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  void* get(size_t n) {
+    if (n > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      n = std::max(n, (size_t)1 << 20);
+      HIPCHK(hipHostMalloc(&p, n, hipHostMallocDefault));
+      cap = n;
+    }
+    return p;
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 int chebyshev(int nb, int a, int b) {
   return std::max(std::abs(a % nb - b % nb), std::abs(a / nb - b / nb));
 }
@@ -152,6 +208,7 @@ struct LevelHost {
   int* d_idx = nullptr;
   int64_t* d_ioff = nullptr;
   int64_t* d_boff = nullptr;
+  void* d_blk = nullptr;  // one block holding d_n0 .. d_boff
   void* d_A = nullptr;
 
   void layout(int depth, const std::vector<int>& counts) {
@@ -373,25 +430,24 @@ Records<R> dev_records(const DepthRecords& d) {
   return r;
 }
 
+// d_cur and d_idx are adjacent so that one copy reads both back
 void alloc_level(rss_ctx* h, LevelHost& L, size_t elem, hipStream_t s) {
-  L.d_n0 = h->arena.up(L.n0, s);
-  L.d_cur = h->arena.up(L.n0, s);
-  L.d_idx = h->arena.up(L.idx, s);
-  L.d_ioff = h->arena.up(L.ioff, s);
-  L.d_boff = h->arena.up(L.boff, s);
+  Packer pk;
+  pk.add(L.d_n0, L.n0);
+  pk.add(L.d_cur, L.n0);
+  pk.add(L.d_idx, L.idx);
+  pk.add(L.d_ioff, L.ioff);
+  pk.add(L.d_boff, L.boff);
+  L.d_blk = pk.flush(h->arena, s);
   L.d_A = h->arena.alloc((size_t)L.nA * elem);
 }
 
 void free_level(rss_ctx* h, LevelHost& L) {
-  h->arena.release(L.d_n0);
-  h->arena.release(L.d_cur);
-  h->arena.release(L.d_idx);
-  h->arena.release(L.d_ioff);
-  h->arena.release(L.d_boff);
+  h->arena.release(L.d_blk);
   h->arena.release(L.d_A);
   L.d_n0 = L.d_cur = L.d_idx = nullptr;
   L.d_ioff = L.d_boff = nullptr;
-  L.d_A = nullptr;
+  L.d_blk = L.d_A = nullptr;
 }
 
 // temporary device buffers of one batched operation; clear() (after the
@@ -555,6 +611,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     }
   }
   Scratch scr;
+  PinnedBuf pinned;
   // leaf stencils of every problem: one launch
   {
     std::vector<Prob<R>> probs;
@@ -612,19 +669,6 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         dr.snmax = std::max(dr.snmax, n + nN0);
       }
       dr.kmax = dr.rmax = cur.nmax;
-      dr.d_k = (int*)h->arena.alloc(nbox * sizeof(int));
-      dr.d_r = (int*)h->arena.alloc(nbox * sizeof(int));
-      dr.d_nN = (int*)h->arena.alloc(nbox * sizeof(int));
-      HIPCHK(hipMemsetAsync(dr.d_k, 0, nbox * sizeof(int), s));
-      HIPCHK(hipMemsetAsync(dr.d_r, 0, nbox * sizeof(int), s));
-      HIPCHK(hipMemsetAsync(dr.d_nN, 0, nbox * sizeof(int), s));
-      dr.d_oT = h->arena.up(oT, s);
-      dr.d_oXi = h->arena.up(oXi, s);
-      dr.d_oXSNR = h->arena.up(oXSNR, s);
-      dr.d_oY = h->arena.up(oY, s);
-      dr.d_oS = h->arena.up(oS, s);
-      dr.d_oR = h->arena.up(oR, s);
-      dr.d_oN = h->arena.up(oN, s);
       dr.d_F = h->arena.alloc((size_t)F * E);
       dr.d_G = (int*)h->arena.alloc((size_t)G * sizeof(int));
       // per-problem phase lists (kept for the solve)
@@ -632,11 +676,30 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         PhaseHost& P = dr.ph[c];
         for (int b = 0; b < nbox; ++b)
           if ((b % nb) % 3 + 3 * ((b / nb) % 3) == c && cur.n0[b] > 0) P.boxes.push_back(b);
-        P.d_box = h->arena.up(P.boxes, s);
-        std::vector<int> zeros(P.boxes.size(), 0);
-        P.d_prob = h->arena.up(zeros, s);
       }
       h->recs.push_back(std::move(dr));
+      {
+        // ranks (zeroed; k, r, nN adjacent for one readback), offsets and phase
+        // lists of this depth in one upload
+        DepthRecords& rd = h->recs.back();
+        Packer pk;
+        pk.zeros(rd.d_k, nbox);
+        pk.zeros(rd.d_r, nbox);
+        pk.zeros(rd.d_nN, nbox);
+        pk.add(rd.d_oT, oT);
+        pk.add(rd.d_oXi, oXi);
+        pk.add(rd.d_oXSNR, oXSNR);
+        pk.add(rd.d_oY, oY);
+        pk.add(rd.d_oS, oS);
+        pk.add(rd.d_oR, oR);
+        pk.add(rd.d_oN, oN);
+        for (int c = 0; c < 9; ++c) {
+          PhaseHost& P = rd.ph[c];
+          pk.add(P.d_box, P.boxes);
+          pk.zeros(P.d_prob, P.boxes.size());
+        }
+        pk.flush(h->arena, s);
+      }
       Prob<R>& pr = probs[a];
       pr.L = dev_level<R>(cur, h->x0, h->y0, h->s0);
       pr.rec = dev_records<R>(h->recs.back());
@@ -649,7 +712,9 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       nNmax = std::max(nNmax, cur.nNmax);
       mmax = std::max(mmax, 2 * cur.msum_max + 2 * h->opt.n_proxy);
     }
-    Prob<R>* d_probs = scr.up(probs, s);
+    Prob<R>* d_probs = nullptr;
+    Packer pk;  // problem descriptors and merged phase lists of this height: one upload
+    pk.add(d_probs, probs);
     // merged colour phases over all active problems, and one shared workspace
     struct Merged {
       std::vector<int> box, prob;
@@ -715,22 +780,28 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     int* mrow = (int*)scr.alloc((size_t)9 * std::max(1, maxph) * sizeof(int));
     GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
     const int chunks = (mmax + 63) / 64;
+    Phase<R> phs[9];
     for (int c = 0; c < 9; ++c) {
       Merged& G = M[c];
       if (G.box.empty()) continue;
-      Phase<R> ph;
+      Phase<R>& ph = phs[c];
       ph.nbox = (int)G.box.size();
-      ph.box = scr.up(G.box, s);
-      ph.prob = scr.up(G.prob, s);
-      ph.oC = scr.up(G.oC, s);
-      ph.oX = scr.up(G.oX, s);
-      ph.oZ = scr.up(G.oZ, s);
-      ph.oI = scr.up(G.oI, s);
+      pk.add(ph.box, G.box);
+      pk.add(ph.prob, G.prob);
+      pk.add(ph.oC, G.oC);
+      pk.add(ph.oX, G.oX);
+      pk.add(ph.oZ, G.oZ);
+      pk.add(ph.oI, G.oI);
+      pk.add(ph.oD, G.oD);
       ph.mrow = mrow + (size_t)c * std::max(1, maxph);
       ph.W = (cx<R>*)Wd;
       ph.Wi = Wi;
       ph.Wd = Wdd;
-      ph.oD = scr.up(G.oD, s);
+    }
+    pk.flush(scr, s);
+    for (int c = 0; c < 9; ++c) {
+      if (M[c].box.empty()) continue;
+      const Phase<R>& ph = phs[c];
       prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
       prof.run(RSS_K_ID, s, [&] {
         if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
@@ -760,14 +831,38 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       dr.m.assign(nbox, 0);
       curk[a].resize(nbox);
       ids[a].resize(cur.idx.size());
-      HIPCHK(hipMemcpyAsync(dr.k.data(), dr.d_k, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(dr.r.data(), dr.d_r, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(dr.nN.data(), dr.d_nN, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(curk[a].data(), cur.d_cur, nbox * sizeof(int), hipMemcpyDeviceToHost, s));
-      if (!ids[a].empty())
-        HIPCHK(hipMemcpyAsync(ids[a].data(), cur.d_idx, ids[a].size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    // two copies per problem (k .. nN and cur .. idx are adjacent) into pinned memory
+    std::vector<size_t> rb_off(2 * act.size() + 1, 0);
+    for (size_t a = 0; a < act.size(); ++a) {
+      const DepthRecords& dr = H[act[a]]->recs.back();
+      const LevelHost& cur = W[act[a]].cur;
+      rb_off[2 * a + 1] = rb_off[2 * a] + (size_t)((char*)(dr.d_nN + dr.k.size()) - (char*)dr.d_k);
+      rb_off[2 * a + 2] = rb_off[2 * a + 1] + (size_t)((char*)(cur.d_idx + cur.idx.size()) - (char*)cur.d_cur);
+    }
+    char* rb = (char*)pinned.get(rb_off.back());
+    for (size_t a = 0; a < act.size(); ++a) {
+      const DepthRecords& dr = H[act[a]]->recs.back();
+      const LevelHost& cur = W[act[a]].cur;
+      HIPCHK(hipMemcpyAsync(rb + rb_off[2 * a], dr.d_k, rb_off[2 * a + 1] - rb_off[2 * a],
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(rb + rb_off[2 * a + 1], cur.d_cur, rb_off[2 * a + 2] - rb_off[2 * a + 1],
+                            hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    for (size_t a = 0; a < act.size(); ++a) {
+      DepthRecords& dr = H[act[a]]->recs.back();
+      const LevelHost& cur = W[act[a]].cur;
+      const size_t nbox = dr.k.size();
+      const char* p0 = rb + rb_off[2 * a];
+      std::memcpy(dr.k.data(), p0, nbox * sizeof(int));
+      std::memcpy(dr.r.data(), p0 + ((char*)dr.d_r - (char*)dr.d_k), nbox * sizeof(int));
+      std::memcpy(dr.nN.data(), p0 + ((char*)dr.d_nN - (char*)dr.d_k), nbox * sizeof(int));
+      const char* p1 = rb + rb_off[2 * a + 1];
+      std::memcpy(curk[a].data(), p1, nbox * sizeof(int));
+      if (!ids[a].empty())
+        std::memcpy(ids[a].data(), p1 + ((char*)cur.d_idx - (char*)cur.d_cur), ids[a].size() * sizeof(int));
+    }
     for (size_t a = 0; a < act.size(); ++a) {
       // the solve sizes its LDS panels by the ranks the level actually has
       DepthRecords& dr = H[act[a]]->recs.back();

@@ -1023,15 +1023,16 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       const size_t bytes = (size_t)nr * nr * E;
       RootDesc<R> rd;
       rd.A = (cx<R>*)h->arena.alloc(bytes);
-      rd.keys = (unsigned long long*)scr.alloc((size_t)nr * 8);
-      HIPCHK(hipMemsetAsync(rd.keys, 0, (size_t)nr * 8, s));
       rd.perm = (int*)scr.alloc((size_t)nr * 2 * sizeof(int));
       rd.n = nr;
+      rd.W = nullptr;
+      rd.gd = nullptr;
       if (f32) {
         RootDesc<double> r64;
         r64.A = (cx<double>*)scr.alloc((size_t)nr * nr * sizeof(cx<double>));
         r64.tmp = (cx<double>*)scr.alloc((size_t)nr * nr * sizeof(cx<double>));
-        r64.keys = rd.keys;
+        r64.W = (cx<double>*)scr.alloc(root_work_elems(nr) * sizeof(cx<double>));
+        r64.gd = nullptr;
         r64.perm = rd.perm;
         r64.n = nr;
         rds64.push_back(r64);
@@ -1041,9 +1042,10 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         h->root_spare = nullptr;
       } else {
         rd.tmp = (cx<R>*)h->arena.alloc(bytes);
-        // the inverse ends in A for odd n, in tmp for even n
-        h->d_root_inv = (nr & 1) ? (void*)rd.A : (void*)rd.tmp;
-        h->root_spare = (nr & 1) ? (void*)rd.tmp : (void*)rd.A;
+        rd.W = (cx<R>*)scr.alloc(root_work_elems(nr) * sizeof(cx<R>));
+        // the inverse ends in tmp
+        h->d_root_inv = (void*)rd.tmp;
+        h->root_spare = (void*)rd.A;
       }
       rds.push_back(rd);
       Prob<R> cp{};
@@ -1073,6 +1075,11 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       PairDesc* d_pds = scr.up(pds, s);
       ListEntry* d_lists = scr.up(lists, s);
       Prob<R>* d_cp = scr.up(cprobs, s);
+      // one update-product descriptor per problem, rewritten by every panel
+      GemmDesc<R>* gdR = (GemmDesc<R>*)scr.alloc(rds.size() * sizeof(GemmDesc<R>));
+      GemmDesc<double>* gd64 = (GemmDesc<double>*)scr.alloc(rds64.size() * sizeof(GemmDesc<double>));
+      for (size_t i = 0; i < rds.size(); ++i) rds[i].gd = gdR + i;
+      for (size_t i = 0; i < rds64.size(); ++i) rds64[i].gd = gd64 + i;
       RootDesc<R>* d_rd = scr.up(rds, s);
       prof.run(RSS_K_ASSEMBLE, s, [&] {
         launch_assemble_pairs<R>(d_pds, (int)pds.size(), d_lists, nrmax, nrmax, d_cp, s);
@@ -1085,14 +1092,13 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
             launch_axpy_from_c64((const cx<float>*)rds[i].A, nn, 1, nullptr, rds64[i].A, s);
           }
           RootDesc<double>* d_rd64 = scr.up(rds64, s);
-          launch_root_inverse<double>(d_rd64, (int)rds64.size(), nrmax, d_err, s);
+          launch_root_inverse<double>(d_rd64, (int)rds64.size(), nrmax, gd64, d_err, s);
           for (size_t i = 0; i < rds64.size(); ++i) {
             const int nn = rds64[i].n;
-            const cx<double>* res = (nn & 1) ? rds64[i].A : rds64[i].tmp;
-            launch_cast_c64(res, (int64_t)nn * nn, 1, (cx<float>*)root_out[i], s);
+            launch_cast_c64(rds64[i].tmp, (int64_t)nn * nn, 1, (cx<float>*)root_out[i], s);
           }
         } else {
-          launch_root_inverse<R>(d_rd, (int)rds.size(), nrmax, d_err, s);
+          launch_root_inverse<R>(d_rd, (int)rds.size(), nrmax, gdR, d_err, s);
         }
       });
       HIPCHK(hipGetLastError());

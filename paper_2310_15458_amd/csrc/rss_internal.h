@@ -116,10 +116,11 @@ struct PairDesc {
 // dense root of one problem: in-place Gauss-Jordan over A / tmp
 template <class R>
 struct RootDesc {
-  cx<R>* A;
-  cx<R>* tmp;
-  unsigned long long* keys;
-  int* perm;     // 2 n ints
+  cx<R>* A;        // n x n, inverted in place (before the final column interchanges)
+  cx<R>* tmp;      // n x n: the inverse
+  cx<R>* W;        // root_work_elems(n) entries: panel copy, panel rows, one column
+  GemmDesc<R>* gd; // this problem's update product of the current panel
+  int* perm;       // 2 n ints
   int n;
 };
 struct ListEntry {
@@ -165,7 +166,10 @@ template <class R>
 void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
                            int max_c, const Prob<R>* child, hipStream_t s);
 template <class R>
-void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errflag, hipStream_t s);
+void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, GemmDesc<R>* gd, int* errflag,
+                         hipStream_t s);
+// workspace entries of RootDesc::W for a root of size n
+size_t root_work_elems(int n);
 // solve sweeps of one colour phase; W: scratch of solve_work_elems entries
 // (qmax: largest k + |N| of the phase's level)
 template <class R>

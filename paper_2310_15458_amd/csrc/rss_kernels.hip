@@ -1335,12 +1335,128 @@ void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* list
 }
 
 // ---------------------------------------------------------------------------
-// root: dense inverse by Gauss-Jordan elimination with partial pivoting, one
-// launch per pivot step for all problems of a batch (ping-pong buffers); the
-// next pivot is chosen by the launch that produces its column (packed |a| /
-// index keys, atomicMax).  After n steps the result (before the final column
-// permutation) is in tmp for odd n and in A for even n.
+// root: dense inverse by blocked Gauss-Jordan elimination with partial
+// pivoting, in place in A, for all problems of a batch.  Per panel of NB
+// columns [k0, k0 + NB): one workgroup per problem runs the NB elimination
+// steps on the panel columns only (pivot search in the current column,
+// interchange of whole rows, the Gauss-Jordan update of the panel); the
+// elimination then reaches every other column X as one product,
+//   X <- [X with the panel rows zeroed] + W X_P,
+// W = the panel columns after the NB steps, X_P = the panel rows of X: one
+// batched GEMM launch (matrix cores) per panel.  Finally the row interchanges
+// are undone as column interchanges in reverse order, gathering into tmp.
 // ---------------------------------------------------------------------------
+constexpr int ROOT_NB = 32;
+constexpr int ROOT_FEW = 8;  // batches up to this size use the unblocked form
+
+template <class R>
+__global__ __launch_bounds__(1024) void k_root_panel(const RootDesc<R>* rd, int k0, int* errflag) {
+  constexpr int NT = 1024, NW = NT / 64;
+  __shared__ double rv[NW];
+  __shared__ int ri[NW];
+  __shared__ cx<R> rowk[ROOT_NB];
+  const RootDesc<R> d = rd[blockIdx.x];
+  const int n = d.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) *d.gd = GemmDesc<R>{d.A, d.W, d.W, n, n, ROOT_NB, 0, 0, 0, 1, 1};  // no update
+  if (k0 >= n) return;
+  const int nbp = min(ROOT_NB, n - k0);
+  cx<R>* A = d.A;
+  cx<R>* Wt = d.W;                          // n x nbp (leading dimension n)
+  cx<R>* Xp = Wt + (size_t)n * ROOT_NB;     // nbp x n (leading dimension ROOT_NB)
+  cx<R>* cb = Xp + (size_t)ROOT_NB * n;     // column kk before the step
+  for (int t = 0; t < nbp; ++t) {
+    const int kk = k0 + t;
+    // pivot: largest |A(i, kk)| over i >= kk, smallest i on ties
+    double best = -1.0;
+    int bi = n;
+    for (int i = kk + threadIdx.x; i < n; i += NT) {
+      const double v = abs2d(A[i + (int64_t)kk * n]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double v2 = __shfl_xor(best, o, 64);
+      const int i2 = __shfl_xor(bi, o, 64);
+      if (v2 > best || (v2 == best && i2 < bi)) {
+        best = v2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      rv[wv] = best;
+      ri[wv] = bi;
+    }
+    __syncthreads();
+    best = rv[0];
+    bi = ri[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > best || (rv[w] == best && ri[w] < bi)) {
+        best = rv[w];
+        bi = ri[w];
+      }
+    if (!(best > 0.0) || bi >= n) {
+      if (threadIdx.x == 0) atomicOr(errflag, ERRF_SINGULAR);
+      return;  // uniform
+    }
+    const int p = bi;
+    if (threadIdx.x == 0) d.perm[kk] = p;
+    if (p != kk)
+      for (int j = threadIdx.x; j < n; j += NT) {
+        const cx<R> a = A[kk + (int64_t)j * n];
+        A[kk + (int64_t)j * n] = A[p + (int64_t)j * n];
+        A[p + (int64_t)j * n] = a;
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) cb[i] = A[i + (int64_t)kk * n];
+    if (threadIdx.x < nbp) rowk[threadIdx.x] = A[kk + (int64_t)(k0 + threadIdx.x) * n];
+    __syncthreads();
+    const cx<R> akk = rowk[t];
+    const double dd = abs2d(akk);
+    const cx<R> pinv{(R)(akk.x / dd), (R)(-akk.y / dd)};
+    for (int e = threadIdx.x; e < n * nbp; e += NT) {
+      const int jj = e / n, i = e - jj * n, j = k0 + jj;
+      const cx<R> aik = cb[i], akj = rowk[jj];
+      cx<R>* a = A + i + (int64_t)j * n;
+      if (j == kk) *a = (i == kk) ? pinv : czero<R>() - aik * pinv;
+      else *a = (i == kk) ? akj * pinv : *a - aik * pinv * akj;
+    }
+    __syncthreads();
+  }
+  // W, X_P (panel columns of X_P zero), and the panel rows of X cleared
+  for (int e = threadIdx.x; e < n * nbp; e += NT) {
+    const int jj = e / n, i = e - jj * n;
+    Wt[i + (int64_t)jj * n] = A[i + (int64_t)(k0 + jj) * n];
+  }
+  for (int e = threadIdx.x; e < nbp * n; e += NT) {
+    const int j = e / nbp, t = e - j * nbp;
+    const bool panel = j >= k0 && j < k0 + nbp;
+    cx<R>* a = A + (k0 + t) + (int64_t)j * n;
+    Xp[t + (int64_t)j * ROOT_NB] = panel ? czero<R>() : *a;
+    if (!panel) *a = czero<R>();
+  }
+  if (threadIdx.x == 0) *d.gd = GemmDesc<R>{A, Wt, Xp, n, n, ROOT_NB, n, n, nbp, 1, 1};
+}
+
+// Few problems: unblocked Gauss-Jordan, one launch per pivot step for all of
+// them (ping-pong buffers, bound by launch latency); the next pivot is chosen
+// by the launch that produces its column (packed |a| / index keys in W,
+// atomicMax).  Pivot keys are zeroed and, for odd n, A is copied to tmp first.
+template <class R>
+__global__ __launch_bounds__(256) void k_root_prep(const RootDesc<R>* rd) {
+  const RootDesc<R> d = rd[blockIdx.y];
+  const int n = d.n;
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(d.W);
+  const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * 256) keys[e] = 0ull;
+  if (n & 1)
+    for (int64_t e = e0; e < (int64_t)n * n; e += (int64_t)gridDim.x * 256) d.tmp[e] = d.A[e];
+}
+
 __device__ __forceinline__ unsigned long long pivkey(double a2, int i) {
   const float f = (float)sqrt(a2);
   return ((unsigned long long)__float_as_uint(f) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
@@ -1350,6 +1466,7 @@ template <class R>
 __global__ __launch_bounds__(256) void k_root_pivot0(const RootDesc<R>* rd) {
   __shared__ unsigned long long red[256];
   const RootDesc<R> d = rd[blockIdx.x];
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(d.W);
   unsigned long long best = 0;
   for (int i = threadIdx.x; i < d.n; i += 256) {
     const unsigned long long kk = pivkey(abs2d(d.A[i]), i);
@@ -1361,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_root_pivot0(const RootDesc<R>* rd) {
     if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) d.keys[0] = red[0];
+  if (threadIdx.x == 0) keys[0] = red[0];
 }
 
 template <class R>
@@ -1369,11 +1486,14 @@ __global__ __launch_bounds__(256) void k_root_gj(const RootDesc<R>* rd, int kk, 
   const RootDesc<R> d = rd[blockIdx.z];
   const int n = d.n;
   if (kk >= n) return;
-  const cx<R>* src = (kk & 1) ? d.tmp : d.A;
-  cx<R>* dst = (kk & 1) ? d.A : d.tmp;
+  // buffers alternate so that step n - 1 writes A: odd n starts from the copy in tmp
+  const bool fromtmp = ((kk ^ n) & 1) != 0;
+  const cx<R>* src = fromtmp ? d.tmp : d.A;
+  cx<R>* dst = fromtmp ? d.A : d.tmp;
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(d.W);
   const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   if (i0 >= n || j0 >= n) return;
-  const unsigned long long key = d.keys[kk];
+  const unsigned long long key = keys[kk];
   const int p = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
   const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4);
   if (key == 0ull || p < kk || p >= n) {  // no pivot recorded (an earlier step was singular)
@@ -1410,14 +1530,13 @@ __global__ __launch_bounds__(256) void k_root_gj(const RootDesc<R>* rd, int kk, 
       if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
       __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0]) atomicMax(d.keys + kk + 1, red[0]);
+    if (threadIdx.x == 0 && red[0]) atomicMax(keys + kk + 1, red[0]);
   }
 }
 
-// undo the row interchanges: the column interchanges in reverse order, then
-// gather the columns into the other buffer (result: A for odd n, tmp for even n)
+// column interchanges of the row interchanges, in reverse order
 template <class R>
-__global__ __launch_bounds__(256) void k_root_finish(const RootDesc<R>* rd) {
+__global__ __launch_bounds__(64) void k_root_finish(const RootDesc<R>* rd) {
   const RootDesc<R> d = rd[blockIdx.y];
   const int n = d.n;
   int* cp = d.perm + n;
@@ -1439,24 +1558,36 @@ __global__ __launch_bounds__(256) void k_root_gather(const RootDesc<R>* rd) {
   const int n = d.n;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)n * n) return;
-  const cx<R>* src = (n & 1) ? d.tmp : d.A;
-  cx<R>* dst = (n & 1) ? d.A : d.tmp;
   const int i = (int)(e % n), j = (int)(e / n);
-  dst[e] = src[i + (int64_t)d.perm[n + j] * n];
+  d.tmp[e] = d.A[i + (int64_t)d.perm[n + j] * n];
 }
 
+// gd: one GemmDesc per problem (device); the inverse ends in tmp
 template <class R>
-void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, int* errflag, hipStream_t s) {
+void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, GemmDesc<R>* gd, int* errflag,
+                         hipStream_t s) {
   if (nprob == 0 || nmax == 0) return;
-  hipLaunchKernelGGL(k_root_pivot0<R>, dim3(nprob), dim3(256), 0, s, rd);
-  const int t = (nmax + 15) / 16;
-  for (int kk = 0; kk < nmax; ++kk)
-    hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t, nprob), dim3(256), 0, s, rd, kk, errflag);
+  if (nprob <= ROOT_FEW) {
+    const int64_t tot = (int64_t)nmax * nmax;
+    hipLaunchKernelGGL(k_root_prep<R>, dim3((unsigned)std::min<int64_t>(4096, (tot + 255) / 256), nprob), dim3(256),
+                       0, s, rd);
+    hipLaunchKernelGGL(k_root_pivot0<R>, dim3(nprob), dim3(256), 0, s, rd);
+    const int t = (nmax + 15) / 16;
+    for (int kk = 0; kk < nmax; ++kk)
+      hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t, nprob), dim3(256), 0, s, rd, kk, errflag);
+  } else {
+    for (int k0 = 0; k0 < nmax; k0 += ROOT_NB) {
+      hipLaunchKernelGGL(k_root_panel<R>, dim3(nprob), dim3(1024), 0, s, rd, k0, errflag);
+      launch_gemm<R>(gd, nprob, nmax, nmax, s);
+    }
+  }
   hipLaunchKernelGGL(k_root_finish<R>, dim3(1, nprob), dim3(64), 0, s, rd);
   const int64_t tot = (int64_t)nmax * nmax;
   hipLaunchKernelGGL(k_root_gather<R>, dim3((unsigned)((tot + 255) / 256), nprob), dim3(256), 0, s,
                      rd);
 }
+
+size_t root_work_elems(int n) { return (size_t)2 * n * ROOT_NB + (size_t)n; }
 
 // ---------------------------------------------------------------------------
 // solve sweeps (Sec. 2.6)
@@ -2090,7 +2221,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t);                    \
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
                                          const Prob<R>*, hipStream_t);                             \
-  template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t);           \
+  template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t);           \
   template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \
                                     cx<R>*, hipStream_t);                                          \
   template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \

@@ -16,7 +16,8 @@ template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStrea
 template <class R> void launch_plan_schur(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
 template <class R> void launch_gemm(const GemmDesc<R>*, int, int, int, hipStream_t) {}
 template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
-template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, int*, hipStream_t) {}
+template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t) {}
+size_t root_work_elems(int n) { return (size_t)65 * n; }
 template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
 template <class R> size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs) { return (size_t)nbox * rmax * nrhs + qmax; }
 template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
@@ -35,7 +36,7 @@ template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
 template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
 template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
 template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \
-template void launch_root_inverse<R>(const RootDesc<R>*, int, int, int*, hipStream_t); \
+template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t); \
 template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \
 template size_t solve_work_elems<R>(int, int, int, int); \
 template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \

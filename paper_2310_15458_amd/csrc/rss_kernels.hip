@@ -855,18 +855,9 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
                                           : ph.Wd + ph.oD[slot];
   for (int e = threadIdx.x; e < r * r; e += NT) A[e] = to_d(X[e]);
   const int i0 = threadIdx.x % r, j0 = threadIdx.x / r, di = NT % r, dj = NT / r;
-  __syncthreads();
-  for (int kk = 0; kk < r; ++kk) {
-    // pivot: largest |A(i, kk)| for i >= kk, smallest i on ties
-    double best = -1.0;
-    int bi = kk;
-    for (int i = kk + threadIdx.x; i < r; i += NT) {
-      const double v = abs2d(A[i + (int64_t)kk * r]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
+  // wave partials of the pivot search of column kk: for kk = 0 here, later
+  // folded into the elimination of step kk - 1
+  auto wave_pivot = [&](double best, int bi) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       const double v2 = __shfl_xor(best, o, 64);
@@ -880,8 +871,25 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
       rv[wv] = best;
       ri[wv] = bi;
     }
+  };
+  {
     __syncthreads();
-    best = rv[0];
+    double best = -1.0;
+    int bi = r;
+    for (int i = threadIdx.x; i < r; i += NT) {
+      const double v = abs2d(A[i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    wave_pivot(best, bi);
+  }
+  __syncthreads();
+  for (int kk = 0; kk < r; ++kk) {
+    // pivot: largest |A(i, kk)| for i >= kk, smallest i on ties
+    double best = rv[0];
+    int bi = ri[0];
     bi = ri[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w)
@@ -910,11 +918,23 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
       rowk[i] = i == kk ? pinv : A[kk + (int64_t)i * r] * pinv;
     }
     __syncthreads();
-    // every entry once; (i, j) of e = tid + NT t advanced without a division
+    // every entry once; (i, j) of e = tid + NT t advanced without a division;
+    // the entries of column kk + 1 below the diagonal feed the next pivot search
+    double nb = -1.0;
+    int nbi = r;
     for (int e = threadIdx.x, i = i0, j = j0; e < r * r; e += NT) {
-      if (i == kk) A[e] = rowk[j];
-      else if (j == kk) A[e] = czero<double>() - colk[i] * pinv;
-      else A[e] = A[e] - colk[i] * rowk[j];
+      cx<double> v;
+      if (i == kk) v = rowk[j];
+      else if (j == kk) v = czero<double>() - colk[i] * pinv;
+      else v = A[e] - colk[i] * rowk[j];
+      A[e] = v;
+      if (j == kk + 1 && i > kk) {
+        const double a2 = abs2d(v);
+        if (a2 > nb || (a2 == nb && i < nbi)) {
+          nb = a2;
+          nbi = i;
+        }
+      }
       i += di;
       j += dj;
       if (i >= r) {
@@ -922,6 +942,7 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
         ++j;
       }
     }
+    wave_pivot(nb, nbi);
     __syncthreads();
   }
   // undo the row interchanges as column interchanges in reverse order: final
@@ -947,9 +968,11 @@ void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int 
   if (ph.nbox == 0) return;
   const size_t E = sizeof(cx<double>);
   const size_t head = ((size_t)nmax * (2 * E + 2 * sizeof(int)) + 15) & ~(size_t)15;
-  // the block itself in LDS up to 96 KiB (r <= 78), within 150 KiB of dynamic LDS in total
-  const size_t room = head < (size_t)(150 * 1024) ? (size_t)(150 * 1024) - head : 0;
-  const size_t cap = std::min({(size_t)nmax * nmax, (size_t)(96 * 1024) / E, room / E});
+  // the block itself in LDS up to 96 KiB (r <= 78) where many boxes share the
+  // CUs; with few boxes (one workgroup per CU anyway) up to the LDS size
+  const size_t lim = ph.nbox <= 512 ? (size_t)(158 * 1024) : (size_t)(150 * 1024);
+  const size_t room = head < lim ? lim - head : 0;
+  const size_t cap = std::min({(size_t)nmax * nmax, ph.nbox <= 512 ? room / E : (size_t)(96 * 1024) / E, room / E});
   const size_t shm = head + cap * E;
   hipLaunchKernelGGL((k_inverse<R, RSS_INVERSE_NT>), dim3(ph.nbox), dim3(RSS_INVERSE_NT), shm, s, probs, ph,
                      errflag, head,

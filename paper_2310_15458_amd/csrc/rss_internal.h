@@ -150,7 +150,7 @@ template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
                     double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s);
 template <class R>
-void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s);
 template <class R>
 void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s);

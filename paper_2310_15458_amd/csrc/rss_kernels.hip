@@ -739,8 +739,25 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 //   X_NR = A_NR - A_NS T         X_RN = A_RN - T^* A_SN
 // part 0: the box's own block; part 1 + j: neighbour j (ascending id).
 // ---------------------------------------------------------------------------
+// sum over s < k of term(s), two accumulators (independent loads in flight)
+template <class F>
+__device__ __forceinline__ cx<double> dot2(int k, F&& term) {
+  cx<double> u0{0.0, 0.0}, u1{0.0, 0.0};
+  int s = 0;
+#pragma unroll 4
+  for (; s + 1 < k; s += 2) {
+    u0 = u0 + term(s);
+    u1 = u1 + term(s + 1);
+  }
+  if (s < k) u0 = u0 + term(s);
+  return u0 + u1;
+}
+
+// LDS: the S and R index lists, then T (k x r) when k r <= tcap
 template <class R>
-__global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph) {
+__global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph, int nmax,
+                                                             int tcap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int slot = blockIdx.x, b = ph.box[slot];
   const Level<R> L = probs[ph.prob[slot]].L;
   const Records<R> rec = probs[ph.prob[slot]].rec;
@@ -759,9 +776,20 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
   }
   if (part > 0 && nbj < 0) return;
   const int n0b = L.n0[b];
-  const int* Sl = ph.Wi + ph.oI[slot];
-  const int* Rl = Sl + n0b;
-  const cx<R>* T = rec.F + rec.oT[b];
+  int* Sl = reinterpret_cast<int*>(smem_raw);
+  int* Rl = Sl + k;
+  cx<R>* Ts = reinterpret_cast<cx<R>*>(smem_raw + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
+  {
+    const int* Sg = ph.Wi + ph.oI[slot];
+    for (int a = threadIdx.x; a < k; a += blockDim.x) Sl[a] = Sg[a];
+    for (int c = threadIdx.x; c < r; c += blockDim.x) Rl[c] = Sg[n0b + c];
+  }
+  const cx<R>* Tg = rec.F + rec.oT[b];
+  const bool tl = k * r <= tcap;
+  if (tl)
+    for (int e = threadIdx.x; e < k * r; e += blockDim.x) Ts[e] = Tg[e];
+  __syncthreads();
+  const cx<R>* T = tl ? Ts : Tg;
   cx<R>* XSNR = rec.F + rec.oXSNR[b];
   const int ldx = k + nN;
   cx<R>* Z = ph.W + ph.oZ[slot];
@@ -771,24 +799,29 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
     const int ld = n0b;
     for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
       const int a = e % k, c = e / k;
-      cx<double> v = to_d(A[Sl[a] + (int64_t)Rl[c] * ld]);
-      for (int s = 0; s < k; ++s) v = v - to_d(A[Sl[a] + (int64_t)Sl[s] * ld]) * to_d(T[s + (int64_t)c * k]);
-      XSNR[a + (int64_t)c * ldx] = from_cd<R>(v);
+      const cx<R>* Ar = A + Sl[a];
+      const cx<R>* Tc = T + (int64_t)c * k;
+      const cx<double> u = dot2(k, [&](int s) { return to_d(Ar[(int64_t)Sl[s] * ld]) * to_d(Tc[s]); });
+      XSNR[a + (int64_t)c * ldx] = from_cd<R>(to_d(Ar[(int64_t)Rl[c] * ld]) - u);
     }
     for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
       const int c = e % r, a = e / r;
-      cx<double> v = to_d(A[Rl[c] + (int64_t)Sl[a] * ld]);
-      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c * k]), to_d(A[Sl[s] + (int64_t)Sl[a] * ld]));
-      Z[c + (int64_t)a * r] = from_cd<R>(v);
+      const cx<R>* Aa = A + (int64_t)Sl[a] * ld;
+      const cx<R>* Tc = T + (int64_t)c * k;
+      const cx<double> u = dot2(k, [&](int s) { return cmulc(to_d(Tc[s]), to_d(Aa[Sl[s]])); });
+      Z[c + (int64_t)a * r] = from_cd<R>(to_d(Aa[Rl[c]]) - u);
     }
     __syncthreads();
     cx<R>* X = ph.W + ph.oX[slot];
     for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
       const int c1 = e % r, c2 = e / r;
-      cx<double> v = to_d(A[Rl[c1] + (int64_t)Rl[c2] * ld]);
-      for (int s = 0; s < k; ++s) v = v - to_d(A[Rl[c1] + (int64_t)Sl[s] * ld]) * to_d(T[s + (int64_t)c2 * k]);
-      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c1 * k]), to_d(XSNR[s + (int64_t)c2 * ldx]));
-      X[c1 + (int64_t)c2 * r] = from_cd<R>(v);
+      const cx<R>* Ar = A + Rl[c1];
+      const cx<R>* T1 = T + (int64_t)c1 * k;
+      const cx<R>* T2 = T + (int64_t)c2 * k;
+      const cx<R>* X2 = XSNR + (int64_t)c2 * ldx;
+      const cx<double> u1 = dot2(k, [&](int s) { return to_d(Ar[(int64_t)Sl[s] * ld]) * to_d(T2[s]); });
+      const cx<double> u2 = dot2(k, [&](int s) { return cmulc(to_d(T1[s]), to_d(X2[s])); });
+      X[c1 + (int64_t)c2 * r] = from_cd<R>(to_d(Ar[(int64_t)Rl[c2] * ld]) - u1 - u2);
     }
     int* gS = rec.G + rec.oS[b];
     int* gR = rec.G + rec.oR[b];
@@ -801,16 +834,18 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
     const int ld1 = L.n0[nbj];
     for (int e = threadIdx.x; e < cn * r; e += blockDim.x) {
       const int i = e % cn, c = e / cn;
-      cx<double> v = to_d(A1[i + (int64_t)Rl[c] * ld1]);
-      for (int s = 0; s < k; ++s) v = v - to_d(A1[i + (int64_t)Sl[s] * ld1]) * to_d(T[s + (int64_t)c * k]);
-      XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(v);
+      const cx<R>* Ai = A1 + i;
+      const cx<R>* Tc = T + (int64_t)c * k;
+      const cx<double> u = dot2(k, [&](int s) { return to_d(Ai[(int64_t)Sl[s] * ld1]) * to_d(Tc[s]); });
+      XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(to_d(Ai[(int64_t)Rl[c] * ld1]) - u);
     }
     const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
     for (int e = threadIdx.x; e < r * cn; e += blockDim.x) {
       const int c = e % r, i = e / r;
-      cx<double> v = to_d(A2[Rl[c] + (int64_t)i * n0b]);
-      for (int s = 0; s < k; ++s) v = v - cmulc(to_d(T[s + (int64_t)c * k]), to_d(A2[Sl[s] + (int64_t)i * n0b]));
-      Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(v);
+      const cx<R>* Ai = A2 + (int64_t)i * n0b;
+      const cx<R>* Tc = T + (int64_t)c * k;
+      const cx<double> u = dot2(k, [&](int s) { return cmulc(to_d(Tc[s]), to_d(Ai[Sl[s]])); });
+      Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(to_d(Ai[Rl[c]]) - u);
     }
     int* gN = rec.G + rec.oN[b];
     const int* gid2 = L.idx + L.ioff[nbj];
@@ -819,9 +854,12 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
 }
 
 template <class R>
-void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(RSS_SPARSIFY_NT), 0, s, probs, ph);
+  // T in LDS up to 64 KiB
+  const int tcap = (int)std::min<size_t>((size_t)nmax * nmax, (64 * 1024) / sizeof(cx<R>));
+  const size_t shm = (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15) + (size_t)tcap * sizeof(cx<R>);
+  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(RSS_SPARSIFY_NT), shm, s, probs, ph, nmax, tcap);
 }
 
 // ---------------------------------------------------------------------------
@@ -2236,7 +2274,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t);                    \
   template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);              \
   template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t);            \
-  template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                  \
+  template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);             \
   template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t);        \
   template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);      \
   template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                   \

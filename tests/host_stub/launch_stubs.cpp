@@ -9,7 +9,7 @@ template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, h
 template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
 template <class R> int solve_group(int, int, int nrhs) { return nrhs < 16 ? nrhs : 16; }
 template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t) { return true; }
-template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, hipStream_t) {}
+template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
 template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
 template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStream_t) {}
@@ -26,7 +26,7 @@ template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, Ge
 template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
 template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
-template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
+template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template int cpqr_mg_groups<R>(int, int, int); \
 template int solve_group<R>(int, int, int); \
 template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t); \

@@ -18,6 +18,10 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <exception>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -56,15 +60,112 @@ constexpr int MIN_DEPTH = 2;  // compressed depths are D .. 2 (4 x 4 boxes and f
 // as their owner (release() ignores them).
 constexpr size_t SLAB = (size_t)2 << 20, SMALL = (size_t)64 << 10;
 
-void* dev_alloc(size_t n) {
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(RSS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+// Device memory cache.  Freed blocks stay with the library, per device and
+// size class (four classes per power of two), and are handed out again, so
+// the per-depth stores of a factorization and repeated factorizations do not
+// pay a hipMalloc and a device-synchronizing hipFree per block.  Callers free
+// only memory that no queued work uses any more (every free follows a
+// synchronization of the stream that used it; when an error unwinds an
+// operation, the device is synchronized before its blocks are cached).  At
+// most a quarter of the device's memory is kept cached; the rest goes back to
+// the driver, and so does the whole cache when an allocation fails.
+class DevPool {
+ public:
+  void* alloc(size_t n) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const size_t c = size_class(n);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto& fl = free_[{dev, c}];
+      if (!fl.empty()) {
+        void* p = fl.back();
+        fl.pop_back();
+        cached_[dev] -= c;
+        live_[p] = {dev, c};
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, c) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(dev);
+      if (hipMalloc(&p, c) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    live_[p] = {dev, c};
+    return p;
   }
+  void free(void* p) {
+    if (!p) return;
+    if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
+    std::unique_lock<std::mutex> g(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) {
+      g.unlock();
+      (void)hipFree(p);
+      return;
+    }
+    const int dev = it->second.first;
+    const size_t c = it->second.second;
+    live_.erase(it);
+    if (cached_[dev] + c <= cap(dev)) {
+      free_[{dev, c}].push_back(p);
+      cached_[dev] += c;
+      return;
+    }
+    g.unlock();
+    (void)hipFree(p);
+  }
+
+ private:
+  static size_t size_class(size_t n) {
+    size_t b = 1;
+    while (b * 2 <= n) b *= 2;
+    const size_t step = b >= 4 ? b / 4 : 1;
+    return (n + step - 1) / step * step;
+  }
+  size_t cap(int dev) {  // with mu_ held
+    auto it = cap_.find(dev);
+    if (it != cap_.end()) return it->second;
+    size_t fr = 0, tot = 0;
+    (void)hipMemGetInfo(&fr, &tot);
+    return cap_[dev] = tot / 4;
+  }
+  void trim(int dev) {
+    std::vector<void*> out;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (auto& kv : free_)
+        if (kv.first.first == dev) {
+          out.insert(out.end(), kv.second.begin(), kv.second.end());
+          kv.second.clear();
+        }
+      cached_[dev] = 0;
+    }
+    for (void* q : out) (void)hipFree(q);
+  }
+  std::mutex mu_;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free_;
+  std::unordered_map<void*, std::pair<int, size_t>> live_;
+  std::map<int, size_t> cached_, cap_;
+};
+
+DevPool& pool() {
+  static DevPool* p = new DevPool();  // never destroyed: handles may outlive static destruction order
+  return *p;
+}
+
+void* dev_alloc(size_t n) {
+  void* p = pool().alloc(n);
+  if (!p) fail(RSS_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
   return p;
 }
+
+void dev_free(void* p) { pool().free(p); }
 
 struct Carver {
   std::vector<void*> slabs;
@@ -81,7 +182,7 @@ struct Carver {
     return p;
   }
   void clear() {
-    for (void* p : slabs) (void)hipFree(p);
+    for (void* p : slabs) dev_free(p);
     slabs.clear();
     used = SLAB;
   }
@@ -106,7 +207,7 @@ struct Arena {
     if (!p) return;
     auto it = std::find(ptrs.begin(), ptrs.end(), p);
     if (it != ptrs.end()) {
-      (void)hipFree(p);
+      dev_free(p);
       const size_t i = (size_t)(it - ptrs.begin());
       bytes -= (double)sizes[i];
       ptrs.erase(it);
@@ -114,7 +215,7 @@ struct Arena {
     }
   }
   ~Arena() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
     small.clear();
   }
   template <class T>
@@ -480,14 +581,14 @@ struct Scratch {
     return p;
   }
   void clear() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
     ptrs.clear();
     si = 0;
     used = 0;
   }
   void release_all() {
     clear();
-    for (void* p : slabs) (void)hipFree(p);
+    for (void* p : slabs) dev_free(p);
     slabs.clear();
   }
   ~Scratch() { release_all(); }

@@ -23,6 +23,9 @@ struct dim3s { unsigned x, y, z; };
 extern struct dim3s threadIdx, blockIdx, blockDim;
 inline hipError_t hipMalloc(void** p, size_t n) { *p = calloc(1, n); return *p ? 0 : 2; }
 inline hipError_t hipFree(void* p) { free(p); return 0; }
+inline hipError_t hipGetDevice(int* d) { *d = 0; return 0; }
+inline hipError_t hipMemGetInfo(size_t* f, size_t* t) { *f = *t = (size_t)1 << 34; return 0; }
+inline hipError_t hipDeviceSynchronize() { return 0; }
 #define hipHostMallocDefault 0u
 inline hipError_t hipHostMalloc(void** p, size_t n, unsigned) { *p = calloc(1, n); return *p ? 0 : 2; }
 inline hipError_t hipHostFree(void* p) { free(p); return 0; }

@@ -25,6 +25,18 @@ constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
 #ifndef RSS_CPQR_MG_CH
 #define RSS_CPQR_MG_CH 4
 #endif
+// threads per workgroup of the single- and multi-workgroup QR
+#ifndef RSS_CPQR_NT
+#define RSS_CPQR_NT 512
+#endif
+#ifndef RSS_CPQR_MG_NT
+#define RSS_CPQR_MG_NT 512
+#endif
+// columns per wave at a time in the single-workgroup QR (rows per lane per
+// round: RSS_CPQR_CH for complex64, half of it for complex128)
+#ifndef RSS_CPQR_CB
+#define RSS_CPQR_CB 2
+#endif
 // threads per workgroup of the sparsification and of the redundant-block inverse
 #ifndef RSS_SPARSIFY_NT
 #define RSS_SPARSIFY_NT 1024
@@ -293,47 +305,75 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
       __syncthreads();
       vp = vs;
     }
-    // CH rows per lane per round: a wave keeps CH loads in flight
-    constexpr int CH = RSS_CPQR_CH;
-    for (int c = j + 1 + wv; c < n; c += NW) {
-      cx<R>* col = C + (int64_t)c * m;
-      double dr = 0.0, di = 0.0;
-      for (int base = j + lane; base < m; base += 64 * CH) {
-        cx<R> a[CH];
+    // a wave takes CB columns at a time, CH rows of each per lane per round:
+    // CB * CH loads in flight
+    constexpr int CH = sizeof(R) == sizeof(double) ? RSS_CPQR_CH / 2 : RSS_CPQR_CH, CB = RSS_CPQR_CB;
+    for (int c0 = j + 1 + wv; c0 < n; c0 += NW * CB) {
+      cx<R>* col[CB];
+      bool on[CB];
 #pragma unroll
-        for (int t = 0; t < CH; ++t)
-          if (base + 64 * t < m) a[t] = col[base + 64 * t];
+      for (int u = 0; u < CB; ++u) {
+        on[u] = c0 + NW * u < n;
+        col[u] = C + (int64_t)(on[u] ? c0 + NW * u : c0) * m;
+      }
+      double dr[CB], di[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) dr[u] = di[u] = 0.0;
+      for (int base = j + lane; base < m; base += 64 * CH) {
+        cx<R> a[CB][CH];
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+#pragma unroll
+          for (int t = 0; t < CH; ++t)
+            if (on[u] && base + 64 * t < m) a[u][t] = col[u][base + 64 * t];
 #pragma unroll
         for (int t = 0; t < CH; ++t)
           if (base + 64 * t < m) {
             const cx<R> v = vp[base + 64 * t - j];
-            dr += (double)v.x * a[t].x + (double)v.y * a[t].y;
-            di += (double)v.x * a[t].y - (double)v.y * a[t].x;
+#pragma unroll
+            for (int u = 0; u < CB; ++u)
+              if (on[u]) {
+                dr[u] += (double)v.x * a[u][t].x + (double)v.y * a[u][t].y;
+                di[u] += (double)v.x * a[u][t].y - (double)v.y * a[u][t].x;
+              }
           }
       }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      const double sr = beta * dr, si = beta * di;
-      double s2 = 0.0;
-      for (int base = j + lane; base < m; base += 64 * CH) {
-        cx<R> a[CH];
+      double sr[CB], si[CB], s2[CB];
 #pragma unroll
-        for (int t = 0; t < CH; ++t)
-          if (base + 64 * t < m) a[t] = col[base + 64 * t];
+      for (int u = 0; u < CB; ++u) {
+        sr[u] = beta * wave_sum(dr[u]);
+        si[u] = beta * wave_sum(di[u]);
+        s2[u] = 0.0;
+      }
+      for (int base = j + lane; base < m; base += 64 * CH) {
+        cx<R> a[CB][CH];
+#pragma unroll
+        for (int u = 0; u < CB; ++u)
+#pragma unroll
+          for (int t = 0; t < CH; ++t)
+            if (on[u] && base + 64 * t < m) a[u][t] = col[u][base + 64 * t];
 #pragma unroll
         for (int t = 0; t < CH; ++t) {
           const int i = base + 64 * t;
           if (i < m) {
             const cx<R> v = vp[i - j];
-            a[t].x -= (R)((double)v.x * sr - (double)v.y * si);
-            a[t].y -= (R)((double)v.x * si + (double)v.y * sr);
-            col[i] = a[t];
-            if (i > j) s2 += abs2d(a[t]);
+#pragma unroll
+            for (int u = 0; u < CB; ++u)
+              if (on[u]) {
+                cx<R> x = a[u][t];
+                x.x -= (R)((double)v.x * sr[u] - (double)v.y * si[u]);
+                x.y -= (R)((double)v.x * si[u] + (double)v.y * sr[u]);
+                col[u][i] = x;
+                if (i > j) s2[u] += abs2d(x);
+              }
           }
         }
       }
-      s2 = wave_sum(s2);
-      if (lane == 0) nrm[c] = s2;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const double t2 = wave_sum(s2[u]);
+        if (lane == 0 && on[u]) nrm[c0 + NW * u] = t2;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) cj[j] = cx<R>{(R)alr, (R)ali};
@@ -384,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_cpqr(const Prob<R>* probs, Phase<R> ph, 
 template <class R>
 void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  constexpr int NT = 512;
+  constexpr int NT = RSS_CPQR_NT;
   const size_t head = ((size_t)nmax * 8 + (NT / 64) * 8 + (size_t)nmax * 8 + 15) & ~(size_t)15;
   // the Householder vector is staged in LDS when it fits in 48 KiB
   const int vcap = (int)((48 * 1024) / sizeof(cx<R>));
@@ -703,7 +743,7 @@ __global__ void k_fill_u32(unsigned* p, int n) {
 
 template <class R>
 int cpqr_mg_groups(int nbox, int nmax, int mmax) {
-  constexpr int NT = 512;
+  constexpr int NT = RSS_CPQR_MG_NT;
   static int cap = -1;
   if (cap < 0) {
     int dev = 0, cus = 0;
@@ -722,7 +762,7 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax) {
 template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
                     double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s) {
-  constexpr int NT = 512;
+  constexpr int NT = RSS_CPQR_MG_NT;
   if (ph.nbox == 0 || G < 2) return false;
   hipLaunchKernelGGL(k_fill_u32, dim3((ph.nbox + 255) / 256), dim3(256), 0, s, bars, ph.nbox);
   const int vcap = std::min(mg_vcap<R>(), (mmax + G - 1) / G);

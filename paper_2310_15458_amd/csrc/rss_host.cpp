@@ -879,7 +879,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     unsigned* bars = (unsigned*)scr.alloc((size_t)std::max(1, maxph) * sizeof(unsigned));
     // row counts of the ID matrices, one slice per colour, read back once per height
     int* mrow = (int*)scr.alloc((size_t)9 * std::max(1, maxph) * sizeof(int));
-    GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * 81 * sizeof(GemmDesc<R>));
+    GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * sizeof(GemmDesc<R>));
     const int chunks = (mmax + 63) / 64;
     Phase<R> phs[9];
     for (int c = 0; c < 9; ++c) {
@@ -913,8 +913,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       launch_plan_y<R>(d_probs, ph, desc, s);
       prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, nmax, nmax + nNmax, s); });
       prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(d_probs, ph, s); });
-      launch_plan_schur<R>(d_probs, ph, desc, s);
-      prof.run(RSS_K_SCHUR, s, [&] { launch_gemm<R>(desc, ph.nbox * 81, nmax, nmax, s); });
+      prof.run(RSS_K_SCHUR, s, [&] { launch_schur<R>(d_probs, ph, nmax + nNmax, s); });
     }
     std::vector<int> mrow_h((size_t)9 * std::max(1, maxph));
     HIPCHK(hipMemcpyAsync(mrow_h.data(), mrow, mrow_h.size() * sizeof(int), hipMemcpyDeviceToHost, s));

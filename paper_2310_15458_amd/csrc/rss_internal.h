@@ -159,9 +159,11 @@ void launch_plan_y(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, 
 template <class R>
 void launch_compact(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
 template <class R>
-void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s);
-template <class R>
 void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipStream_t s);
+// Schur update of every box of the phase as one (k + |N|)^2 product per box,
+// scattered into the stencil blocks (qmax: bound on k + |N|)
+template <class R>
+void launch_schur(const Prob<R>* probs, const Phase<R>& ph, int qmax, hipStream_t s);
 template <class R>
 void launch_assemble_pairs(const PairDesc* pd, int npairs, const ListEntry* lists, int max_r,
                            int max_c, const Prob<R>* child, hipStream_t s);

@@ -3,7 +3,7 @@
 // form); kernel entries are always evaluated in FP64 and then rounded.
 //
 // Per colour phase of one depth the factorization runs
-//   build_C -> cpqr -> sparsify -> inverse -> (plan_y, gemm) -> compact -> (plan_schur, gemm)
+//   build_C -> cpqr -> sparsify -> inverse -> (plan_y, gemm) -> compact -> schur
 // over all boxes of the phase at once (one workgroup or more per box).  Boxes
 // of one colour are at least three boxes apart, so they read and write
 // disjoint blocks (Rem. r:t, Rem. r:nn) and need no synchronisation.
@@ -1091,56 +1091,6 @@ void launch_plan_y(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, 
 // Schur complement update (eq. e:step, Rem. r:nn):
 //   block(t1, t2) -= [X_SR; X_NR](rows of t1) * Y(:, cols of t2)
 // for t1, t2 in {B} u N(B); B's own rows/columns are its skeletons.
-template <class R>
-__global__ void k_plan_schur(const Prob<R>* probs, Phase<R> ph, GemmDesc<R>* desc) {
-  const int slot = blockIdx.x, b = ph.box[slot];
-  const Level<R> L = probs[ph.prob[slot]].L;
-  const Records<R> rec = probs[ph.prob[slot]].rec;
-  const int t = threadIdx.x;
-  if (t >= 81) return;
-  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
-  int box[9], off[9], cnt[9];
-  box[0] = b;
-  off[0] = 0;
-  cnt[0] = k;
-  int o = k;
-  for (int j = 0; j < 8; ++j) {
-    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
-    box[j + 1] = b2;
-    off[j + 1] = o;
-    cnt[j + 1] = b2 >= 0 ? L.cur[b2] : 0;
-    if (b2 >= 0) o += L.cur[b2];
-  }
-  const int t1 = t / 9, t2 = t % 9;
-  GemmDesc<R> d;
-  d.beta = 1;
-  d.sign = -1;
-  d.K = r;
-  if (r == 0 || box[t1] < 0 || box[t2] < 0) {
-    d.M = 0;
-    d.N = 0;
-    d.C = nullptr;
-    d.A = nullptr;
-    d.B = nullptr;
-    d.ldc = d.lda = d.ldb = 1;
-  } else {
-    d.C = block_ptr(L, box[t1], box[t2]);
-    d.ldc = L.n0[box[t1]];
-    d.A = rec.F + rec.oXSNR[b] + off[t1];
-    d.lda = k + nN;
-    d.B = rec.F + rec.oY[b] + (int64_t)off[t2] * r;
-    d.ldb = r;
-    d.M = cnt[t1];
-    d.N = cnt[t2];
-  }
-  desc[(int64_t)slot * 81 + t] = d;
-}
-
-template <class R>
-void launch_plan_schur(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s) {
-  if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_plan_schur<R>, dim3(ph.nbox), dim3(128), 0, s, probs, ph, desc);
-}
 
 // ---------------------------------------------------------------------------
 // batched ragged complex GEMM on the matrix cores: C = (beta C) + sign * A B.
@@ -1174,16 +1124,18 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-template <class R>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles_m) {
+// One 64 x 64 tile of C(i0 + ., j0 + .) = A (M x K, leading dimension lda)
+// times B (K x N, ldb): four waves, each a 32 x 32 quarter on the matrix cores
+// (4 real MFMAs per complex product).  The waves compute B^T A^T so that
+// consecutive lanes hold consecutive rows of C; emit(i, j, re, im) receives
+// every element inside M x N (complex64 form: the K slices summed in FP64).
+template <class R, class Emit>
+__device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* B, int ldb, int Mr, int Nc, int K,
+                                          int i0, int j0, Emit&& emit) {
   using M = Mfma<R>;
   using acc_t = typename M::acc;
   __shared__ cx<R> As[16][64];
   __shared__ cx<R> Bs[16][65];
-  const GemmDesc<R> d = desc[blockIdx.x];
-  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
-  const int i0 = tm * 64, j0 = tn * 64;
-  if (i0 >= d.M || j0 >= d.N) return;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
   acc_t cr[2][2], ci[2][2];
@@ -1197,14 +1149,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
 #pragma unroll
       for (int v = 0; v < 4; ++v) fr[a][b][v] = fi[a][b][v] = 0.0;
     }
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
       const int i = e & 63, kk = e >> 6;
       const int gi = i0 + i, gk = k0 + kk;
-      As[kk][i] = (gi < d.M && gk < d.K) ? d.A[gi + (int64_t)gk * d.lda] : czero<R>();
+      As[kk][i] = (gi < Mr && gk < K) ? A[gi + (int64_t)gk * lda] : czero<R>();
       const int kb = e & 15, j = e >> 4;
       const int gj = j0 + j, gkb = k0 + kb;
-      Bs[kb][j] = (gj < d.N && gkb < d.K) ? d.B[gkb + (int64_t)gj * d.ldb] : czero<R>();
+      Bs[kb][j] = (gj < Nc && gkb < K) ? B[gkb + (int64_t)gj * ldb] : czero<R>();
     }
     __syncthreads();
 #pragma unroll
@@ -1242,22 +1194,100 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
     }
   }
   // block (a, b) holds rows wi + 16 a + (l & 15) of C and columns wj + 16 b + M::row(l, v)
-  const double sg = (double)d.sign;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = i0 + wi + 16 * a + (l & 15), gj = j0 + wj + 16 * b + M::row(l, v);
-        if (gi < d.M && gj < d.N) {
+        const int li = wi + 16 * a + (l & 15), lj = wj + 16 * b + M::row(l, v);
+        if (i0 + li < Mr && j0 + lj < Nc) {
           const double re = sizeof(R) == sizeof(double) ? (double)cr[a][b][v] : fr[a][b][v];
           const double im = sizeof(R) == sizeof(double) ? (double)ci[a][b][v] : fi[a][b][v];
-          cx<R>* p = d.C + gi + (int64_t)gj * d.ldc;
-          const cx<R> val{(R)(sg * re), (R)(sg * im)};
-          *p = d.beta ? (*p + val) : val;
+          emit(li, lj, re, im);
         }
       }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles_m) {
+  const GemmDesc<R> d = desc[blockIdx.x];
+  const int tm = blockIdx.y % tiles_m, tn = blockIdx.y / tiles_m;
+  const int i0 = tm * 64, j0 = tn * 64;
+  if (i0 >= d.M || j0 >= d.N) return;
+  const double sg = (double)d.sign;
+  gemm_tile<R>(d.A, d.lda, d.B, d.ldb, d.M, d.N, d.K, i0, j0, [&](int li, int lj, double re, double im) {
+    cx<R>* p = d.C + (i0 + li) + (int64_t)(j0 + lj) * d.ldc;
+    const cx<R> val{(R)(sg * re), (R)(sg * im)};
+    *p = d.beta ? (*p + val) : val;
+  });
+}
+
+// Schur update of one box (eq. e:step) as one product:
+//   [A_SS A_SN; A_NS A_NN] -= [X_SR; X_NR] Y,   Y = X_RR^{-1} [X_RS X_RN],
+// rows and columns ordered [S; N_1 .. N_8] (Q = k + |N|).  Workgroup (slot, tile)
+// computes a 64 x 64 tile of the Q x Q product and subtracts each element from
+// the stencil block of its row box and column box.
+template <class R>
+__global__ __launch_bounds__(256) void k_schur(const Prob<R>* probs, Phase<R> ph, int tiles_q) {
+  __shared__ cx<R>* bp[9][9];
+  __shared__ int ldr[9];
+  __shared__ unsigned char rbk[64], cbk[64];
+  __shared__ short rloc[64], cloc[64];
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  const int Q = k + nN;
+  const int i0 = (blockIdx.y % tiles_q) * 64, j0 = (blockIdx.y / tiles_q) * 64;
+  if (r == 0 || i0 >= Q || j0 >= Q) return;
+  int box[9], off[9], cnt[9];
+  box[0] = b;
+  off[0] = 0;
+  cnt[0] = k;
+  int o = k;
+  for (int j = 0; j < 8; ++j) {
+    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
+    box[j + 1] = b2;
+    off[j + 1] = o;
+    cnt[j + 1] = b2 >= 0 ? L.cur[b2] : 0;
+    if (b2 >= 0) o += cnt[j + 1];
+  }
+  const int t = threadIdx.x;
+  if (t < 81) {
+    const int t1 = t / 9, t2 = t % 9;
+    bp[t1][t2] = (box[t1] >= 0 && box[t2] >= 0) ? block_ptr(L, box[t1], box[t2]) : nullptr;
+  }
+  if (t < 9) ldr[t] = box[t] >= 0 ? L.n0[box[t]] : 0;
+  if (t < 128) {
+    // row (t < 64) or column (t >= 64) i0/j0 + (t & 63): its box and local index
+    const int g = (t < 64 ? i0 : j0) + (t & 63);
+    int q = 0;
+    for (int u = 1; u < 9; ++u)
+      if (cnt[u] > 0 && g >= off[u]) q = u;
+    if (t < 64) {
+      rbk[t] = (unsigned char)q;
+      rloc[t] = (short)(g - off[q]);
+    } else {
+      cbk[t - 64] = (unsigned char)q;
+      cloc[t - 64] = (short)(g - off[q]);
+    }
+  }
+  __syncthreads();
+  const cx<R>* XA = rec.F + rec.oXSNR[b];  // Q x r
+  const cx<R>* YB = rec.F + rec.oY[b];     // r x Q
+  gemm_tile<R>(XA, Q, YB, r, Q, Q, r, i0, j0, [&](int li, int lj, double re, double im) {
+    const int rb = rbk[li], cb = cbk[lj];
+    cx<R>* p = bp[rb][cb] + rloc[li] + (int64_t)cloc[lj] * ldr[rb];
+    *p = *p - cx<R>{(R)re, (R)im};
+  });
+}
+
+template <class R>
+void launch_schur(const Prob<R>* probs, const Phase<R>& ph, int qmax, hipStream_t s) {
+  if (ph.nbox == 0 || qmax <= 0) return;
+  const int tq = (qmax + 63) / 64;
+  hipLaunchKernelGGL(k_schur<R>, dim3(ph.nbox, tq * tq), dim3(256), 0, s, probs, ph, tq);
 }
 
 template <class R>
@@ -2318,8 +2348,8 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t);        \
   template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);      \
   template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                   \
-  template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);  \
   template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t);                    \
+  template void launch_schur<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);                \
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
                                          const Prob<R>*, hipStream_t);                             \
   template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t);           \

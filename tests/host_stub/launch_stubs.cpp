@@ -13,8 +13,8 @@ template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, hi
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
 template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
 template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStream_t) {}
-template <class R> void launch_plan_schur(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
 template <class R> void launch_gemm(const GemmDesc<R>*, int, int, int, hipStream_t) {}
+template <class R> void launch_schur(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
 template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t) {}
 size_t root_work_elems(int n) { return (size_t)65 * n; }
@@ -33,8 +33,8 @@ template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, 
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
 template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
-template void launch_plan_schur<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
 template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
+template void launch_schur<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \
 template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t); \
 template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \

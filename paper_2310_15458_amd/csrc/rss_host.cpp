@@ -436,6 +436,7 @@ struct rss_ctx {
   int D = 0;
   Arena arena;
   double* d_P = nullptr;
+  int* d_tperm = nullptr;  // residual target order (spatial_order), made on the first refined solve
   std::vector<DepthRecords> recs;  // index 0 .. : depths D, D-1, ..., 2
   int n_root = 0;
   int* d_root_ids = nullptr;
@@ -622,7 +623,35 @@ struct ResProblem {
   const cx<double>* B;
   cx<double>* R;
   int nrhs;
+  const int* tperm;  // device target order, or null (index order)
 };
+
+// Points ordered cell by cell (row-major cells of ~64 points over the
+// bounding box, index order inside a cell): consecutive runs of 64 targets are
+// spatially compact, so the residual's per-pair branch (near / far argument of
+// the kernel) takes one side for most waves.
+std::vector<int> spatial_order(const double* P, int64_t n) {
+  double lox = P[0], hix = P[0], loy = P[1], hiy = P[1];
+  for (int64_t i = 1; i < n; ++i) {
+    lox = std::min(lox, P[2 * i]);
+    hix = std::max(hix, P[2 * i]);
+    loy = std::min(loy, P[2 * i + 1]);
+    hiy = std::max(hiy, P[2 * i + 1]);
+  }
+  const int G = std::max(1, (int)std::sqrt((double)n / 64.0));
+  const double wx = hix > lox ? (hix - lox) : 1.0, wy = hiy > loy ? (hiy - loy) : 1.0;
+  std::vector<int> cell(n), cnt((size_t)G * G + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int cx = std::min(G - 1, std::max(0, (int)((P[2 * i] - lox) / wx * G)));
+    const int cy = std::min(G - 1, std::max(0, (int)((P[2 * i + 1] - loy) / wy * G)));
+    cell[i] = cy * G + cx;
+    cnt[cell[i] + 1]++;
+  }
+  for (size_t c = 1; c < cnt.size(); ++c) cnt[c] += cnt[c - 1];
+  std::vector<int> perm(n);
+  for (int64_t i = 0; i < n; ++i) perm[cnt[cell[i]]++] = (int)i;
+  return perm;
+}
 
 void residual_batch(const std::vector<ResProblem>& rp, Scratch& scr, hipStream_t s) {
   int64_t tblocks = 0;
@@ -645,6 +674,7 @@ void residual_batch(const std::vector<ResProblem>& rp, Scratch& scr, hipStream_t
     e.B = q.B;
     e.R = q.R;
     e.nrhs = q.nrhs;
+    e.tperm = q.tperm;
     e.S = (int)std::min<int64_t>(S, nt);
     e.part = e.S > 1 ? (cx<double>*)scr.alloc((size_t)e.S * 16 * q.n * sizeof(cx<double>)) : nullptr;
     for (int64_t tb = 0; tb < nt; ++tb) {
@@ -1643,8 +1673,13 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
         // residuals r = b - A x (FP64, on the fly), every live problem in one launch
         {
           std::vector<ResProblem> rp;
-          for (int p : live)
-            rp.push_back({H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p]});
+          for (int p : live) {
+            if (!H[p]->d_tperm) {
+              const std::vector<int> perm = spatial_order(H[p]->h_points.data(), H[p]->N);
+              H[p]->d_tperm = H[p]->arena.up(perm, s);
+            }
+            rp.push_back({H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p], H[p]->d_tperm});
+          }
           residual_batch(rp, rscr, s);
         }
         for (int p : live) {
@@ -1733,7 +1768,12 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
     if (n < 1 || nrhs < 1) fail(RSS_EINVAL, "bad sizes");
     const KParams kp = to_kp(*k);
     Scratch scr;
-    residual_batch({{kp, points, n, (const cx<double>*)X, (const cx<double>*)B, (cx<double>*)R, nrhs}},
+    std::vector<double> hp((size_t)n * 2);
+    HIPCHK(hipMemcpyAsync(hp.data(), points, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    const int* tperm = scr.up(spatial_order(hp.data(), n), (hipStream_t)stream);
+    residual_batch({{kp, points, n, (const cx<double>*)X, (const cx<double>*)B, (cx<double>*)R, nrhs, tperm}},
                    scr, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize((hipStream_t)stream));

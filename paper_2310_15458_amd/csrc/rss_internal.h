@@ -208,6 +208,7 @@ struct ResDesc {
   const cx<double>* B;
   cx<double>* R;
   cx<double>* part;     // S x 16 x n partial sums when S > 1
+  const int* tperm;     // target order (spatially compact runs of 64), or null
   int nrhs;
   int S;                // source slices
 };

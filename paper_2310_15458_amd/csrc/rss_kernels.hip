@@ -2155,7 +2155,8 @@ void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64
 }
 
 // r = b - A x for several problems at once (FP64, entries evaluated on the
-// fly).  Workgroup = (problem, block of 256 targets, source slice): sources
+// fly).  Workgroup = (problem, block of 256 targets in the order tperm, source
+// slice): sources
 // stream through LDS 256 at a time with their NC right-hand-side values; a
 // problem with one slice writes r directly, otherwise each slice writes its
 // partial sums (16 columns per slice) and k_residual_sum subtracts them from b
@@ -2169,8 +2170,11 @@ __global__ __launch_bounds__(256) void k_residual(const ResDesc* dd, const ResBl
   if (c0 >= D.nrhs) return;
   const int nc = min(NC, D.nrhs - c0);
   const int64_t n = D.n;
-  const int64_t i = (int64_t)bb.tb * 256 + threadIdx.x;
-  const bool live = i < n;
+  // the wave's targets are spatially compact (tperm), so the kernel's
+  // near / far branch rarely diverges inside a wave
+  const int64_t lin = (int64_t)bb.tb * 256 + threadIdx.x;
+  const bool live = lin < n;
+  const int64_t i = !live ? 0 : D.tperm ? (int64_t)D.tperm[lin] : lin;
   const double xi = live ? D.P[2 * i] : 0.0, yi = live ? D.P[2 * i + 1] : 0.0;
   const int64_t ntile = (n + 255) / 256, per = (ntile + D.S - 1) / D.S;
   const int64_t lo = (int64_t)bb.sp * per * 256, hi = min(n, lo + per * 256);

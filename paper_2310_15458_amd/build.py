@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librss.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["rss_kernels.hip", "rss_host.cpp", "rss_server.cpp"]
+SOURCES = ["rss_kernels.hip", "rss_residual.hip", "rss_host.cpp", "rss_server.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
@@ -26,6 +26,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
+
+
+# per-source additions: the residual's matrix-core accumulators stay in
+# ordinary vector registers (the accumulation registers would be copied to and
+# from on every iteration of its branchy source loop)
+EXTRA_FLAGS = {"rss_residual.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -37,7 +43,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
-    cmd = [hipcc(), "-c", *FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"), "-x", "hip",
+    cmd = [hipcc(), "-c", *FLAGS, *EXTRA_FLAGS.get(src, []), "-I", os.path.join(os.path.dirname(HERE), "include"), "-x", "hip",
            os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

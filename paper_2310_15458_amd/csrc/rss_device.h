@@ -72,47 +72,61 @@ struct KParams {
   double kappa, weight, diag;
 };
 
-// H0^(1)(x) = J0(x) + i Y0(x) for x > 0.
-// x < XA: polynomial interpolants (Horner form in t in [-1, 1]) of J0 and of
-// G = Y0 - (2/pi) log(x/2) J0 (both entire) on intervals of width XA / NSEG;
-// x >= XA: Hankel's large-argument expansion with the phase factor
-// e^{i(x - pi/4)} = (cos x + i sin x)(1 - i)/sqrt(2).
-__device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0) {
+// H0^(1)(x) = J0(x) + i Y0(x) for x > 0, in two parts.
+// x < XA (bessel_poly): polynomial interpolants (Horner form in t in [-1, 1])
+// on intervals of width XA / NSEG, of J0 and of Y0 itself, except on the first
+// NLOG intervals, which carry the entire G = Y0 - (2/pi) log(x/2) J0 instead;
+// the two coefficient lists come interleaved term by term from `tab`
+// (rss_poly_jy, a copy of it in LDS, or such a copy scaled per list).  Returns
+// the interval; the caller adds (2/pi) log(x/2) J0 when it is below NLOG.
+// x >= XA (bessel_asym): Hankel's large-argument expansion with the phase
+// factor e^{i(x - pi/4)} = (cos x + i sin x)(1 - i)/sqrt(2).
+constexpr double RSS_TWO_OVER_PI = 0.63661977236758134308;
+
+__device__ __forceinline__ int bessel_poly(double x, const double* tab, double& pj, double& py) {
   constexpr double W = RSS_BESSEL_XA / RSS_BESSEL_NSEG;
-  constexpr double TWO_OVER_PI = 0.63661977236758134308;
+  int s = (int)(x * (1.0 / W));
+  s = s < RSS_BESSEL_NSEG - 1 ? s : RSS_BESSEL_NSEG - 1;
+  // local variable of interval s (exact when W is a power of two)
+  const double t = (x - (s + 0.5) * W) * (2.0 / W);
+  const double* c = tab + s * (2 * (RSS_BESSEL_DEG + 1));
+  pj = c[2 * RSS_BESSEL_DEG];
+  py = c[2 * RSS_BESSEL_DEG + 1];
+#pragma unroll
+  for (int k = RSS_BESSEL_DEG - 1; k >= 0; --k) {
+    pj = fma(pj, t, c[2 * k]);
+    py = fma(py, t, c[2 * k + 1]);
+  }
+  return s;
+}
+
+__device__ __forceinline__ void bessel_asym(double x, double& j0, double& y0) {
+  const double ix = 1.0 / x;  // one division; u, Q / x and the amplitude reuse it
+  const double u = ix * ix;
+  double P = rss_asym_p[RSS_BESSEL_NASYM_HALF - 1];
+  double Q = rss_asym_q[RSS_BESSEL_NASYM_HALF - 1];
+#pragma unroll
+  for (int k = RSS_BESSEL_NASYM_HALF - 2; k >= 0; --k) {
+    P = fma(P, u, rss_asym_p[k]);
+    Q = fma(Q, u, rss_asym_q[k]);
+  }
+  Q = Q * ix;
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  constexpr double RS2 = 0.70710678118654752440;
+  const double er = (cs + sn) * RS2, ei = (sn - cs) * RS2;
+  const double amp = sqrt(RSS_TWO_OVER_PI * ix);
+  j0 = amp * (er * P - ei * Q);
+  y0 = amp * (er * Q + ei * P);
+}
+
+__device__ __forceinline__ void bessel_j0y0(double x, double& j0, double& y0,
+                                            const double* tab = rss_poly_jy) {
   if (x < RSS_BESSEL_XA) {
-    int s = (int)(x * (1.0 / W));
-    s = s < RSS_BESSEL_NSEG - 1 ? s : RSS_BESSEL_NSEG - 1;
-    // local variable of interval s (exact when W is a power of two)
-    const double t = (x - (s + 0.5) * W) * (2.0 / W);
-    const double* cj = rss_poly_j0 + s * (RSS_BESSEL_DEG + 1);
-    const double* cg = rss_poly_g + s * (RSS_BESSEL_DEG + 1);
-    double pj = cj[RSS_BESSEL_DEG], pg = cg[RSS_BESSEL_DEG];
-#pragma unroll
-    for (int k = RSS_BESSEL_DEG - 1; k >= 0; --k) {
-      pj = fma(pj, t, cj[k]);
-      pg = fma(pg, t, cg[k]);
-    }
-    j0 = pj;
-    y0 = fma(TWO_OVER_PI * log(0.5 * x), pj, pg);
+    const int s = bessel_poly(x, tab, j0, y0);
+    if (s < RSS_BESSEL_NLOG) y0 = fma(RSS_TWO_OVER_PI * log(0.5 * x), j0, y0);
   } else {
-    const double ix = 1.0 / x;  // one division; u, Q / x and the amplitude reuse it
-    const double u = ix * ix;
-    double P = rss_asym_p[RSS_BESSEL_NASYM_HALF - 1];
-    double Q = rss_asym_q[RSS_BESSEL_NASYM_HALF - 1];
-#pragma unroll
-    for (int k = RSS_BESSEL_NASYM_HALF - 2; k >= 0; --k) {
-      P = fma(P, u, rss_asym_p[k]);
-      Q = fma(Q, u, rss_asym_q[k]);
-    }
-    Q = Q * ix;
-    double sn, cs;
-    sincos(x, &sn, &cs);
-    constexpr double RS2 = 0.70710678118654752440;
-    const double er = (cs + sn) * RS2, ei = (sn - cs) * RS2;
-    const double amp = sqrt(TWO_OVER_PI * ix);
-    j0 = amp * (er * P - ei * Q);
-    y0 = amp * (er * Q + ei * P);
+    bessel_asym(x, j0, y0);
   }
 }
 
@@ -124,7 +138,7 @@ __device__ __forceinline__ double dist_rn(double xi, double yi, double xj, doubl
 
 // K(x_i, x_j) without weight (complex, FP64).
 __device__ __forceinline__ cx<double> kernel_raw(const KParams& kp, double xi, double yi, double xj,
-                                                 double yj) {
+                                                 double yj, const double* tab = rss_poly_jy) {
   if (kp.kind == 2) {
     const double dot = __dadd_rn(__dmul_rn(xi, xj), __dmul_rn(yi, yj));
     const double base = 1.0 + dot;
@@ -138,7 +152,7 @@ __device__ __forceinline__ cx<double> kernel_raw(const KParams& kp, double xi, d
     return {-log(r) / TWO_PI, 0.0};
   }
   double j0, y0;
-  bessel_j0y0(__dmul_rn(kp.kappa, r), j0, y0);
+  bessel_j0y0(__dmul_rn(kp.kappa, r), j0, y0, tab);
   // (i/4)(J0 + i Y0) = -Y0/4 + i J0/4
   return {-0.25 * y0, 0.25 * j0};
 }

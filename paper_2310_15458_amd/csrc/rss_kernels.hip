@@ -2135,7 +2135,7 @@ void launch_root_apply(const RootApply<R>* ra, int nprob, int max_n, int max_nrh
 }
 
 // ---------------------------------------------------------------------------
-// kernel block evaluation and the FP64 on-the-fly residual R = B - A X
+// kernel block evaluation (the FP64 on-the-fly residual is in rss_residual.hip)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_kernel_block(KParams kp, const double* P, const int* I,
                                                       int64_t ni, const int* J, int64_t nj,
@@ -2152,146 +2152,6 @@ void launch_kernel_block(const KParams& kp, const double* P, const int* I, int64
   if (tot == 0) return;
   hipLaunchKernelGGL(k_kernel_block, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, kp, P, I,
                      ni, J, nj, out);
-}
-
-// r = b - A x for several problems at once (FP64, entries evaluated on the
-// fly), 16 right-hand sides per launch.  Work item = (problem, block of 256
-// targets in the order tperm, source slice), split over 256 / RES_TPB
-// workgroups; sources stream through LDS RES_SB at a time with their 16
-// right-hand-side values.  The contraction runs on the matrix cores: lane l
-// evaluates the entry for target l mod 16 of a 16-target group and source
-// l / 16 of a quad of sources, which is the A operand of
-// v_mfma_f64_16x16x4f64 (the B operand: the quad's 16 right-hand-side values),
-// four real MFMAs per complex product.  A problem with one slice writes r
-// directly, otherwise each slice writes its partial sums and k_residual_sum
-// subtracts them from b in slice order.
-#ifndef RSS_RES_RG
-#define RSS_RES_RG 2
-#endif
-constexpr int RES_RG = RSS_RES_RG;       // groups of 16 targets per wave
-constexpr int RES_TPB = 64 * RES_RG;     // targets per workgroup (a block of 256 spans 256 / RES_TPB)
-#ifndef RSS_RES_SB
-#define RSS_RES_SB 256
-#endif
-constexpr int RES_SB = RSS_RES_SB;       // sources per LDS batch
-
-__global__ __launch_bounds__(256) void k_residual(const ResDesc* dd, const ResBlock* blk, int c0) {
-  __shared__ double sx[RES_SB], sy[RES_SB];
-  __shared__ cx<double> xs[RES_SB * 16];
-  const ResBlock bb = blk[blockIdx.x];
-  const ResDesc D = dd[bb.prob];
-  if (c0 >= D.nrhs) return;
-  const int nc = min(16, D.nrhs - c0);
-  const int64_t n = D.n;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  // this lane's target in each of the wave's groups of 16: the A-operand row
-  const int64_t base = (int64_t)bb.tb * 256 + (int64_t)blockIdx.y * RES_TPB + wv * 16 * RES_RG;
-  double tx[RES_RG], ty[RES_RG];
-  int64_t ti[RES_RG];
-#pragma unroll
-  for (int g = 0; g < RES_RG; ++g) {
-    const int64_t lin = base + g * 16 + li;
-    ti[g] = lin < n ? (D.tperm ? (int64_t)D.tperm[lin] : lin) : -1;
-    tx[g] = ti[g] >= 0 ? D.P[2 * ti[g]] : 0.0;
-    ty[g] = ti[g] >= 0 ? D.P[2 * ti[g] + 1] : 0.0;
-  }
-  const int64_t ntile = (n + 255) / 256, per = (ntile + D.S - 1) / D.S;
-  const int64_t lo = (int64_t)bb.sp * per * 256, hi = min(n, lo + per * 256);
-  const KParams kp = D.kp;
-  mf_d4 ar[RES_RG], ai[RES_RG];
-#pragma unroll
-  for (int g = 0; g < RES_RG; ++g) {
-    ar[g] = mf_d4{0, 0, 0, 0};
-    ai[g] = mf_d4{0, 0, 0, 0};
-  }
-  for (int64_t t0 = lo; t0 < hi; t0 += RES_SB) {
-    __syncthreads();
-    if (threadIdx.x < RES_SB) {
-      const int64_t sj = t0 + threadIdx.x;
-      sx[threadIdx.x] = sj < hi ? D.P[2 * sj] : 0.0;
-      sy[threadIdx.x] = sj < hi ? D.P[2 * sj + 1] : 0.0;
-    }
-    for (int e = threadIdx.x; e < RES_SB * 16; e += 256) {
-      const int sl = e >> 4, c = e & 15;
-      const int64_t sj = t0 + sl;
-      xs[e] = (sj < hi && c < nc) ? D.X[sj + (int64_t)(c0 + c) * n] : czero<double>();
-    }
-    __syncthreads();
-    const int cnt = (int)min((int64_t)RES_SB, hi - t0);
-    for (int q = 0; q < cnt; q += 4) {
-      // source q + lk of this quad: the A-operand column and the B-operand row
-      const int sl = q + lk;
-      const bool sv = sl < cnt;
-      const cx<double> xv = xs[sl * 16 + li];
-      const double px = sx[sl], py = sy[sl];
-      const int64_t sg = t0 + sl;
-#pragma unroll
-      for (int g = 0; g < RES_RG; ++g) {
-        cx<double> a = czero<double>();
-        if (sv && ti[g] >= 0) {
-          if (sg == ti[g]) {
-            a = cx<double>{kp.diag, 0.0};
-          } else {
-            const cx<double> kv = kernel_raw(kp, tx[g], ty[g], px, py);
-            a = cx<double>{kp.weight * kv.x, kp.weight * kv.y};
-          }
-        }
-        ar[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xv.x, ar[g], 0, 0, 0);
-        ar[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, xv.y, ar[g], 0, 0, 0);
-        ai[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xv.y, ai[g], 0, 0, 0);
-        ai[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, xv.x, ai[g], 0, 0, 0);
-      }
-    }
-  }
-  // result row lk + 4 v (target of the group), column li (right-hand side)
-#pragma unroll
-  for (int g = 0; g < RES_RG; ++g)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t lin = base + g * 16 + lk + 4 * v;
-      if (lin >= n || li >= nc) continue;
-      const int64_t i = D.tperm ? (int64_t)D.tperm[lin] : lin;
-      const cx<double> val{ar[g][v], ai[g][v]};
-      if (D.S == 1) {
-        const int64_t e = i + (int64_t)(c0 + li) * n;
-        D.R[e] = D.B[e] - val;
-      } else {
-        D.part[((int64_t)bb.sp * 16 + li) * n + i] = val;
-      }
-    }
-}
-
-// r = b - (sum of the slices' partials, in slice order) for the columns
-// c0 .. c0 + width - 1; one workgroup per block of 256 targets of a sliced problem
-__global__ __launch_bounds__(256) void k_residual_sum(const ResDesc* dd, const ResBlock* blk, int c0,
-                                                     int width) {
-  const ResBlock bb = blk[blockIdx.x];
-  const ResDesc D = dd[bb.prob];
-  if (c0 >= D.nrhs) return;
-  const int nc = min(width, D.nrhs - c0);  // the columns of this chunk
-  const int64_t n = D.n;
-  const int64_t i = (int64_t)bb.tb * 256 + threadIdx.x;
-  if (i >= n) return;
-  for (int c = 0; c < nc; ++c) {
-    cx<double> v = D.B[i + (int64_t)(c0 + c) * n];
-    for (int sp = 0; sp < D.S; ++sp) v = v - D.part[((int64_t)sp * 16 + c) * n + i];
-    D.R[i + (int64_t)(c0 + c) * n] = v;
-  }
-}
-
-int residual_slices(int64_t target_blocks) {
-  if (target_blocks >= 1024) return 1;
-  return (int)std::min<int64_t>(16, (1024 + target_blocks - 1) / std::max<int64_t>(target_blocks, 1));
-}
-
-void launch_residual(const ResDesc* d, const ResBlock* blk, int nblk, const ResBlock* sum_blk,
-                     int nsum, int max_nrhs, hipStream_t s) {
-  for (int c0 = 0; c0 < max_nrhs; c0 += 16) {
-    hipLaunchKernelGGL(k_residual, dim3(nblk, 256 / RES_TPB), dim3(256), 0, s, d, blk, c0);
-    if (nsum > 0)
-      hipLaunchKernelGGL(k_residual_sum, dim3(nsum), dim3(256), 0, s, d, sum_blk, c0, std::min(16, max_nrhs - c0));
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -228,6 +228,35 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
  */
 int rss_set_stream(rss_handle h, void* stream);
 
+/*
+ * rss_set_graphs -- process-wide switch (default on) for the captured solve
+ * sweeps of Sec. 2.6: with it on, an apply of a single handle (rss_apply,
+ * rss_solve and each refinement step, a server batch of one) replays a HIP
+ * graph of all its launches, captured on the handle's first apply with that
+ * nrhs and kept until rss_free; the vectors are reached through descriptor
+ * tables in device memory that each call rewrites before the replay.  Off:
+ * every apply launches its kernels directly (the same kernels, same results).
+ * Batches of several handles always launch directly.  enable: 0 or 1; returns
+ * the previous setting.
+ */
+int rss_set_graphs(int enable);
+
+/*
+ * rss_set_autotune -- process-wide switch (default on) for the solve's tile
+ * autotuner.  Each level of a solve (one tree height of one or more handles)
+ * runs its sweeps with a tile: the right-hand sides per workgroup and the
+ * workgroups per box of its two wide products.  With the switch on, the first
+ * apply that meets a level shape not seen before (precision, largest group
+ * width, largest skeleton and redundant counts rounded up to 8, largest
+ * k + |N| rounded up to 32, box count rounded up to a power of two) times the candidate tiles on that apply's own shapes (on
+ * vectors of zeros: the caller's data is untouched) and keeps the fastest for
+ * the rest of the process; later applies of that shape, across handles and
+ * servers, reuse it.  Off: untuned shapes use the default tile.  A tile that
+ * splits a summation differently changes results at the rounding level only.
+ * enable: 0 or 1; returns the previous setting.
+ */
+int rss_set_autotune(int enable);
+
 /* ------------------------------------------------------------------------- */
 /* Solve server: factorizations stay resident in device memory; factor and   */
 /* solve requests are served with continuous batching (a factor worker and a */

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -421,6 +423,11 @@ struct DepthRecords {
 
 }  // namespace
 
+// a captured apply of one handle (see ApplyGraph); destroyed with the handle
+struct ApplyGraphBase {
+  virtual ~ApplyGraphBase() {}
+};
+
 struct rss_ctx {
   int64_t N = 0;
   rss_kernel kern{};
@@ -450,6 +457,9 @@ struct rss_ctx {
   rss_stats stats{};
   Prof prof;
   int* d_err = nullptr;
+  // captured applies per (sizeof(R), nrhs); declared last, so destroyed before
+  // the arena that owns the factors they read
+  std::map<std::pair<int, int>, std::unique_ptr<ApplyGraphBase>> graphs;
 };
 
 namespace {
@@ -1269,86 +1279,95 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   }
 }
 
-// z_p <- F_p^{-1} z_p for every handle of a batch (complex<R>, N_p x nrhs_p,
-// ld N_p), on stream s: one launch per (height, colour) and direction.
+// The launches of one batched apply (the solve sweeps of Sec. 2.6: forward over the
+// records in factor order, the root, backward in reverse), with every
+// descriptor they read in device memory.  The vectors z_p are reached only
+// through the descriptor tables (SolveProb::z, RootApply::z), so a plan can be
+// replayed on other vectors of the same shape after set_z rewrites them.
 template <class R>
-void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
-                 const std::vector<int>& nrhs, hipStream_t s) {
-  const int np = (int)H.size();
-  int tmax = -1, nrhs_max = 0;
-  for (int p = 0; p < np; ++p) {
-    tmax = std::max(tmax, (int)H[p]->recs.size() - 1);
-    nrhs_max = std::max(nrhs_max, nrhs[p]);
-  }
-  Scratch scr;
-  // per height: SolveProb array over the problems that have that height, and merged phases
+struct ApplyPlan {
   struct HPhase {
     SolveProb<R>* d_sp = nullptr;
+    std::vector<SolveProb<R>> sp;  // host copy (z rewritten per call)
+    std::vector<int> owner;        // problem of each entry of sp
     Phase<R> ph[9];
     int kmax = 0, rmax = 0, qmax = 0;
+    int gmax = 0;                  // largest valid ncg (LDS budget)
+    SolveTile tile[9];             // per colour phase
   };
-  std::vector<HPhase> HP(tmax + 1);
-  for (int t = 0; t <= tmax; ++t) {
-    std::vector<SolveProb<R>> sp;
-    std::vector<int> idxmap(np, -1);
-    for (int p = 0; p < np; ++p)
-      if (t < (int)H[p]->recs.size()) {
-        idxmap[p] = (int)sp.size();
-        SolveProb<R> q;
-        q.rec = dev_records<R>(H[p]->recs[t]);
-        q.z = Z[p];
-        q.ldz = H[p]->N;
-        q.nrhs = nrhs[p];
-        sp.push_back(q);
-        HP[t].kmax = std::max(HP[t].kmax, H[p]->recs[t].kmax);
-        HP[t].rmax = std::max(HP[t].rmax, H[p]->recs[t].rmax);
-        HP[t].qmax = std::max(HP[t].qmax, H[p]->recs[t].qmax);
-      }
-    HP[t].d_sp = scr.up(sp, s);
-    for (int c = 0; c < 9; ++c) {
-      Phase<R>& ph = HP[t].ph[c];
-      ph = Phase<R>{};
-      if (sp.size() == 1) {
-        for (int p = 0; p < np; ++p)
-          if (idxmap[p] == 0) {
-            const PhaseHost& P = H[p]->recs[t].ph[c];
-            ph.nbox = (int)P.boxes.size();
-            ph.box = P.d_box;
-            ph.prob = P.d_prob;
+  std::vector<HPhase> HP;
+  int tmax = -1, nrhs_max = 0, nmax = 0;
+  cx<R>* Wk = nullptr;
+  size_t wcap = 0;                 // entries of Wk
+  RootApply<R>* d_ra = nullptr;
+  std::vector<RootApply<R>> ra;
+  std::vector<int> ra_owner;
+  GemmDesc<R>* desc = nullptr;
+
+  void build(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z, const std::vector<int>& nrhs,
+             Scratch& mem, hipStream_t s) {
+    const int np = (int)H.size();
+    for (int p = 0; p < np; ++p) {
+      tmax = std::max(tmax, (int)H[p]->recs.size() - 1);
+      nrhs_max = std::max(nrhs_max, nrhs[p]);
+    }
+    // per height: SolveProb array over the problems that have that height, and merged phases
+    HP.assign(tmax + 1, HPhase{});
+    for (int t = 0; t <= tmax; ++t) {
+      std::vector<int> idxmap(np, -1);
+      for (int p = 0; p < np; ++p)
+        if (t < (int)H[p]->recs.size()) {
+          idxmap[p] = (int)HP[t].sp.size();
+          SolveProb<R> q;
+          q.rec = dev_records<R>(H[p]->recs[t]);
+          q.z = Z[p];
+          q.ldz = H[p]->N;
+          q.nrhs = nrhs[p];
+          HP[t].sp.push_back(q);
+          HP[t].owner.push_back(p);
+          HP[t].kmax = std::max(HP[t].kmax, H[p]->recs[t].kmax);
+          HP[t].rmax = std::max(HP[t].rmax, H[p]->recs[t].rmax);
+          HP[t].qmax = std::max(HP[t].qmax, H[p]->recs[t].qmax);
+        }
+      HP[t].d_sp = mem.up(HP[t].sp, s);
+      for (int c = 0; c < 9; ++c) {
+        Phase<R>& ph = HP[t].ph[c];
+        ph = Phase<R>{};
+        if (HP[t].sp.size() == 1) {
+          const PhaseHost& P = H[HP[t].owner[0]]->recs[t].ph[c];
+          ph.nbox = (int)P.boxes.size();
+          ph.box = P.d_box;
+          ph.prob = P.d_prob;
+        } else {
+          std::vector<int> box, prob;
+          for (int p = 0; p < np; ++p)
+            if (idxmap[p] >= 0)
+              for (int b : H[p]->recs[t].ph[c].boxes) {
+                box.push_back(b);
+                prob.push_back(idxmap[p]);
+              }
+          ph.nbox = (int)box.size();
+          if (ph.nbox) {
+            ph.box = mem.up(box, s);
+            ph.prob = mem.up(prob, s);
           }
-      } else {
-        std::vector<int> box, prob;
-        for (int p = 0; p < np; ++p)
-          if (idxmap[p] >= 0)
-            for (int b : H[p]->recs[t].ph[c].boxes) {
-              box.push_back(b);
-              prob.push_back(idxmap[p]);
-            }
-        ph.nbox = (int)box.size();
-        if (ph.nbox) {
-          ph.box = scr.up(box, s);
-          ph.prob = scr.up(prob, s);
         }
       }
     }
-  }
-  size_t wel = 1;
-  for (int t = 0; t <= tmax; ++t) {
-    if (solve_group<R>(HP[t].kmax, HP[t].rmax, nrhs_max) == 0)
-      fail(RSS_EUNSUPPORTED, "ranks too large for the solve's LDS panels");
-    for (int c = 0; c < 9; ++c)
-      if (HP[t].ph[c].nbox)
-        wel = std::max(wel, solve_work_elems<R>(HP[t].ph[c].nbox, HP[t].rmax, HP[t].qmax, nrhs_max));
-  }
-  // partial products between the two launches of each sweep step
-  cx<R>* Wk = (cx<R>*)scr.alloc(wel * sizeof(cx<R>));
-  for (int t = 0; t <= tmax; ++t)
-    for (int c = 0; c < 9; ++c)
-      launch_solve_fwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax, Wk, s);
-  // roots
-  {
-    std::vector<RootApply<R>> ra;
-    int nmax = 0;
+    // tiles: the tuned choice for the level's shape, else the defaults; the
+    // work buffer is sized for the largest slice count a tile may take
+    size_t wel = 1;
+    for (int t = 0; t <= tmax; ++t) {
+      HP[t].gmax = solve_group<R>(HP[t].kmax, HP[t].rmax, nrhs_max);
+      if (HP[t].gmax == 0) fail(RSS_EUNSUPPORTED, "ranks too large for the solve's LDS panels");
+      apply_choice(t, tuned_choice(tune_key(t)));
+      for (int c = 0; c < 9; ++c)
+        if (HP[t].ph[c].nbox)
+          wel = std::max(wel, solve_work_elems<R>(HP[t].ph[c].nbox, HP[t].rmax, max_slices(t, c), nrhs_max));
+    }
+    // partial products between the two launches of each sweep step
+    wcap = wel;
+    Wk = (cx<R>*)mem.alloc(wel * sizeof(cx<R>));
     for (int p = 0; p < np; ++p) {
       const int nr = H[p]->n_root;
       if (nr == 0) continue;
@@ -1359,26 +1378,245 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
       q.z = Z[p];
       q.ldz = H[p]->N;
       q.nrhs = nrhs[p];
-      q.ws = (cx<R>*)scr.alloc((size_t)nr * nrhs[p] * 2 * sizeof(cx<R>));
+      q.ws = (cx<R>*)mem.alloc((size_t)nr * nrhs[p] * 2 * sizeof(cx<R>));
       ra.push_back(q);
+      ra_owner.push_back(p);
       nmax = std::max(nmax, nr);
     }
     if (!ra.empty()) {
-      RootApply<R>* d_ra = scr.up(ra, s);
-      GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc(ra.size() * sizeof(GemmDesc<R>));
-      launch_root_apply<R>(d_ra, (int)ra.size(), nmax, nrhs_max, desc, s);
+      d_ra = mem.up(ra, s);
+      desc = (GemmDesc<R>*)mem.alloc(ra.size() * sizeof(GemmDesc<R>));
     }
   }
-  for (int t = tmax; t >= 0; --t)
-    for (int c = 8; c >= 0; --c)
-      launch_solve_bwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax, Wk, s);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));  // scratch descriptors are freed on return
-}
+
+  // Tile choice of a level: the RHS group width as a divisor of the largest
+  // valid one (1, 2 or 4) and the slice count as a multiple of the default
+  // (x1/2, x1 or x2, clamped to 1 .. SOLVE_SMAX).
+  struct Choice {
+    int gdiv = 1, smul = 2;  // smul: 1 = half, 2 = default, 4 = double
+  };
+  static constexpr int NGDIV = 3, NSMUL = 3;
+  static int gdiv_of(int i) { return 1 << i; }
+  static int smul_of(int i) { return 1 << i; }
+  int slices(int t, int c, int smul) const {
+    const int S0 = solve_slices(HP[t].ph[c].nbox, HP[t].qmax);
+    return std::max(1, std::min(SOLVE_SMAX, S0 * smul / 2));
+  }
+  int max_slices(int t, int c) const { return slices(t, c, smul_of(NSMUL - 1)); }
+  void apply_choice(int t, Choice ch) {
+    const int ncg = std::max(1, HP[t].gmax / ch.gdiv);
+    for (int c = 0; c < 9; ++c) HP[t].tile[c] = SolveTile{ncg, slices(t, c, ch.smul)};
+  }
+  // the level's shape as a tuning key: precision, largest valid group width,
+  // the ranks rounded up to 8, the level's box count rounded to a power of two
+  std::array<int, 6> tune_key(int t) const {
+    int nb = 0;
+    for (int c = 0; c < 9; ++c) nb += HP[t].ph[c].nbox;
+    int p2 = 1;
+    while (p2 < nb) p2 <<= 1;
+    return {(int)sizeof(R), HP[t].gmax, (HP[t].kmax + 7) / 8, (HP[t].rmax + 7) / 8,
+            (HP[t].qmax + 31) / 32, p2};
+  }
+
+  // Measure the tile choices of every level on this plan's shapes (vectors
+  // of zeros, so the caller's data is untouched) and record the fastest: per
+  // level, first the group width at the default slice count, then the slice
+  // count at that width, each timed as the whole apply (best of two).  Levels
+  // whose key is already tuned keep their choice.
+  void autotune(const std::vector<int64_t>& N, const std::vector<int>& nrhs, Scratch& mem, hipStream_t s) {
+    std::vector<int> todo;
+    for (int t = 0; t <= tmax; ++t)
+      if (!tuned_lookup(tune_key(t), nullptr)) todo.push_back(t);
+    if (todo.empty()) return;
+    std::vector<cx<R>*> Zt;
+    for (size_t p = 0; p < N.size(); ++p) {
+      const size_t bytes = (size_t)N[p] * nrhs[p] * sizeof(cx<R>);
+      cx<R>* z = (cx<R>*)mem.alloc(bytes);
+      HIPCHK(hipMemsetAsync(z, 0, bytes, s));
+      Zt.push_back(z);
+    }
+    std::vector<cx<R>*> Zsave = current_z();
+    set_z(Zt, s);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_apply = [&]() {
+      float best = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(hipEventRecord(e0, s));
+        launch(s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return best;
+    };
+    launch(s);  // warm-up
+    for (int t : todo) {
+      Choice best;
+      float tb = 1e30f;
+      for (int gi = 0; gi < NGDIV; ++gi) {
+        Choice ch;
+        ch.gdiv = gdiv_of(gi);
+        if (gi > 0 && HP[t].gmax / ch.gdiv < 1) break;
+        apply_choice(t, ch);
+        const float ms = time_apply();
+        if (ms < tb) tb = ms, best = ch;
+      }
+      for (int si = 0; si < NSMUL; ++si) {
+        Choice ch = best;
+        ch.smul = smul_of(si);
+        if (ch.smul == 2) continue;  // the default, timed above
+        apply_choice(t, ch);
+        const float ms = time_apply();
+        if (ms < tb) tb = ms, best = ch;
+      }
+      apply_choice(t, best);
+      tuned_store(tune_key(t), best);
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    set_z(Zsave, s);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  std::vector<cx<R>*> current_z() const {
+    // the vectors as the descriptors hold them, by problem
+    int np = 0;
+    for (auto& hp : HP)
+      for (int o : hp.owner) np = std::max(np, o + 1);
+    for (int o : ra_owner) np = std::max(np, o + 1);
+    std::vector<cx<R>*> Z(np, nullptr);
+    for (auto& hp : HP)
+      for (size_t e = 0; e < hp.sp.size(); ++e) Z[hp.owner[e]] = hp.sp[e].z;
+    for (size_t e = 0; e < ra.size(); ++e) Z[ra_owner[e]] = ra[e].z;
+    return Z;
+  }
+
+  // process-wide table of tuned choices (shared by all handles and servers)
+  static std::mutex& tuned_mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::map<std::array<int, 6>, Choice>& tuned_table() {
+    static std::map<std::array<int, 6>, Choice> m;
+    return m;
+  }
+  static bool tuned_lookup(const std::array<int, 6>& key, Choice* out) {
+    std::lock_guard<std::mutex> lk(tuned_mu());
+    auto it = tuned_table().find(key);
+    if (it == tuned_table().end()) return false;
+    if (out) *out = it->second;
+    return true;
+  }
+  static Choice tuned_choice(const std::array<int, 6>& key) {
+    Choice ch;
+    tuned_lookup(key, &ch);
+    return ch;
+  }
+  static void tuned_store(const std::array<int, 6>& key, Choice ch) {
+    std::lock_guard<std::mutex> lk(tuned_mu());
+    tuned_table()[key] = ch;
+  }
+
+  // point the descriptor tables at new vectors (same shapes as at build)
+  void set_z(const std::vector<cx<R>*>& Z, hipStream_t s) {
+    for (auto& hp : HP) {
+      for (size_t e = 0; e < hp.sp.size(); ++e) hp.sp[e].z = Z[hp.owner[e]];
+      HIPCHK(hipMemcpyAsync(hp.d_sp, hp.sp.data(), hp.sp.size() * sizeof(SolveProb<R>),
+                            hipMemcpyHostToDevice, s));
+    }
+    if (!ra.empty()) {
+      for (size_t e = 0; e < ra.size(); ++e) ra[e].z = Z[ra_owner[e]];
+      HIPCHK(hipMemcpyAsync(d_ra, ra.data(), ra.size() * sizeof(RootApply<R>), hipMemcpyHostToDevice, s));
+    }
+  }
+
+  // the kernel launches only (no copies, allocations or synchronisation), so
+  // that a stream capture records exactly these
+  void launch(hipStream_t s) const {
+    for (int t = 0; t <= tmax; ++t)
+      for (int c = 0; c < 9; ++c)
+        launch_solve_fwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax,
+                            HP[t].tile[c], Wk, s);
+    if (!ra.empty()) launch_root_apply<R>(d_ra, (int)ra.size(), nmax, nrhs_max, desc, s);
+    for (int t = tmax; t >= 0; --t)
+      for (int c = 8; c >= 0; --c)
+        launch_solve_bwd<R>(HP[t].d_sp, HP[t].ph[c], nrhs_max, HP[t].kmax, HP[t].rmax, HP[t].qmax,
+                            HP[t].tile[c], Wk, s);
+  }
+};
+
+// An apply plan of one handle captured into a HIP graph: its memory, the
+// captured graph and the executable instance, kept in the handle per
+// (precision, nrhs) and replayed by every later apply of that shape.
+template <class R>
+struct ApplyGraph : ApplyGraphBase {
+  Scratch mem;
+  ApplyPlan<R> plan;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~ApplyGraph() override {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+std::atomic<bool> g_use_graphs{true};
+std::atomic<bool> g_autotune{true};
 
 template <class R>
-void apply_impl(rss_ctx* h, cx<R>* z, int nrhs) {
-  apply_batch<R>(std::vector<rss_ctx*>{h}, std::vector<cx<R>*>{z}, std::vector<int>{nrhs}, h->stream);
+void maybe_autotune(ApplyPlan<R>& plan, const std::vector<rss_ctx*>& H, const std::vector<int>& nrhs,
+                    hipStream_t s) {
+  if (!g_autotune.load()) return;
+  std::vector<int64_t> N;
+  for (auto* h : H) N.push_back(h->N);
+  Scratch tmp;
+  plan.autotune(N, nrhs, tmp, s);
+}
+
+// z_p <- F_p^{-1} z_p for every handle of a batch (complex<R>, N_p x nrhs_p,
+// ld N_p), on stream s: one launch per (height, colour) and direction.  A
+// batch of one handle replays that handle's captured graph for this nrhs
+// (captured on first use); a batch of several handles launches its merged
+// plan directly.
+template <class R>
+void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
+                 const std::vector<int>& nrhs, hipStream_t s) {
+  if (H.size() == 1 && g_use_graphs.load()) {
+    rss_ctx* h = H[0];
+    const std::pair<int, int> key{(int)sizeof(R), nrhs[0]};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+      std::unique_ptr<ApplyGraph<R>> g(new ApplyGraph<R>());
+      g->plan.build(H, Z, nrhs, g->mem, s);
+      maybe_autotune(g->plan, H, nrhs, s);
+      HIPCHK(hipStreamSynchronize(s));  // descriptor uploads done before the capture
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      g->plan.launch(s);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s, &graph);
+      g->graph = graph;
+      HIPCHK(ec);
+      HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+      it = h->graphs.emplace(key, std::move(g)).first;
+    }
+    ApplyGraph<R>* g = static_cast<ApplyGraph<R>*>(it->second.get());
+    g->plan.set_z(Z, s);
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));  // the host copies of the descriptors are reused next call
+    return;
+  }
+  Scratch scr;
+  ApplyPlan<R> plan;
+  plan.build(H, Z, nrhs, scr, s);
+  maybe_autotune(plan, H, nrhs, s);
+  plan.launch(s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));  // scratch descriptors are freed on return
 }
 
 int run(const std::function<void()>& f) {
@@ -1788,6 +2026,10 @@ int rss_set_stream(rss_handle h, void* stream) {
   h->stream = (hipStream_t)stream;
   return RSS_OK;
 }
+
+int rss_set_graphs(int enable) { return g_use_graphs.exchange(enable != 0) ? 1 : 0; }
+
+int rss_set_autotune(int enable) { return g_autotune.exchange(enable != 0) ? 1 : 0; }
 
 const char* rss_last_error(void) { return g_err.c_str(); }
 

@@ -172,16 +172,25 @@ void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, GemmDesc<R>
                          hipStream_t s);
 // workspace entries of RootDesc::W for a root of size n
 size_t root_work_elems(int n);
+// Tile of the solve sweeps of one colour phase: ncg right-hand sides per
+// workgroup (1 .. solve_group) and S workgroups per box for the two wide
+// products (slices of their summation; 1 .. SOLVE_SMAX).
+struct SolveTile {
+  int ncg, S;
+};
+constexpr int SOLVE_SMAX = 64;
+// the default slice count: enough workgroups for the chip when a colour holds few boxes
+int solve_slices(int nbox, int qmax);
 // solve sweeps of one colour phase; W: scratch of solve_work_elems entries
 // (qmax: largest k + |N| of the phase's level)
 template <class R>
 void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      int qmax, cx<R>* W, hipStream_t s);
+                      int qmax, SolveTile tile, cx<R>* W, hipStream_t s);
 template <class R>
 void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      int qmax, cx<R>* W, hipStream_t s);
+                      int qmax, SolveTile tile, cx<R>* W, hipStream_t s);
 template <class R>
-size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs);
+size_t solve_work_elems(int nbox, int rmax, int S, int nrhs);
 // batched root apply: z[ids] <- Ainv z[ids] per problem (ws: 2 n nrhs entries per problem)
 template <class R>
 struct RootApply {

@@ -1870,8 +1870,8 @@ int solve_slices(int nbox, int qmax) {
 }
 
 template <class R>
-size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs) {
-  return (size_t)nbox * solve_slices(nbox, qmax) * rmax * nrhs;
+size_t solve_work_elems(int nbox, int rmax, int S, int nrhs) {
+  return (size_t)nbox * S * rmax * nrhs;
 }
 
 // forward, part 1 (one workgroup per box and column group):
@@ -1958,10 +1958,10 @@ __global__ __launch_bounds__(256) void k_solve_fwd_b(const SolveProb<R>* sp, Pha
 
 template <class R>
 void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      int qmax, cx<R>* W, hipStream_t s) {
-  const int ncg = solve_group<R>(kmax, rmax, nrhs);
-  if (ph.nbox == 0 || ncg == 0) return;  // ncg == 0 is rejected by the caller
-  const int S = solve_slices(ph.nbox, qmax);
+                      int qmax, SolveTile tile, cx<R>* W, hipStream_t s) {
+  (void)qmax;
+  const int ncg = tile.ncg, S = tile.S;
+  if (ph.nbox == 0 || ncg <= 0 || S <= 0) return;  // the caller validates the tile
   const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
   const dim3 groups((nrhs + ncg - 1) / ncg);
   hipLaunchKernelGGL(k_solve_fwd_a<R>, dim3(ph.nbox, groups.x), dim3(256),
@@ -2076,11 +2076,10 @@ __global__ __launch_bounds__(256) void k_solve_bwd_b(const SolveProb<R>* sp, Pha
 
 template <class R>
 void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
-                      int qmax, cx<R>* W, hipStream_t s) {
+                      int qmax, SolveTile tile, cx<R>* W, hipStream_t s) {
   (void)kmax;
-  const int ncg = solve_group<R>(kmax, rmax, nrhs);
-  if (ph.nbox == 0 || ncg == 0) return;  // ncg == 0 is rejected by the caller
-  const int S = solve_slices(ph.nbox, qmax);
+  const int ncg = tile.ncg, S = tile.S;
+  if (ph.nbox == 0 || ncg <= 0 || S <= 0) return;  // the caller validates the tile
   const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
   const dim3 groups((nrhs + ncg - 1) / ncg);
   // z_{S,N} chunk: one slice's rows if they fit, else what is left of the budget (>= 16 rows)
@@ -2243,9 +2242,9 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \
                                          const Prob<R>*, hipStream_t);                             \
   template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t);           \
-  template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \
+  template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, \
                                     cx<R>*, hipStream_t);                                          \
-  template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int,      \
+  template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, \
                                     cx<R>*, hipStream_t);                                          \
   template size_t solve_work_elems<R>(int, int, int, int);                                           \
   template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);  \

@@ -50,7 +50,7 @@ class rss_stats(ctypes.Structure):
 
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
            "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
-           "rss_set_stream", "rss_server_create", "rss_server_factor", "rss_server_solve",
+           "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
 
@@ -118,6 +118,8 @@ def load():
     lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
     lib.rss_solve_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
     lib.rss_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.rss_set_graphs.argtypes = [ctypes.c_int]
+    lib.rss_set_autotune.argtypes = [ctypes.c_int]
     lib.rss_server_create.argtypes = [P(rss_server_options), P(ctypes.c_void_p)]
     lib.rss_server_factor.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, P(rss_kernel),
                                       P(ctypes.c_int64)]
@@ -285,6 +287,18 @@ def apply_batch(facts, Bs):
     bs = (ctypes.c_void_p * n)(*[B.data_ptr() for B in Bs])
     nr = (ctypes.c_int * n)(*[f._b(B) for f, B in zip(facts, Bs)])
     _check(load().rss_apply_batch(n, hs, bs, nr))
+
+
+def set_graphs(enable: bool) -> bool:
+    """rss_set_graphs: replay captured HIP graphs for single-handle applies
+    (default) or launch every apply directly.  Returns the previous setting."""
+    return bool(load().rss_set_graphs(1 if enable else 0))
+
+
+def set_autotune(enable: bool) -> bool:
+    """rss_set_autotune: time candidate solve tiles on first use of a level
+    shape (default) or keep the default tiles.  Returns the previous setting."""
+    return bool(load().rss_set_autotune(1 if enable else 0))
 
 
 def kernel_block(kern, points_dev, I_dev, J_dev):

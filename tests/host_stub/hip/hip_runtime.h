@@ -16,6 +16,9 @@
 typedef int hipError_t;
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;
+typedef struct ihipGraph_t* hipGraph_t;
+typedef struct ihipGraphExec_t* hipGraphExec_t;
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1, hipStreamCaptureModeRelaxed = 2 };
 enum { hipSuccess = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3,
        hipStreamNonBlocking = 1 };
 typedef int hipMemcpyKind;
@@ -35,6 +38,12 @@ inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) { memset
 inline hipError_t hipStreamSynchronize(hipStream_t) { return 0; }
 inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = (hipStream_t)malloc(8); return 0; }
 inline hipError_t hipStreamDestroy(hipStream_t s) { free(s); return 0; }
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return 0; }
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = (hipGraph_t)malloc(8); return 0; }
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t, void*, char*, size_t) { *e = (hipGraphExec_t)malloc(8); return 0; }
+inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return 0; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) { free(e); return 0; }
+inline hipError_t hipGraphDestroy(hipGraph_t g) { free(g); return 0; }
 inline hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t)malloc(8); return 0; }
 inline hipError_t hipEventDestroy(hipEvent_t e) { free(e); return 0; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return 0; }

@@ -18,9 +18,10 @@ template <class R> void launch_schur(const Prob<R>*, const Phase<R>&, int, hipSt
 template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
 template <class R> void launch_root_inverse(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t) {}
 size_t root_work_elems(int n) { return (size_t)65 * n; }
-template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
-template <class R> size_t solve_work_elems(int nbox, int rmax, int qmax, int nrhs) { return (size_t)nbox * rmax * nrhs + qmax; }
-template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t) {}
+template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, cx<R>*, hipStream_t) {}
+template <class R> size_t solve_work_elems(int nbox, int rmax, int S, int nrhs) { return (size_t)nbox * S * rmax * nrhs; }
+template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, cx<R>*, hipStream_t) {}
+int solve_slices(int nbox, int) { return nbox < 64 ? 4 : 1; }
 template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t) {}
 #define I(R) \
 template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
@@ -37,9 +38,9 @@ template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
 template void launch_schur<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \
 template void launch_root_inverse<R>(const RootDesc<R>*, int, int, GemmDesc<R>*, int*, hipStream_t); \
-template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \
+template void launch_solve_fwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, cx<R>*, hipStream_t); \
 template size_t solve_work_elems<R>(int, int, int, int); \
-template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, cx<R>*, hipStream_t); \
+template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, cx<R>*, hipStream_t); \
 template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
 I(double) I(float)
 void launch_kernel_block(const KParams&, const double*, const int*, int64_t, const int*, int64_t, cx<double>*, hipStream_t) {}

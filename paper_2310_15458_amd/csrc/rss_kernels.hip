@@ -1126,7 +1126,9 @@ struct Mfma<float> {
 
 // One 64 x 64 tile of C(i0 + ., j0 + .) = A (M x K, leading dimension lda)
 // times B (K x N, ldb): four waves, each a 32 x 32 quarter on the matrix cores
-// (4 real MFMAs per complex product).  The waves compute B^T A^T so that
+// (4 real MFMAs per complex product), K in slices of 16 staged in LDS, the
+// next slice's loads in flight during the current slice's MFMAs, and no MFMA
+// steps past K in the last slice.  The waves compute B^T A^T so that
 // consecutive lanes hold consecutive rows of C; emit(i, j, re, im) receives
 // every element inside M x N (complex64 form: the K slices summed in FP64).
 template <class R, class Emit>
@@ -1149,18 +1151,36 @@ __device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* 
 #pragma unroll
       for (int v = 0; v < 4; ++v) fr[a][b][v] = fi[a][b][v] = 0.0;
     }
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = threadIdx.x; e < 1024; e += 256) {
+  // this thread's four A and four B entries of a K slice, loaded into
+  // registers one slice ahead so that the loads overlap the previous slice's
+  // MFMAs
+  cx<R> ra[4], rb[4];
+  auto load_slice = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
       const int i = e & 63, kk = e >> 6;
       const int gi = i0 + i, gk = k0 + kk;
-      As[kk][i] = (gi < Mr && gk < K) ? A[gi + (int64_t)gk * lda] : czero<R>();
+      ra[u] = (gi < Mr && gk < K) ? A[gi + (int64_t)gk * lda] : czero<R>();
       const int kb = e & 15, j = e >> 4;
       const int gj = j0 + j, gkb = k0 + kb;
-      Bs[kb][j] = (gj < Nc && gkb < K) ? B[gkb + (int64_t)gj * ldb] : czero<R>();
+      rb[u] = (gj < Nc && gkb < K) ? B[gkb + (int64_t)gj * ldb] : czero<R>();
+    }
+  };
+  load_slice(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      As[e >> 6][e & 63] = ra[u];
+      Bs[e & 15][e >> 4] = rb[u];
     }
     __syncthreads();
+    if (k0 + 16 < K) load_slice(k0 + 16);
+    const int kc = min(16, K - k0);  // steps of 4 past kc would multiply zeros
 #pragma unroll
     for (int k4 = 0; k4 < 16; k4 += 4) {
+      if (k4 >= kc) break;
       const int kk = k4 + (l >> 4);
       cx<R> av[2], bv[2];
 #pragma unroll

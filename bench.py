@@ -101,7 +101,10 @@ def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
     jobs, Helmholtz kappa ~ U[10,60], FP32+refine to 1e-10, 200 GB budget, LRU),
     with fewer requests, sides {128, 256} and nrhs <= 16 so that it runs in
     seconds (every solve pays O(N^2) FP64 residuals).  The arrival rate is
-    `load` times the capacity measured on one factor and one solve per side."""
+    `load` times the capacity measured on one factor and one solve per side.
+    Before that, one solve per side and right-hand-side bucket (1, 2, 4, 8, 16)
+    lets the solve-tile autotuner settle its one-time choices for those level
+    shapes, as a long-running server would have done before this stream."""
     from paper_2310_15458_amd import serve
     t_f, t_s = [], []
     for n in sides:
@@ -111,6 +114,11 @@ def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
         t0 = time.perf_counter()
         F = rss.Factorization(P, k, 1e-6, 64, precision="fp32")
         t1 = time.perf_counter()
+        nb = 1
+        while nb <= max_nrhs:  # the autotuner's one-time tuning for this side
+            Bw = torch.from_numpy(np.ascontiguousarray(W.rhs(n * n, nb, 6).T)).cuda().t()
+            F.solve(Bw)
+            nb *= 2
         Bh = W.rhs(n * n, max_nrhs // 2, 5)
         B = torch.from_numpy(np.ascontiguousarray(Bh.T)).cuda().t()
         torch.cuda.synchronize()
@@ -127,7 +135,7 @@ def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
     res["rate_per_s"] = rate
     res["stream"] = (f"{count} requests, Poisson rate {rate:.2f}/s (= {load} x measured capacity), "
                      f"sides {list(sides)}, nrhs U{{1..{max_nrhs}}}, 20% factor jobs, seed 4, "
-                     f"FP32+refine to 1e-10, budget 200 GB")
+                     f"FP32+refine to 1e-10, budget 200 GB, solve tiles tuned before the stream")
     return res
 
 

@@ -246,9 +246,9 @@ int rss_set_graphs(int enable);
  * autotuner.  Each level of a solve (one tree height of one or more handles)
  * runs its sweeps with a tile: the right-hand sides per workgroup and the
  * workgroups per box of its two wide products.  With the switch on, the first
- * apply that meets a level shape not seen before (precision, largest group
- * width, largest skeleton and redundant counts rounded up to 8, largest
- * k + |N| rounded up to 32, box count rounded up to a power of two) times the candidate tiles on that apply's own shapes (on
+ * apply that meets a level shape not seen before (precision; largest group
+ * width and box count, each rounded up to a power of two; largest skeleton
+ * and redundant counts rounded up to 8; largest k + |N| rounded up to 32) times the candidate tiles on that apply's own shapes (on
  * vectors of zeros: the caller's data is untouched) and keeps the fastest for
  * the rest of the process; later applies of that shape, across handles and
  * servers, reuse it.  Off: untuned shapes use the default tile.  A tile that

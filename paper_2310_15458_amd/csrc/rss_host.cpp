@@ -1407,21 +1407,24 @@ struct ApplyPlan {
     const int ncg = std::max(1, HP[t].gmax / ch.gdiv);
     for (int c = 0; c < 9; ++c) HP[t].tile[c] = SolveTile{ncg, slices(t, c, ch.smul)};
   }
-  // the level's shape as a tuning key: precision, largest valid group width,
-  // the ranks rounded up to 8, the level's box count rounded to a power of two
+  // the level's shape as a tuning key: precision, largest valid group width
+  // and box count rounded up to powers of two, the ranks rounded up to 8
   std::array<int, 6> tune_key(int t) const {
+    auto pow2 = [](int v) {
+      int p = 1;
+      while (p < v) p <<= 1;
+      return p;
+    };
     int nb = 0;
     for (int c = 0; c < 9; ++c) nb += HP[t].ph[c].nbox;
-    int p2 = 1;
-    while (p2 < nb) p2 <<= 1;
-    return {(int)sizeof(R), HP[t].gmax, (HP[t].kmax + 7) / 8, (HP[t].rmax + 7) / 8,
-            (HP[t].qmax + 31) / 32, p2};
+    return {(int)sizeof(R), pow2(HP[t].gmax), (HP[t].kmax + 7) / 8, (HP[t].rmax + 7) / 8,
+            (HP[t].qmax + 31) / 32, pow2(nb)};
   }
 
   // Measure the tile choices of every level on this plan's shapes (vectors
   // of zeros, so the caller's data is untouched) and record the fastest: per
   // level, first the group width at the default slice count, then the slice
-  // count at that width, each timed as the whole apply (best of two).  Levels
+  // count at that width, each timed as one whole apply after a warm-up.  Levels
   // whose key is already tuned keep their choice.
   void autotune(const std::vector<int64_t>& N, const std::vector<int>& nrhs, Scratch& mem, hipStream_t s) {
     std::vector<int> todo;
@@ -1441,17 +1444,13 @@ struct ApplyPlan {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     auto time_apply = [&]() {
-      float best = 1e30f;
-      for (int rep = 0; rep < 2; ++rep) {
-        HIPCHK(hipEventRecord(e0, s));
-        launch(s);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        best = std::min(best, ms);
-      }
-      return best;
+      HIPCHK(hipEventRecord(e0, s));
+      launch(s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
     };
     launch(s);  // warm-up
     for (int t : todo) {

@@ -253,6 +253,8 @@ int rss_set_graphs(int enable);
  * the rest of the process; later applies of that shape, across handles and
  * servers, reuse it.  Off: untuned shapes use the default tile.  A tile that
  * splits a summation differently changes results at the rounding level only.
+ * Inside the solve server, batches that merge several handles reuse what is
+ * tuned and otherwise take the default tile (no tuning on request latency).
  * enable: 0 or 1; returns the previous setting.
  */
 int rss_set_autotune(int enable);

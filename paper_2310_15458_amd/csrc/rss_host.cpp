@@ -1565,11 +1565,18 @@ struct ApplyGraph : ApplyGraphBase {
 
 std::atomic<bool> g_use_graphs{true};
 std::atomic<bool> g_autotune{true};
+}  // namespace
+namespace rss {
+thread_local bool g_server_thread = false;
+}
+namespace {
 
 template <class R>
 void maybe_autotune(ApplyPlan<R>& plan, const std::vector<rss_ctx*>& H, const std::vector<int>& nrhs,
                     hipStream_t s) {
-  if (!g_autotune.load()) return;
+  // the server's merged batches only reuse tuned shapes: their compositions
+  // vary, and tuning inside a request stream would land on request latency
+  if (!g_autotune.load() || (H.size() != 1 && g_server_thread)) return;
   std::vector<int64_t> N;
   for (auto* h : H) N.push_back(h->N);
   Scratch tmp;

@@ -240,4 +240,8 @@ void launch_cast_c64(const cx<double>* V, int64_t n, int nrhs, cx<float>* out, h
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_t s);
 
+// set on the solve server's worker threads: batches of several handles there
+// reuse tuned solve tiles but do not tune (see rss_set_autotune)
+extern thread_local bool g_server_thread;
+
 }  // namespace rss

@@ -27,6 +27,12 @@
 
 #include "rss.h"
 
+namespace rss {
+// defined with the host driver: marks the server's worker threads, whose
+// merged solve batches reuse tuned solve tiles without tuning
+extern thread_local bool g_server_thread;
+}  // namespace rss
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -262,8 +268,14 @@ int rss_server_create(const rss_server_options* o, rss_server_t* out) {
     return RSS_EHIP;
   }
   rss_server* p = s.get();
-  p->tf = std::thread([p] { p->factor_loop(); });
-  p->ts = std::thread([p] { p->solve_loop(); });
+  p->tf = std::thread([p] {
+    rss::g_server_thread = true;
+    p->factor_loop();
+  });
+  p->ts = std::thread([p] {
+    rss::g_server_thread = true;
+    p->solve_loop();
+  });
   *out = s.release();
   return RSS_OK;
 }

@@ -255,7 +255,12 @@ int rss_set_graphs(int enable);
  * splits a summation differently changes results at the rounding level only.
  * Inside the solve server, batches that merge several handles reuse what is
  * tuned and otherwise take the default tile (no tuning on request latency).
- * enable: 0 or 1; returns the previous setting.
+ * The candidates per level: 1, 1/2 or 1/4 of the widest group that fits the
+ * LDS budget; half, the default or twice the default workgroups per box; and
+ * the fused tile (each sweep step in one launch, one workgroup per box).
+ * enable: 0 (off), 1 (on) or 2 (no timing: every level takes the fused tile
+ * where its LDS fits, the default tile elsewhere; for tests and comparisons).
+ * Returns the previous setting, or RSS_EINVAL for another value.
  */
 int rss_set_autotune(int enable);
 

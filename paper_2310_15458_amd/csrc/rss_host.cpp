@@ -1394,6 +1394,7 @@ struct ApplyPlan {
   // (x1/2, x1 or x2, clamped to 1 .. SOLVE_SMAX).
   struct Choice {
     int gdiv = 1, smul = 2;  // smul: 1 = half, 2 = default, 4 = double
+    bool fused = false;      // each sweep step in one launch (one workgroup per box)
   };
   static constexpr int NGDIV = 3, NSMUL = 3;
   static int gdiv_of(int i) { return 1 << i; }
@@ -1403,9 +1404,13 @@ struct ApplyPlan {
     return std::max(1, std::min(SOLVE_SMAX, S0 * smul / 2));
   }
   int max_slices(int t, int c) const { return slices(t, c, smul_of(NSMUL - 1)); }
+  bool fused_ok(int t, Choice ch) const {
+    return solve_fused_fits<R>(HP[t].kmax, HP[t].rmax, std::max(1, HP[t].gmax / ch.gdiv));
+  }
   void apply_choice(int t, Choice ch) {
     const int ncg = std::max(1, HP[t].gmax / ch.gdiv);
-    for (int c = 0; c < 9; ++c) HP[t].tile[c] = SolveTile{ncg, slices(t, c, ch.smul)};
+    const bool fused = ch.fused && fused_ok(t, ch);
+    for (int c = 0; c < 9; ++c) HP[t].tile[c] = SolveTile{ncg, fused ? 1 : slices(t, c, ch.smul), fused};
   }
   // the level's shape as a tuning key: precision, largest valid group width
   // and box count rounded up to powers of two, the ranks rounded up to 8
@@ -1424,7 +1429,8 @@ struct ApplyPlan {
   // Measure the tile choices of every level on this plan's shapes (vectors
   // of zeros, so the caller's data is untouched) and record the fastest: per
   // level, first the group width at the default slice count, then the slice
-  // count at that width, each timed as one whole apply after a warm-up.  Levels
+  // count at that width, then the fused kernels at that width, each timed as
+  // one whole apply after a warm-up.  Levels
   // whose key is already tuned keep their choice.
   void autotune(const std::vector<int64_t>& N, const std::vector<int>& nrhs, Scratch& mem, hipStream_t s) {
     std::vector<int> todo;
@@ -1472,6 +1478,15 @@ struct ApplyPlan {
         const float ms = time_apply();
         if (ms < tb) tb = ms, best = ch;
       }
+      {
+        Choice ch = best;
+        ch.fused = true;
+        if (fused_ok(t, ch)) {
+          apply_choice(t, ch);
+          const float ms = time_apply();
+          if (ms < tb) tb = ms, best = ch;
+        }
+      }
       apply_choice(t, best);
       tuned_store(tune_key(t), best);
     }
@@ -1479,6 +1494,14 @@ struct ApplyPlan {
     HIPCHK(hipEventDestroy(e1));
     set_z(Zsave, s);
     HIPCHK(hipStreamSynchronize(s));
+  }
+
+  void force_fused() {
+    for (int t = 0; t <= tmax; ++t) {
+      Choice ch;
+      ch.fused = true;
+      apply_choice(t, ch);
+    }
   }
 
   std::vector<cx<R>*> current_z() const {
@@ -1565,6 +1588,7 @@ struct ApplyGraph : ApplyGraphBase {
 
 std::atomic<bool> g_use_graphs{true};
 std::atomic<bool> g_autotune{true};
+std::atomic<int> g_autotune_mode{1};
 }  // namespace
 namespace rss {
 thread_local bool g_server_thread = false;
@@ -1576,6 +1600,10 @@ void maybe_autotune(ApplyPlan<R>& plan, const std::vector<rss_ctx*>& H, const st
                     hipStream_t s) {
   // the server's merged batches only reuse tuned shapes: their compositions
   // vary, and tuning inside a request stream would land on request latency
+  if (g_autotune_mode.load() == 2) {  // every level fused where it fits (no timing)
+    plan.force_fused();
+    return;
+  }
   if (!g_autotune.load() || (H.size() != 1 && g_server_thread)) return;
   std::vector<int64_t> N;
   for (auto* h : H) N.push_back(h->N);
@@ -2035,7 +2063,14 @@ int rss_set_stream(rss_handle h, void* stream) {
 
 int rss_set_graphs(int enable) { return g_use_graphs.exchange(enable != 0) ? 1 : 0; }
 
-int rss_set_autotune(int enable) { return g_autotune.exchange(enable != 0) ? 1 : 0; }
+int rss_set_autotune(int enable) {
+  if (enable < 0 || enable > 2) {
+    g_err = "rss_set_autotune takes 0, 1 or 2";
+    return RSS_EINVAL;
+  }
+  g_autotune.exchange(enable == 1);
+  return g_autotune_mode.exchange(enable);
+}
 
 const char* rss_last_error(void) { return g_err.c_str(); }
 

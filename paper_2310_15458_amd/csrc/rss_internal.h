@@ -174,10 +174,15 @@ void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, GemmDesc<R>
 size_t root_work_elems(int n);
 // Tile of the solve sweeps of one colour phase: ncg right-hand sides per
 // workgroup (1 .. solve_group) and S workgroups per box for the two wide
-// products (slices of their summation; 1 .. SOLVE_SMAX).
+// products (slices of their summation; 1 .. SOLVE_SMAX); fused: each sweep
+// step in one launch, one workgroup per box (the arithmetic of S = 1).
 struct SolveTile {
   int ncg, S;
+  bool fused;
 };
+// whether the fused tile's LDS fits for a level
+template <class R>
+bool solve_fused_fits(int kmax, int rmax, int ncg);
 constexpr int SOLVE_SMAX = 64;
 // the default slice count: enough workgroups for the chip when a colour holds few boxes
 int solve_slices(int nbox, int qmax);

@@ -1939,6 +1939,59 @@ __global__ __launch_bounds__(256) void k_solve_fwd_a(const SolveProb<R>* sp, Pha
   }
 }
 
+// forward in one workgroup per box and column group (the fused tile):
+// z_R -= T^* z_S;  w = X_RR^{-1} z_R kept in LDS;  z_R written back;
+// z_{S,N} -= [X_SR; X_NR] w.  Same arithmetic as parts 1 and 2 with one slice.
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_fwd_fused(const SolveProb<R>* sp, Phase<R> ph, int kmax,
+                                                         int rmax, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sld = ncg + 1;
+  cx<R>* zS = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* zR = zS + (int64_t)kmax * sld;
+  cx<R>* red = zR + (int64_t)rmax * sld;
+  cx<R>* w = red + (int64_t)SRED * sld;
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * ncg;
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(ncg, pr.nrhs - c0);
+  const int* gS = rec.G + rec.oS[b];
+  const int* gR = rec.G + rec.oR[b];
+  const int* gN = rec.G + rec.oN[b];
+  const cx<R>* T = rec.F + rec.oT[b];
+  const cx<R>* Xi = rec.F + rec.oXi[b];
+  const cx<R>* XS = rec.F + rec.oXSNR[b];
+  gather(zS, sld, z, ldz, c0, k, nc, [&](int i) { return gS[i]; });
+  gather(zR, sld, z, ldz, c0, r, nc, [&](int i) { return gR[i]; });
+  __syncthreads();
+  blk_mm<R, true>(T, k, r, 0, k, zS, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) zR[a * sld + c] = zR[a * sld + c] - v[c];
+  });
+  __syncthreads();
+  blk_mm<R, false>(Xi, r, r, 0, r, zR, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) w[a * sld + c] = v[c];
+  });
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = zR[a * sld + c];
+  }
+  const int q = k + nN;
+  blk_mm<R, false>(XS, q, q, 0, r, w, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+    sub_row(z, ldz, a < k ? gS[a] : gN[a - k], c0, nc, v);
+  });
+}
+
 // forward, part 2 (S workgroups per box, each a slice of rows):
 // z_{S,N} -= [X_SR; X_NR] w
 template <class R>
@@ -1984,6 +2037,11 @@ void launch_solve_fwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int 
   if (ph.nbox == 0 || ncg <= 0 || S <= 0) return;  // the caller validates the tile
   const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
   const dim3 groups((nrhs + ncg - 1) / ncg);
+  if (tile.fused) {
+    hipLaunchKernelGGL(k_solve_fwd_fused<R>, dim3(ph.nbox, groups.x), dim3(256),
+                       (size_t)(kmax + 2 * rmax + SRED) * row, s, sp, ph, kmax, rmax, ncg);
+    return;
+  }
   hipLaunchKernelGGL(k_solve_fwd_a<R>, dim3(ph.nbox, groups.x), dim3(256),
                      (size_t)(kmax + rmax + SRED) * row, s, sp, ph, kmax, rmax, ncg, W, nrhs);
   hipLaunchKernelGGL(k_solve_fwd_b<R>, dim3(ph.nbox * S, groups.x), dim3(256),
@@ -2094,6 +2152,82 @@ __global__ __launch_bounds__(256) void k_solve_bwd_b(const SolveProb<R>* sp, Pha
   }
 }
 
+// backward in one workgroup per box and column group (the fused tile):
+// p = Y z_{S,N} (chunks of z_{S,N} in LDS, summed in chunk order);
+// x_R = X_RR^{-1} z_R - p;  z_S -= T x_R;  z_R = x_R.  Same arithmetic as
+// parts 1 and 2 with one slice.
+template <class R>
+__global__ __launch_bounds__(256) void k_solve_bwd_fused(const SolveProb<R>* sp, Phase<R> ph, int rmax,
+                                                         int chunk, int ncg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int sld = ncg + 1;
+  cx<R>* xp = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* red = xp + (int64_t)rmax * sld;
+  cx<R>* zq = red + (int64_t)SRED * sld;  // chunk rows of z_{S,N}; then z_R and x_R
+  cx<R>* zR = zq;
+  cx<R>* xR = zq + (int64_t)rmax * sld;
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const SolveProb<R> pr = sp[ph.prob[slot]];
+  const Records<R>& rec = pr.rec;
+  cx<R>* z = pr.z;
+  const int64_t ldz = pr.ldz;
+  const int k = rec.k[b], r = rec.r[b], nN = rec.nN[b];
+  if (r == 0) return;
+  const int c0 = blockIdx.y * ncg;
+  if (c0 >= pr.nrhs) return;
+  const int nc = min(ncg, pr.nrhs - c0);
+  const int q = k + nN;
+  const int* gS = rec.G + rec.oS[b];
+  const int* gR = rec.G + rec.oR[b];
+  const int* gN = rec.G + rec.oN[b];
+  const cx<R>* Y = rec.F + rec.oY[b];
+  const cx<R>* T = rec.F + rec.oT[b];
+  const cx<R>* Xi = rec.F + rec.oXi[b];
+  for (int e = threadIdx.x; e < r * sld; e += 256) xp[e] = czero<R>();
+  for (int q0 = 0; q0 < q; q0 += chunk) {
+    const int nq = min(chunk, q - q0);
+    __syncthreads();
+    gather(zq, sld, z, ldz, c0, nq, nc,
+           [&](int i) { return (q0 + i) < k ? gS[q0 + i] : gN[q0 + i - k]; });
+    __syncthreads();
+    blk_mm<R, false>(Y, r, r, q0, q0 + nq, zq, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+      for (int c = 0; c < SNC; ++c)
+        if (c < nc) xp[a * sld + c] = xp[a * sld + c] + v[c];
+    });
+  }
+  __syncthreads();
+  gather(zR, sld, z, ldz, c0, r, nc, [&](int i) { return gR[i]; });
+  __syncthreads();
+  blk_mm<R, false>(Xi, r, r, 0, r, zR, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
+#pragma unroll
+    for (int c = 0; c < SNC; ++c)
+      if (c < nc) xR[a * sld + c] = v[c] - xp[a * sld + c];
+  });
+  __syncthreads();
+  blk_mm<R, false>(T, k, k, 0, r, xR, sld, nc, red,
+                   [&](int a, const cx<R>(&v)[SNC]) { sub_row(z, ldz, gS[a], c0, nc, v); });
+  for (int e = threadIdx.x; e < r * nc; e += 256) {
+    const int a = e % r, c = e / r;
+    z[gR[a] + (int64_t)(c0 + c) * ldz] = xR[a * sld + c];
+  }
+}
+
+// LDS rows (times ncg + 1 entries) of the backward kernels for a level: the
+// chunk of z_{S,N} staged at once, and whether the fused kernel fits
+template <class R>
+static int bwd_chunk(int rmax, int qmax, int S, size_t row) {
+  const int qs = (qmax + S - 1) / S;
+  return (int)std::min<size_t>(std::max(qs, 16), SOLVE_LDS / row - (size_t)rmax - SRED);
+}
+
+template <class R>
+bool solve_fused_fits(int kmax, int rmax, int ncg) {
+  const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
+  return (size_t)(kmax + 2 * rmax + SRED) * row <= SOLVE_LDS &&
+         (size_t)(3 * rmax + SRED) * row <= SOLVE_LDS;
+}
+
 template <class R>
 void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int kmax, int rmax,
                       int qmax, SolveTile tile, cx<R>* W, hipStream_t s) {
@@ -2103,8 +2237,13 @@ void launch_solve_bwd(const SolveProb<R>* sp, const Phase<R>& ph, int nrhs, int 
   const size_t row = (size_t)(ncg + 1) * sizeof(cx<R>);
   const dim3 groups((nrhs + ncg - 1) / ncg);
   // z_{S,N} chunk: one slice's rows if they fit, else what is left of the budget (>= 16 rows)
-  const int qs = (qmax + S - 1) / S;
-  const int chunk = (int)std::min<size_t>(std::max(qs, 16), SOLVE_LDS / row - (size_t)rmax - SRED);
+  const int chunk = bwd_chunk<R>(rmax, qmax, tile.fused ? 1 : S, row);
+  if (tile.fused) {
+    const int u = std::max(chunk, 2 * rmax);  // the chunk, later z_R and x_R
+    hipLaunchKernelGGL(k_solve_bwd_fused<R>, dim3(ph.nbox, groups.x), dim3(256),
+                       (size_t)(rmax + SRED + u) * row, s, sp, ph, rmax, chunk, ncg);
+    return;
+  }
   hipLaunchKernelGGL(k_solve_bwd_a<R>, dim3(ph.nbox * S, groups.x), dim3(256),
                      (size_t)(rmax + SRED + chunk) * row, s, sp, ph, rmax, chunk, ncg, S, W, nrhs);
   hipLaunchKernelGGL(k_solve_bwd_b<R>, dim3(ph.nbox, groups.x), dim3(256),
@@ -2270,6 +2409,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);  \
   template int cpqr_mg_groups<R>(int, int, int);                                                     \
   template int solve_group<R>(int, int, int);                                                        \
+  template bool solve_fused_fits<R>(int, int, int);                                                  \
   template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*,  \
                                   unsigned*, int*, hipStream_t);
 

@@ -295,10 +295,13 @@ def set_graphs(enable: bool) -> bool:
     return bool(load().rss_set_graphs(1 if enable else 0))
 
 
-def set_autotune(enable: bool) -> bool:
-    """rss_set_autotune: time candidate solve tiles on first use of a level
-    shape (default) or keep the default tiles.  Returns the previous setting."""
-    return bool(load().rss_set_autotune(1 if enable else 0))
+def set_autotune(mode) -> int:
+    """rss_set_autotune: 1/True times candidate solve tiles on first use of a
+    level shape (default), 0/False keeps the default tiles, 2 takes the fused
+    tile wherever it fits.  Returns the previous mode."""
+    rc = load().rss_set_autotune(int(mode))
+    _check(min(rc, 0))
+    return rc
 
 
 def kernel_block(kern, points_dev, I_dev, J_dev):

@@ -22,6 +22,7 @@ template <class R> void launch_solve_fwd(const SolveProb<R>*, const Phase<R>&, i
 template <class R> size_t solve_work_elems(int nbox, int rmax, int S, int nrhs) { return (size_t)nbox * S * rmax * nrhs; }
 template <class R> void launch_solve_bwd(const SolveProb<R>*, const Phase<R>&, int, int, int, int, SolveTile, cx<R>*, hipStream_t) {}
 int solve_slices(int nbox, int) { return nbox < 64 ? 4 : 1; }
+template <class R> bool solve_fused_fits(int, int rmax, int) { return rmax < 64; }
 template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t) {}
 #define I(R) \
 template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
@@ -30,6 +31,7 @@ template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStrea
 template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template int cpqr_mg_groups<R>(int, int, int); \
 template int solve_group<R>(int, int, int); \
+template bool solve_fused_fits<R>(int, int, int); \
 template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t); \
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \

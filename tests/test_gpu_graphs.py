@@ -124,3 +124,47 @@ def test_autotuned_tiles_agree_with_default(torch_cuda):
     finally:
         rss.set_autotune(prev_t)
         rss.set_graphs(prev_g)
+
+
+@pytest.mark.parametrize("kappa,n,leaf", [(40.0, 64, 64), (30.0, 48, 36)])
+def test_fused_tiles_agree_with_default(torch_cuda, kappa, n, leaf):
+    """The fused solve tile (each sweep step in one launch per box;
+    rss_set_autotune(2) forces it wherever its LDS fits) does the arithmetic of
+    one slice: an FP64 apply equals the default tiles' to 1e-13, and a refined
+    FP32 solve reaches relres <= 1e-10 by the oracle's exact product, directly
+    and through a captured graph (two replays, equal bit for bit)."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    from oracle import matvec as omv
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, kappa)
+    B0 = W.rhs(n * n, 5, 41)
+    prev_t, prev_g = rss.set_autotune(0), rss.set_graphs(False)
+    try:
+        f = rss.Factorization(P, k, 1e-6, leaf, precision="fp64", max_refine=-1)
+        E = _dev(torch, B0)
+        f.apply(E)
+        ref = E.cpu().numpy()
+        f.close()
+        rss.set_autotune(2)
+        f = rss.Factorization(P, k, 1e-6, leaf, precision="fp64", max_refine=-1)
+        X = _dev(torch, B0)
+        f.apply(X)
+        got = X.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-13
+        f.close()
+        g = rss.Factorization(P, k, 1e-6, leaf, precision="fp32")
+        Y = _dev(torch, B0)
+        assert g.solve(Y) == rss.RSS_OK
+        y = Y.cpu().numpy()
+        assert omv.relres(omv.fft_matvec(k, n, y), B0) <= 1e-10
+        rss.set_graphs(True)
+        for rep in range(2):
+            Z = _dev(torch, B0)
+            assert g.solve(Z) == rss.RSS_OK
+            assert np.array_equal(Z.cpu().numpy(), y), rep
+        g.close()
+        assert rss.set_autotune(0) == 2
+    finally:
+        rss.set_autotune(prev_t)
+        rss.set_graphs(prev_g)

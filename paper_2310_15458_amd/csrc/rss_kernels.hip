@@ -756,7 +756,11 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax) {
   }
   int G = cap / (nbox > 0 ? nbox : 1);
   G = min(G, max(1, mmax / 128));
-  return min(G, RSS_CPQR_MG_GMAX);
+  // measured at N=512^2: 8 per box beats 4 for phases of up to 16 boxes
+  // (15.6 vs 19.3 ms, 13.7 vs 15.6 ms per level), 4 beats 8 for ~28 boxes
+  // (20.8 vs 23.5 ms): past 16 boxes the per-step barriers of more groups cost
+  // more than their parallel work saves
+  return min(G, nbox > 16 ? RSS_CPQR_MG_GMAX / 2 : RSS_CPQR_MG_GMAX);
 }
 
 template <class R>

@@ -233,7 +233,9 @@ int rss_set_stream(rss_handle h, void* stream);
  * sweeps of Sec. 2.6: with it on, an apply of a single handle (rss_apply,
  * rss_solve and each refinement step, a server batch of one) replays a HIP
  * graph of all its launches, captured on the handle's first apply with that
- * nrhs and kept until rss_free; the vectors are reached through descriptor
+ * nrhs and kept until rss_free (at most 4 per handle, the least recently used
+ * dropped; their descriptors and workspace are device memory beyond
+ * rss_stats.device_bytes); the vectors are reached through descriptor
  * tables in device memory that each call rewrites before the replay.  Off:
  * every apply launches its kernels directly (the same kernels, same results).
  * Batches of several handles always launch directly.  enable: 0 or 1; returns

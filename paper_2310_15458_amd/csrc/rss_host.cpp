@@ -425,6 +425,7 @@ struct DepthRecords {
 
 // a captured apply of one handle (see ApplyGraph); destroyed with the handle
 struct ApplyGraphBase {
+  uint64_t last_use = 0;  // for the handle's least-recently-used eviction
   virtual ~ApplyGraphBase() {}
 };
 
@@ -457,9 +458,12 @@ struct rss_ctx {
   rss_stats stats{};
   Prof prof;
   int* d_err = nullptr;
-  // captured applies per (sizeof(R), nrhs); declared last, so destroyed before
-  // the arena that owns the factors they read
+  // captured applies per (sizeof(R), nrhs), at most MAX_GRAPHS (least recently
+  // used dropped); declared last, so destroyed before the arena that owns the
+  // factors they read
+  static constexpr size_t MAX_GRAPHS = 4;
   std::map<std::pair<int, int>, std::unique_ptr<ApplyGraphBase>> graphs;
+  uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -1624,6 +1628,14 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
     const std::pair<int, int> key{(int)sizeof(R), nrhs[0]};
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
+      if (h->graphs.size() >= rss_ctx::MAX_GRAPHS) {
+        // drop the least recently used capture (the stream is idle: every
+        // apply ends with a synchronisation)
+        auto lru = h->graphs.begin();
+        for (auto jt = h->graphs.begin(); jt != h->graphs.end(); ++jt)
+          if (jt->second->last_use < lru->second->last_use) lru = jt;
+        h->graphs.erase(lru);
+      }
       std::unique_ptr<ApplyGraph<R>> g(new ApplyGraph<R>());
       g->plan.build(H, Z, nrhs, g->mem, s);
       maybe_autotune(g->plan, H, nrhs, s);
@@ -1638,6 +1650,7 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
       it = h->graphs.emplace(key, std::move(g)).first;
     }
     ApplyGraph<R>* g = static_cast<ApplyGraph<R>*>(it->second.get());
+    g->last_use = ++h->graph_clock;
     g->plan.set_z(Z, s);
     HIPCHK(hipGraphLaunch(g->exec, s));
     HIPCHK(hipGetLastError());

@@ -6,8 +6,9 @@ Bar: every replay equals the direct launches bit for bit (the same kernels
 in the same order, every reduction in a fixed order), for several replays in
 a row with the program's own eager work and synchronisations between them, on
 fresh buffers each time (so the descriptor rewrite is exercised), for both
-precision forms, for a change of nrhs (a second captured graph) and back, and
-through the refined solve.
+precision forms, for changes of nrhs (more captured graphs than a handle keeps,
+so the least recently used one is dropped and captured again), and through
+the refined solve.
 """
 import numpy as np
 import pytest
@@ -41,7 +42,8 @@ def test_graph_replays_equal_direct_launches(torch_cuda, precision):
     f = rss.Factorization(P, k, 1e-6, 36, precision=precision, max_refine=-1)
     prev = rss.set_graphs(True)
     try:
-        for nrhs, seed in ((3, 11), (5, 12), (3, 13)):
+        # five widths: the handle keeps four captures, so the last 3 is captured again
+        for nrhs, seed in ((3, 11), (5, 12), (1, 14), (2, 15), (4, 16), (3, 13)):
             B0 = W.rhs(n * n, nrhs, seed)
             rss.set_graphs(False)
             E = _dev(torch, B0)

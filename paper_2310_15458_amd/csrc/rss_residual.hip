@@ -15,6 +15,24 @@ namespace rss {
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
+// |p - q| for distinct points: the square root of d = dx^2 + dy^2 from the
+// hardware reciprocal-square-root estimate, one Goldschmidt step and two
+// Newton corrections (the library square root adds range scaling and
+// special-case selects that a d of two distinct workload points never needs)
+__device__ __forceinline__ double dist_pos(double xi, double yi, double xj, double yj) {
+  const double dx = __dsub_rn(xi, xj), dy = __dsub_rn(yi, yj);
+  const double d = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+  const double y = __builtin_amdgcn_rsq(d);
+  double g = d * y, h = 0.5 * y;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double rr = fma(-g, g, d);
+  g = fma(rr, h, g);
+  rr = fma(-g, g, d);
+  return fma(rr, h, g);
+}
+
 // r = b - A x for several problems at once (FP64, entries evaluated on the
 // fly), 16 right-hand sides per launch.  Work item = (problem, block of 256
 // targets in the order tperm, source slice), split over 256 / RES_TPB
@@ -113,7 +131,7 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
           if (sg == ti[g]) {
             a = cx<double>{kp.diag, 0.0};
           } else if (kp.kind == 1) {
-            const double x = __dmul_rn(kp.kappa, dist_rn(tx[g], ty[g], px, py));
+            const double x = __dmul_rn(kp.kappa, dist_pos(tx[g], ty[g], px, py));
             if (x < RSS_BESSEL_XA) {
               double pj, pm;  // (w/4) J0 and -(w/4) Y0 (or -(w/4) G)
               const int s = bessel_poly(x, stab, pj, pm);

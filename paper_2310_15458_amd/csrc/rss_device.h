@@ -87,8 +87,10 @@ __device__ __forceinline__ int bessel_poly(double x, const double* tab, double& 
   constexpr double W = RSS_BESSEL_XA / RSS_BESSEL_NSEG;
   int s = (int)(x * (1.0 / W));
   s = s < RSS_BESSEL_NSEG - 1 ? s : RSS_BESSEL_NSEG - 1;
-  // local variable of interval s (exact when W is a power of two)
-  const double t = (x - (s + 0.5) * W) * (2.0 / W);
+  // local variable of interval s: (x - (s + 1/2) W) 2 / W, formed as one
+  // fused multiply-add 2x/W - (2s + 1) (the same single rounding when W is a
+  // power of two)
+  const double t = fma(2.0 / W, x, -(double)(2 * s + 1));
   const double* c = tab + s * (2 * (RSS_BESSEL_DEG + 1));
   pj = c[2 * RSS_BESSEL_DEG];
   py = c[2 * RSS_BESSEL_DEG + 1];

@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the path is single-device); "
+        print("bench.py: the library runs on one GPU only (the path is single-device); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

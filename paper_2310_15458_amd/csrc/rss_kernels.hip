@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rss_internal.h"
 
@@ -1128,6 +1129,10 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// write sink of the read-modify-write epilogue below: one complex128 slot per
+// thread of a 256-thread workgroup, never read for a result
+__device__ __align__(16) double rss_rmw_sink[2 * 256];
+
 // One 64 x 64 tile of C(i0 + ., j0 + .) = A (M x K, leading dimension lda)
 // times B (K x N, ldb): four waves, each a 32 x 32 quarter on the matrix cores
 // (4 real MFMAs per complex product), K in slices of 16 staged in LDS, the
@@ -1135,9 +1140,13 @@ struct Mfma<float> {
 // steps past K in the last slice.  The waves compute B^T A^T so that
 // consecutive lanes hold consecutive rows of C; emit(i, j, re, im) receives
 // every element inside M x N (complex64 form: the K slices summed in FP64).
-template <class R, class Emit>
+// With sub_at given instead (a functor (i, j) -> cx<R>*), each element is
+// subtracted from *sub_at(i, j): all of a lane's 16 targets are loaded before
+// any is stored, so the read-modify-writes overlap instead of taking one
+// memory round trip each.
+template <class R, class Emit, class SubAt = std::nullptr_t>
 __device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* B, int ldb, int Mr, int Nc, int K,
-                                          int i0, int j0, Emit&& emit) {
+                                          int i0, int j0, Emit&& emit, SubAt sub_at = nullptr) {
   using M = Mfma<R>;
   using acc_t = typename M::acc;
   __shared__ cx<R> As[16][64];
@@ -1218,19 +1227,59 @@ __device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* 
     }
   }
   // block (a, b) holds rows wi + 16 a + (l & 15) of C and columns wj + 16 b + M::row(l, v)
+  if constexpr (std::is_same<SubAt, std::nullptr_t>::value) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int li = wi + 16 * a + (l & 15), lj = wj + 16 * b + M::row(l, v);
-        if (i0 + li < Mr && j0 + lj < Nc) {
+        for (int v = 0; v < 4; ++v) {
+          const int li = wi + 16 * a + (l & 15), lj = wj + 16 * b + M::row(l, v);
+          if (i0 + li < Mr && j0 + lj < Nc) {
+            const double re = sizeof(R) == sizeof(double) ? (double)cr[a][b][v] : fr[a][b][v];
+            const double im = sizeof(R) == sizeof(double) ? (double)ci[a][b][v] : fi[a][b][v];
+            emit(li, lj, re, im);
+          }
+        }
+  } else {
+    (void)emit;
+    // global (not flat) accesses, and no branches: elements outside the
+    // product read and write a sink slot of this lane instead, so the 16
+    // loads go out together and the stores need no wait on one another
+    typedef __attribute__((address_space(1))) R* gptr;  // (real, imaginary) pairs
+    const gptr sink = (gptr)(reinterpret_cast<R*>(rss_rmw_sink) + 2 * threadIdx.x);
+    gptr p[2][2][4];
+    R ore[2][2][4], oim[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int li = wi + 16 * a + (l & 15), lj = wj + 16 * b + M::row(l, v);
+          p[a][b][v] = (i0 + li < Mr && j0 + lj < Nc) ? (gptr) reinterpret_cast<R*>(sub_at(li, lj)) : sink;
+        }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          ore[a][b][v] = p[a][b][v][0];
+          oim[a][b][v] = p[a][b][v][1];
+        }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
           const double re = sizeof(R) == sizeof(double) ? (double)cr[a][b][v] : fr[a][b][v];
           const double im = sizeof(R) == sizeof(double) ? (double)ci[a][b][v] : fi[a][b][v];
-          emit(li, lj, re, im);
+          p[a][b][v][0] = ore[a][b][v] - (R)re;
+          p[a][b][v][1] = oim[a][b][v] - (R)im;
         }
-      }
+  }
 }
 
 template <class R>
@@ -1300,10 +1349,9 @@ __global__ __launch_bounds__(256) void k_schur(const Prob<R>* probs, Phase<R> ph
   __syncthreads();
   const cx<R>* XA = rec.F + rec.oXSNR[b];  // Q x r
   const cx<R>* YB = rec.F + rec.oY[b];     // r x Q
-  gemm_tile<R>(XA, Q, YB, r, Q, Q, r, i0, j0, [&](int li, int lj, double re, double im) {
+  gemm_tile<R>(XA, Q, YB, r, Q, Q, r, i0, j0, [](int, int, double, double) {}, [&](int li, int lj) {
     const int rb = rbk[li], cb = cbk[lj];
-    cx<R>* p = bp[rb][cb] + rloc[li] + (int64_t)cloc[lj] * ldr[rb];
-    *p = *p - cx<R>{(R)re, (R)im};
+    return bp[rb][cb] + rloc[li] + (int64_t)cloc[lj] * ldr[rb];
   });
 }
 

@@ -114,24 +114,35 @@ void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStr
 template <class R>
 __global__ __launch_bounds__(256) void k_build_C(const Prob<R>* probs, Phase<R> ph) {
   __shared__ int mbox[16], moff[17];
+  __shared__ int b25[25], n25[25];
   const int slot = blockIdx.x, b = ph.box[slot];
   const Prob<R>& pr = probs[ph.prob[slot]];
   const Level<R> L = pr.L;
   const KParams kp = pr.kp;
   const double* P = pr.P;
   const int n = L.cur[b];
+  // the boxes of M (distance exactly 2) and their sizes, looked up by 25
+  // threads at once; then listed in (dy, dx) order by one thread
+  if (threadIdx.x < 25) {
+    const int dx = (int)threadIdx.x % 5 - 2, dy = (int)threadIdx.x / 5 - 2;
+    int b2 = -1, cn = 0;
+    if (max(abs(dx), abs(dy)) == 2) {
+      b2 = box_at(L, b, dx, dy);
+      if (b2 >= 0) cn = L.cur[b2];
+    }
+    b25[threadIdx.x] = b2;
+    n25[threadIdx.x] = cn;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     int c = 0, o = 0;
-    for (int dy = -2; dy <= 2; ++dy)
-      for (int dx = -2; dx <= 2; ++dx) {
-        if (max(abs(dx), abs(dy)) != 2) continue;
-        const int b2 = box_at(L, b, dx, dy);
-        if (b2 < 0) continue;
-        mbox[c] = b2;
-        moff[c] = o;
-        o += L.cur[b2];
-        ++c;
-      }
+    for (int t = 0; t < 25; ++t) {
+      if (b25[t] < 0) continue;
+      mbox[c] = b25[t];
+      moff[c] = o;
+      o += n25[t];
+      ++c;
+    }
     for (int i = c; i < 17; ++i) moff[i] = o;
     for (int i = c; i < 16; ++i) mbox[i] = -1;
   }
@@ -809,15 +820,22 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
   const int k = rec.k[b], r = rec.r[b];
   if (r == 0) return;
   const int part = blockIdx.y;
+  // the 8 neighbours' sizes, loaded together (a missing neighbour reads the
+  // box's own entry, then counts 0)
+  int nbb[8], ncur[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) nbb[j] = box_at(L, b, nb_dx(j), nb_dy(j));
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ncur[j] = L.cur[nbb[j] >= 0 ? nbb[j] : b];
   int nN = 0, offj = 0, nbj = -1;
+#pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
-    if (b2 < 0) continue;
+    if (nbb[j] < 0) continue;
     if (j == part - 1) {
       offj = nN;
-      nbj = b2;
+      nbj = nbb[j];
     }
-    nN += L.cur[b2];
+    nN += ncur[j];
   }
   if (part > 0 && nbj < 0) return;
   const int n0b = L.n0[b];
@@ -1319,12 +1337,16 @@ __global__ __launch_bounds__(256) void k_schur(const Prob<R>* probs, Phase<R> ph
   off[0] = 0;
   cnt[0] = k;
   int o = k;
+  int ncur[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) box[j + 1] = box_at(L, b, nb_dx(j), nb_dy(j));
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ncur[j] = L.cur[box[j + 1] >= 0 ? box[j + 1] : b];  // loaded together
+#pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int b2 = box_at(L, b, nb_dx(j), nb_dy(j));
-    box[j + 1] = b2;
     off[j + 1] = o;
-    cnt[j + 1] = b2 >= 0 ? L.cur[b2] : 0;
-    if (b2 >= 0) o += cnt[j + 1];
+    cnt[j + 1] = box[j + 1] >= 0 ? ncur[j] : 0;
+    o += cnt[j + 1];
   }
   const int t = threadIdx.x;
   if (t < 81) {

@@ -238,8 +238,11 @@ int rss_set_stream(rss_handle h, void* stream);
  * rss_stats.device_bytes); the vectors are reached through descriptor
  * tables in device memory that each call rewrites before the replay.  Off:
  * every apply launches its kernels directly (the same kernels, same results).
- * Batches of several handles always launch directly.  enable: 0 or 1; returns
- * the previous setting.
+ * Batches of several handles always launch directly.  The capture runs in
+ * thread-local mode on the handle's stream (library-created streams are
+ * non-blocking); a caller-supplied blocking stream should not meet legacy
+ * default-stream work from other threads during a first apply, or graphs
+ * should be switched off.  enable: 0 or 1; returns the previous setting.
  */
 int rss_set_graphs(int enable);
 

@@ -1158,13 +1158,14 @@ __device__ __align__(16) double rss_rmw_sink[2 * 256];
 // steps past K in the last slice.  The waves compute B^T A^T so that
 // consecutive lanes hold consecutive rows of C; emit(i, j, re, im) receives
 // every element inside M x N (complex64 form: the K slices summed in FP64).
-// With sub_at given instead (a functor (i, j) -> cx<R>*), each element is
-// subtracted from *sub_at(i, j): all of a lane's 16 targets are loaded before
-// any is stored, so the read-modify-writes overlap instead of taking one
-// memory round trip each.
+// With sub_at given instead (a functor (i, j) -> cx<R>*), each element times
+// sub_scale is subtracted from *sub_at(i, j): all of a lane's 16 targets are
+// loaded before any is stored, so the read-modify-writes overlap instead of
+// taking one memory round trip each.
 template <class R, class Emit, class SubAt = std::nullptr_t>
 __device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* B, int ldb, int Mr, int Nc, int K,
-                                          int i0, int j0, Emit&& emit, SubAt sub_at = nullptr) {
+                                          int i0, int j0, Emit&& emit, SubAt sub_at = nullptr,
+                                          double sub_scale = 1.0) {
   using M = Mfma<R>;
   using acc_t = typename M::acc;
   __shared__ cx<R> As[16][64];
@@ -1294,8 +1295,8 @@ __device__ __forceinline__ void gemm_tile(const cx<R>* A, int lda, const cx<R>* 
         for (int v = 0; v < 4; ++v) {
           const double re = sizeof(R) == sizeof(double) ? (double)cr[a][b][v] : fr[a][b][v];
           const double im = sizeof(R) == sizeof(double) ? (double)ci[a][b][v] : fi[a][b][v];
-          p[a][b][v][0] = ore[a][b][v] - (R)re;
-          p[a][b][v][1] = oim[a][b][v] - (R)im;
+          p[a][b][v][0] = ore[a][b][v] - (R)(sub_scale * re);
+          p[a][b][v][1] = oim[a][b][v] - (R)(sub_scale * im);
         }
   }
 }
@@ -1307,11 +1308,16 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
   const int i0 = tm * 64, j0 = tn * 64;
   if (i0 >= d.M || j0 >= d.N) return;
   const double sg = (double)d.sign;
-  gemm_tile<R>(d.A, d.lda, d.B, d.ldb, d.M, d.N, d.K, i0, j0, [&](int li, int lj, double re, double im) {
-    cx<R>* p = d.C + (i0 + li) + (int64_t)(j0 + lj) * d.ldc;
-    const cx<R> val{(R)(sg * re), (R)(sg * im)};
-    *p = d.beta ? (*p + val) : val;
-  });
+  if (d.beta) {
+    // C += sign A B, as C - (-sign) A B through the overlapped read-modify-write
+    gemm_tile<R>(
+        d.A, d.lda, d.B, d.ldb, d.M, d.N, d.K, i0, j0, [](int, int, double, double) {},
+        [&](int li, int lj) { return d.C + (i0 + li) + (int64_t)(j0 + lj) * d.ldc; }, -sg);
+  } else {
+    gemm_tile<R>(d.A, d.lda, d.B, d.ldb, d.M, d.N, d.K, i0, j0, [&](int li, int lj, double re, double im) {
+      d.C[(i0 + li) + (int64_t)(j0 + lj) * d.ldc] = cx<R>{(R)(sg * re), (R)(sg * im)};
+    });
+  }
 }
 
 // Schur update of one box (eq. e:step) as one product:

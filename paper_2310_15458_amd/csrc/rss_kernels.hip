@@ -705,17 +705,17 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
     mg_barrier(bar, (++nbar) * G, err);
     k = j + 1;
   }
-  if (g != 0) return;
+  // every workgroup leaves the last barrier with the same k and perm; the G
+  // workgroups share the columns of T (position c goes to workgroup c mod G)
   const int r = n - k;
-  if (threadIdx.x == 0) {
+  if (g == 0 && threadIdx.x == 0) {
     rec.k[b] = k;
     rec.r[b] = r;
   }
-  // T = R11^{-1} R12 (R in rows 0..k-1, columns in pivot order via perm), one thread per column
+  // T = R11^{-1} R12 (R in rows 0..k-1, columns in pivot order via perm), one
+  // thread per column, in place of R12
   cx<R>* Tout = rec.F + rec.oT[b];
-  cx<R>* Tw = C + (int64_t)perm[0] * m;  // unused column space is not touched: write T in place
-  (void)Tw;
-  for (int c = k + threadIdx.x; c < n; c += NT) {
+  for (int c = k + g + G * (int)threadIdx.x; c < n; c += G * NT) {
     cx<R>* col = C + (int64_t)perm[c] * m;
     for (int i = k - 1; i >= 0; --i) {
       double sr = col[i].x, si = col[i].y;
@@ -736,13 +736,17 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
     int rk = 0;
     for (int a2 = lo; a2 < hi; ++a2) rk += perm[a2] < pa;
     rankv[a] = rk;
-    if (isS) Sloc[rk] = pa;
-    else Rloc[rk] = pa;
+    if (g == 0) {
+      if (isS) Sloc[rk] = pa;
+      else Rloc[rk] = pa;
+    }
   }
   __syncthreads();
-  if (k > 0 && r > 0) {
-    for (int e = threadIdx.x; e < k * r; e += NT) {
-      const int a = e % k, c = e / k;
+  // this workgroup's columns of T, copied out in sorted order
+  const int rg = r > g ? (r - g + G - 1) / G : 0;
+  if (k > 0 && rg > 0) {
+    for (int e = threadIdx.x; e < k * rg; e += NT) {
+      const int a = e % k, c = g + G * (e / k);
       Tout[rankv[a] + (int64_t)k * rankv[k + c]] = C[a + (int64_t)perm[k + c] * m];
     }
   }

@@ -35,7 +35,7 @@ SOLVE_REPS = 20
 # HBM bytes per k_residual launch at this workload: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, each scaled by the counts of a 1 GiB elementwise copy.  Valid for
 # the kernel as measured; None when the kernel changes until measured again.
-RESIDUAL_TRAFFIC_B = 1.064e+10
+RESIDUAL_TRAFFIC_B = 1.074e+10
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TF = 78.6
 FP32_MFMA_PEAK_TF = 157.3

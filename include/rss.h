@@ -33,7 +33,8 @@ extern "C" {
 typedef enum {
   RSS_OK = 0,
   RSS_EINVAL = -1,        /* bad argument: null pointer, n < 1, tol <= 0, leaf < 1,
-                             nrhs < 1, non-finite point, kappa <= 0 for Helmholtz */
+                             nrhs < 1, non-finite or coincident points (two points with
+                             equal x and y), kappa <= 0 for Helmholtz */
   RSS_ENOMEM = -2,        /* device allocation failed or the memory budget is exceeded */
   RSS_EUNSUPPORTED = -3,  /* e.g. a tree deeper than 15 levels or more than 2^31-1 points */
   RSS_ESINGULAR = -4,     /* an exactly zero pivot in a redundant-block or root LU */

@@ -491,6 +491,21 @@ void validate(const double* points, int64_t n, const rss_kernel* k, double tol, 
   if (!std::isfinite(k->weight) || !std::isfinite(k->diag)) fail(RSS_EINVAL, "non-finite weight/diag");
   for (int64_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(points[i])) fail(RSS_EINVAL, "non-finite point coordinate");
+  // coincident points would put K(0) (log 0, H0(0)) into the matrix: sort the
+  // (x, y) pairs and reject any repeat
+  std::vector<int64_t> ord(n);
+  for (int64_t i = 0; i < n; ++i) ord[i] = i;
+  auto less = [points](int64_t a, int64_t b) {
+    if (points[2 * a] != points[2 * b]) return points[2 * a] < points[2 * b];
+    return points[2 * a + 1] < points[2 * b + 1];
+  };
+  std::sort(ord.begin(), ord.end(), less);
+  for (int64_t i = 1; i < n; ++i) {
+    const int64_t a = ord[i - 1], b = ord[i];
+    if (points[2 * a] == points[2 * b] && points[2 * a + 1] == points[2 * b + 1])
+      fail(RSS_EINVAL, "duplicate points " + std::to_string(std::min(a, b)) + " and " +
+                           std::to_string(std::max(a, b)));
+  }
 }
 
 // Box coordinates at depth MAX_DEPTH: floor((p - corner) / side) clamped to the
@@ -1213,7 +1228,16 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       nrmax = std::max(nrmax, nr);
       w.flops_lu += 8.0 * (double)nr * nr * nr;
       w.fbytes += (double)nr * nr * E;
-      if (!have) w.kevals += (double)nr * nr;
+      if (!have) {
+        w.kevals += (double)nr * nr;
+      } else {
+        // fresh kernel blocks of the root: pairs of depth-2 boxes more than 2 apart
+        const std::vector<int>& kk = h->skel_k.back();
+        const int nb = 1 << MIN_DEPTH;
+        for (int a = 0; a < nb * nb; ++a)
+          for (int b = 0; b < nb * nb; ++b)
+            if (kk[a] > 0 && kk[b] > 0 && chebyshev(nb, a, b) > 2) w.kevals += (double)kk[a] * kk[b];
+      }
     }
     if (!pds.empty()) {
       PairDesc* d_pds = scr.up(pds, s);
@@ -1902,10 +1926,13 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
       // each problem until max_j ||r_j|| / ||b_j|| <= its refine_tol
       struct St {
         cx<double>*b, *x, *r;
+        cx<double>* xb = nullptr;  // best iterate so far, when it is not the current x
         double* nrm;
         cx<float>* z;
         std::vector<double> bn, rn;
         double relres = 1.0;
+        double best = HUGE_VAL;    // relres of the best iterate
+        bool best_is_x = false;    // the best iterate is the current x (else xb)
         int it = 0;
         bool done = false;
       };
@@ -1978,15 +2005,29 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
           q.relres = 0.0;
           for (int j = 0; j < nr[p]; ++j) q.relres = std::max(q.relres, q.bn[j] > 0 ? q.rn[j] / q.bn[j] : 0.0);
           if (q.relres <= H[p]->opt.refine_tol || q.it >= H[p]->refine_steps) q.done = true;
-          else q.it++;
+          // a NaN relres never counts as an improvement
+          const bool better = q.relres < q.best;
+          if (better) q.best = q.relres;
+          if (better && !q.done) {
+            // x changes in the next step: keep a copy of this iterate
+            const size_t tot = (size_t)H[p]->N * nr[p];
+            if (!q.xb) q.xb = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
+            HIPCHK(hipMemcpyAsync(q.xb, q.x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+          }
+          q.best_is_x = better;
+          if (!q.done) q.it++;
         }
       }
       for (int p = 0; p < nh; ++p) {
         const size_t tot = (size_t)H[p]->N * nr[p];
-        HIPCHK(hipMemcpyAsync(B[p], st[p].x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        St& q = st[p];
+        // the best iterate: the last one unless refinement stalled or diverged
+        const cx<double>* xo = (q.best_is_x || !q.xb) ? q.x : q.xb;
+        HIPCHK(hipMemcpyAsync(B[p], xo, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        if (!q.best_is_x && q.xb) q.relres = q.best;
         H[p]->stats.last_relres = st[p].relres;
         H[p]->stats.last_iters = st[p].it;
-        if (st[p].relres > H[p]->opt.refine_tol) {
+        if (!(st[p].relres <= H[p]->opt.refine_tol)) {
           g_err = "refinement did not reach refine_tol";
           code = RSS_ENOCONV;
         }

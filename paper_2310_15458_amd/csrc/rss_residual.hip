@@ -1,6 +1,8 @@
-// The FP64 on-the-fly residual R = B - A X of the refinement (Sec. 4): kernel
-// entries (eq. e:aij) are evaluated as they are needed and contracted with X
-// on the matrix cores, so A is never stored.  Built in a translation unit of
+// The FP64 on-the-fly residual R = B - A X of the refinement (the residual
+// whose norm Tab. t:notations reports; refinement stands in for the
+// preconditioned iterations of Sec. 5): kernel entries (eq. e:aij) are
+// evaluated as they are needed and contracted with X on the matrix cores, so
+// A is never stored.  Built in a translation unit of
 // its own so that the matrix-core accumulators can be kept in ordinary vector
 // registers (see build.py): the near/far branches of the entry evaluation
 // inside the source loop otherwise make the compiler copy them between

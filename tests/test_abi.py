@@ -64,3 +64,26 @@ def _struct_fields(name):
                                       ("rss_server_stats", rss.rss_server_stats)])
 def test_struct_mirrors(cname, py):
     assert _struct_fields(cname) == [f for f, _ in py._fields_]
+
+
+def test_coincident_and_nonfinite_points_rejected_before_any_gpu_work():
+    # argument validation runs before the library touches the device, so these
+    # calls return RSS_EINVAL on a machine without a GPU
+    import ctypes
+    import numpy as np
+    lib = rss.load()
+    k = rss.rss_kernel(1, 25.0, 1.0 / 64, 1.0, 2)
+    h = ctypes.c_void_p()
+    P = np.ascontiguousarray(np.random.default_rng(1).random((64, 2)))
+    for bad in ("dup", "nan"):
+        Q = P.copy()
+        if bad == "dup":
+            Q[40] = Q[7]
+        else:
+            Q[3, 1] = np.nan
+        rc = lib.rss_factor(Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), Q.shape[0],
+                            ctypes.byref(k), 1e-6, 16, ctypes.byref(h))
+        assert rc == rss.RSS_EINVAL, (bad, rc)
+        assert h.value is None
+        msg = lib.rss_last_error().decode()
+        assert ("duplicate points 7 and 40" in msg) if bad == "dup" else ("non-finite" in msg)

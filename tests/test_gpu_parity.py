@@ -60,12 +60,42 @@ def test_kernel_entries(torch_cuda, kind, kappa, q):
                                  torch.from_numpy(J).cuda()))
     ref = okern.entries(k, P, I, J)
     scale = np.abs(ref).max()
-    # H0^(1)(x) has condition number ~x in its argument: a rounding of x = kappa r
-    # moves the value by ~x ulp, so the bar grows with x
+    # both sides form the same FP64 argument x = kappa r (correctly rounded
+    # square root); the bar's x-growing term is the phase error of SciPy's
+    # hankel1 at large x, not the device's (test_h0_large_argument pins the
+    # device against 30-digit values at the same x without it)
     x = kappa * np.hypot(P[I, 0][:, None] - P[J, 0][None, :], P[I, 1][:, None] - P[J, 1][None, :])
     bar = (2e-14 + 2.5e-16 * x) * np.abs(ref) + 1e-16 * scale
     ratio = np.max(np.abs(got - ref) / bar)
     assert ratio <= 1.0, ratio
+
+
+def test_h0_large_argument(torch_cuda):
+    """Device H0^(1)(x) against a 30-digit evaluation (mpmath) at the same FP64
+    argument, x from 0.01 to ~280: points (0, 0) and (a, 0), so r = a exactly
+    and x = fl(kappa a) on both sides; relative error of the complex value
+    <= 1e-14 everywhere, including the far range of Hankel's expansion."""
+    import mpmath
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    kappa = 200.0
+    a = np.concatenate([np.geomspace(5e-5, 1.4, 300), np.linspace(0.3, 1.4, 200)])
+    P = np.zeros((a.size + 1, 2))
+    P[1:, 0] = a
+    k = W.Kernel("helmholtz", kappa=kappa, weight=4.0, diag=1.0)   # w/4 = 1: entries are i H0
+    I = np.zeros(1, np.int32)
+    J = np.arange(1, a.size + 1, dtype=np.int32)
+    got = _host(rss.kernel_block(k, torch.from_numpy(P).cuda(), torch.from_numpy(I).cuda(),
+                                 torch.from_numpy(J).cuda()))[0]
+    mpmath.mp.dps = 30
+    worst = 0.0
+    for j, aj in enumerate(a):
+        x = kappa * float(np.sqrt(aj * aj))
+        h = mpmath.hankel1(0, mpmath.mpf(x))
+        ref = complex(1j * complex(h))
+        worst = max(worst, abs(got[j] - ref) / abs(ref))
+    print(f"H0 worst relative error {worst:.2e} up to x = {kappa * a.max():.0f}", flush=True)
+    assert worst <= 1e-14
 
 
 def test_residual_matches_fft(torch_cuda):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librss.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["rss_kernels.hip", "rss_residual.hip", "rss_host.cpp", "rss_server.cpp"]
+SOURCES = ["rss_kernels.hip", "rss_id.hip", "rss_residual.hip", "rss_host.cpp", "rss_server.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
@@ -31,7 +31,9 @@ FLAGS = [
 # per-source additions: the residual's matrix-core accumulators stay in
 # ordinary vector registers (the accumulation registers would be copied to and
 # from on every iteration of its branchy source loop)
-EXTRA_FLAGS = {"rss_residual.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA_FLAGS = {"rss_residual.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               # double-double arithmetic: each operation rounded on its own
+               "rss_id.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:

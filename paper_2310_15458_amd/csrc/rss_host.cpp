@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <exception>
@@ -624,6 +625,19 @@ struct Scratch {
   ~Scratch() { release_all(); }
 };
 
+// Largest box (points) whose ID goes through the Gram matrix; larger boxes
+// take column-pivoted Householder QR.  GRAM_NMAX unless the environment
+// variable RSS_GRAM_NMAX (read once) sets a smaller value (0: Householder QR
+// everywhere; for tests that cover both forms).
+int gram_nmax() {
+  static const int v = [] {
+    const char* e = std::getenv("RSS_GRAM_NMAX");
+    if (!e || !*e) return GRAM_NMAX;
+    return std::max(0, std::min(GRAM_NMAX, std::atoi(e)));
+  }();
+  return v;
+}
+
 // Per-problem state while a batch is being factored.
 struct Work {
   rss_ctx* h = nullptr;
@@ -879,9 +893,16 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     struct Merged {
       std::vector<int> box, prob;
       std::vector<int64_t> oC, oX, oZ, oI, oD;
-      int64_t tot = 0, itot = 0, dtot = 0;
+      std::vector<int64_t> oP, oG, oR;  // Gram ID workspace per slot (doubles)
+      int64_t tot = 0, itot = 0, dtot = 0, gtot = 0;
+      int rows_ub = 0;                   // most rows of Y = [A_MB; K(proxy, B)] of a slot
+      int chunks = 1, chunk_rows = 1;
+      int nmax = 0;                      // largest box of the phase
     } M[9];
-    int64_t Wmax = 0, Imax = 0, Dmax = 0;
+    // the ID through the double-double Gram matrix for boxes of up to
+    // GRAM_NMAX points, else column-pivoted Householder QR on C
+    const bool use_gram = nmax <= gram_nmax();
+    int64_t Wmax = 0, Imax = 0, Dmax = 0, Gmax_ws = 0;
     int maxph = 0;
     for (int c = 0; c < 9; ++c) {
       Merged& G = M[c];
@@ -897,10 +918,12 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
           for (int x : ring(nb, b, 2)) msum += cur.n0[x];
           for (int x : ring(nb, b, 1)) nN0 += cur.n0[x];
           const int m = 2 * msum + 2 * H[p]->opt.n_proxy;
+          G.rows_ub = std::max(G.rows_ub, msum + H[p]->opt.n_proxy);
+          G.nmax = std::max(G.nmax, n);
           G.box.push_back(b);
           G.prob.push_back((int)a);
           cx_.push_back(C);
-          C += (int64_t)m * n;
+          if (!use_gram) C += (int64_t)m * n;
           xx_.push_back(X);
           X += (int64_t)n * n;
           zx_.push_back(Z);
@@ -918,6 +941,30 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       }
       G.tot = C + X + Z;
       G.itot = I;
+      if (use_gram && !G.box.empty()) {
+        // row chunks per box: enough workgroups to fill the chip (~2048), at
+        // least 32 rows of Y per chunk
+        const int nslot = (int)G.box.size();
+        const int tgroups = gram_tile_groups(std::max(1, G.nmax));
+        const int want = std::max(1, (2048 + nslot * tgroups - 1) / (nslot * tgroups));
+        const int most = std::max(1, (G.rows_ub + 31) / 32);
+        const int ch = std::min(want, most);
+        G.chunk_rows = ((G.rows_ub + ch - 1) / ch + 15) / 16 * 16;
+        G.chunks = std::max(1, (G.rows_ub + G.chunk_rows - 1) / G.chunk_rows);
+        int64_t o = 0;
+        for (size_t i = 0; i < G.box.size(); ++i) {
+          const int n = W[act[G.prob[i]]].cur.n0[G.box[i]];
+          const int64_t nn = (int64_t)n * n;
+          G.oG.push_back(o);
+          o += 2 * nn;
+          G.oR.push_back(o);
+          o += nn;
+          G.oP.push_back(o);
+          if (G.chunks > 1) o += (int64_t)G.chunks * 2 * nn;
+        }
+        G.gtot = o;
+        Gmax_ws = std::max(Gmax_ws, o);
+      }
       Wmax = std::max(Wmax, G.tot);
       Imax = std::max(Imax, I);
       Dmax = std::max(Dmax, G.dtot);
@@ -927,6 +974,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     int* Wi = (int*)scr.alloc((size_t)Imax * sizeof(int));
     // FP64 work for the redundant-block inverses too large for LDS
     cx<double>* Wdd = (cx<double>*)scr.alloc((size_t)std::max<int64_t>(1, Dmax) * sizeof(cx<double>));
+    double* Wg = use_gram ? (double*)scr.alloc((size_t)std::max<int64_t>(1, Gmax_ws) * sizeof(double)) : nullptr;
     // multi-workgroup ID for colours with few boxes: G workgroups per box
     int Gc[9], Gmax = 1;
     for (int c = 0; c < 9; ++c) {
@@ -941,6 +989,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     GemmDesc<R>* desc = (GemmDesc<R>*)scr.alloc((size_t)std::max(1, maxph) * sizeof(GemmDesc<R>));
     const int chunks = (mmax + 63) / 64;
     Phase<R> phs[9];
+    GramWs gws[9];
     for (int c = 0; c < 9; ++c) {
       Merged& G = M[c];
       if (G.box.empty()) continue;
@@ -957,16 +1006,32 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       ph.W = (cx<R>*)Wd;
       ph.Wi = Wi;
       ph.Wd = Wdd;
+      if (use_gram) {
+        GramWs& gw = gws[c];
+        gw.part = gw.G = gw.Rw = Wg;
+        pk.add(gw.oP, G.oP);
+        pk.add(gw.oG, G.oG);
+        pk.add(gw.oR, G.oR);
+        gw.chunks = G.chunks;
+        gw.chunk_rows = G.chunk_rows;
+      }
     }
     pk.flush(scr, s);
     for (int c = 0; c < 9; ++c) {
       if (M[c].box.empty()) continue;
       const Phase<R>& ph = phs[c];
-      prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
-      prof.run(RSS_K_ID, s, [&] {
-        if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
-          launch_cpqr<R>(d_probs, ph, nmax, mmax, s);
-      });
+      if (use_gram) {
+        prof.run(RSS_K_ID, s, [&] {
+          launch_gram<R>(d_probs, ph, gws[c], M[c].nmax, s);
+          launch_chol<R>(d_probs, ph, gws[c], M[c].nmax, s);
+        });
+      } else {
+        prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
+        prof.run(RSS_K_ID, s, [&] {
+          if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
+            launch_cpqr<R>(d_probs, ph, nmax, mmax, s);
+        });
+      }
       prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(d_probs, ph, nmax, s); });
       prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(d_probs, ph, d_err, nmax, s); });
       launch_plan_y<R>(d_probs, ph, desc, s);

@@ -29,6 +29,23 @@ struct Level {
   double x0, y0, side;  // geometry of this depth's boxes (side = box side)
 };
 
+constexpr double TIE = 1e-8;  // pivot tie window of the interpolative decomposition
+
+// box at offset (dx, dy) from b, or -1 off the grid
+template <class R>
+__device__ __forceinline__ int box_at(const Level<R>& L, int b, int dx, int dy) {
+  const int bx = b % L.nb + dx, by = b / L.nb + dy;
+  if (bx < 0 || by < 0 || bx >= L.nb || by >= L.nb) return -1;
+  return by * L.nb + bx;
+}
+
+// the stored block A[b, b2] (b2 within distance 2 of b)
+template <class R>
+__device__ __forceinline__ cx<R>* block_ptr(const Level<R>& L, int b, int b2) {
+  const int dx = b2 % L.nb - b % L.nb, dy = b2 / L.nb - b / L.nb;
+  return L.A + L.boff[(int64_t)b * 25 + slot_of(dx, dy)];
+}
+
 // Factor records of the boxes of one depth (offsets are worst-case slots):
 //  T     k x r      (ld k)         interpolation matrix, rows S, cols R ascending
 //  Xi    r x r      (ld r)         X_RR^{-1}
@@ -91,6 +108,23 @@ struct Phase {
   cx<double>* Wd;
 };
 
+// Workspace of the interpolative decomposition through the Gram matrix of one
+// colour phase (FP64 arrays; every box's n is its active count n0[b]).
+//  part : per slot, `chunks` partial Gram matrices, each hi (n x n) then lo
+//  G    : per slot, the summed Gram matrix, hi then lo (aliases part when
+//         chunks == 1)
+//  Rw   : per slot, n x n: the rows of the pivoted Cholesky factor, then T
+struct GramWs {
+  double* part;
+  const int64_t* oP;
+  double* G;
+  const int64_t* oG;
+  double* Rw;
+  const int64_t* oR;
+  int chunks;      // row chunks per slot
+  int chunk_rows;  // rows of Y (complex) per chunk
+};
+
 template <class R>
 struct GemmDesc {
   cx<R>* C;
@@ -149,6 +183,16 @@ int solve_group(int kmax, int rmax, int nrhs);
 template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
                     double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s);
+// Interpolative decomposition through a double-double Gram matrix (boxes of
+// at most GRAM_NMAX points): partial Gram matrices of row chunks, their sum,
+// and the pivoted Cholesky factorization with T = R11^{-1} R12.
+constexpr int GRAM_NMAX = 192;
+// 4 x 4 tiles of the upper triangle of an n x n Gram matrix, in groups of 256
+int gram_tile_groups(int nmax);
+template <class R>
+void launch_gram(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s);
+template <class R>
+void launch_chol(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s);
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s);
 template <class R>

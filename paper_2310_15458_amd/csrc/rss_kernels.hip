@@ -16,8 +16,6 @@
 
 namespace rss {
 
-constexpr double TIE = 1e-8;  // pivot tie window of the column-pivoted QR
-
 // rows per lane loaded per round in the column loops of the column-pivoted QR
 // (one workgroup per box / several workgroups per box)
 #ifndef RSS_CPQR_CH
@@ -61,19 +59,6 @@ __device__ __forceinline__ int nb_dx(int j) {  // j-th of the 8 neighbour offset
 __device__ __forceinline__ int nb_dy(int j) {
   const int t = j < 4 ? j : j + 1;
   return t / 3 - 1;
-}
-
-template <class R>
-__device__ __forceinline__ int box_at(const Level<R>& L, int b, int dx, int dy) {
-  const int bx = b % L.nb + dx, by = b / L.nb + dy;
-  if (bx < 0 || by < 0 || bx >= L.nb || by >= L.nb) return -1;
-  return by * L.nb + bx;
-}
-
-template <class R>
-__device__ __forceinline__ cx<R>* block_ptr(const Level<R>& L, int b, int b2) {
-  const int dx = b2 % L.nb - b % L.nb, dy = b2 / L.nb - b / L.nb;
-  return L.A + L.boff[(int64_t)b * 25 + slot_of(dx, dy)];
 }
 
 // ---------------------------------------------------------------------------

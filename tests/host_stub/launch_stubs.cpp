@@ -10,6 +10,9 @@ template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 
 template <class R> int solve_group(int, int, int nrhs) { return nrhs < 16 ? nrhs : 16; }
 template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t) { return true; }
 template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
+int gram_tile_groups(int nmax) { return nmax > 64 ? 3 : 1; }
+template <class R> void launch_gram(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
+template <class R> void launch_chol(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
 template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
 template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStream_t) {}
@@ -29,6 +32,8 @@ template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
 template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
 template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
+template void launch_gram<R>(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t); \
+template void launch_chol<R>(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t); \
 template int cpqr_mg_groups<R>(int, int, int); \
 template int solve_group<R>(int, int, int); \
 template bool solve_fused_fits<R>(int, int, int); \

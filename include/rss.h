@@ -224,6 +224,24 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
                  const void* B, void* R, int nrhs, void* stream);
 
 /*
+ * rss_residual_static -- rss_residual without any device allocation, for
+ * callers that cannot allocate (code under stream capture, serving loops
+ * with a fixed memory footprint, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results as rss_residual; its target order,
+ * descriptors and source-slice partial sums live in a 64 MiB array that the
+ * library holds on every device it runs on until the process ends.
+ *   n : at most about 16 million points (the target order and one slice must
+ *       fit; larger n returns RSS_EINVAL).  Fewer source slices than
+ *       rss_residual chooses are used when their partial sums do not fit,
+ *       which changes results at the rounding level only.
+ * Calls on one device share that array: calls that overlap in time on the
+ * same device (other threads, other streams) race and must not be made.
+ * Returns after the work has completed on `stream`.
+ */
+int rss_residual_static(const rss_kernel* k, const double* points, int64_t n, const void* X,
+                        const void* B, void* R, int nrhs, void* stream);
+
+/*
  * rss_set_stream -- move a handle's later work to another stream (hipStream_t;
  * NULL is not allowed).  The caller orders it after work already queued.
  */

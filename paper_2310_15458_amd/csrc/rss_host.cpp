@@ -2171,6 +2171,74 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
   });
 }
 
+int rss_residual_static(const rss_kernel* k, const double* points, int64_t n, const void* X,
+                        const void* B, void* R, int nrhs, void* stream) {
+  return run([&] {
+    if (!k || !points || !X || !B || !R) fail(RSS_EINVAL, "null argument");
+    if (n < 1 || nrhs < 1) fail(RSS_EINVAL, "bad sizes");
+    const hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)residual_static_scratch();
+    if (!base) fail(RSS_EHIP, "the static scratch of the current device is not available");
+    const KParams kp = to_kp(*k);
+    // layout of the scratch: target order, descriptor, work items, partial sums
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t tb = (n + 255) / 256;
+    auto need = [&](int S) {
+      size_t o = up256((size_t)n * sizeof(int)) + up256(sizeof(ResDesc)) +
+                 up256((size_t)tb * S * sizeof(ResBlock));
+      if (S > 1) o += up256((size_t)tb * sizeof(ResBlock)) + (size_t)S * 16 * n * sizeof(cx<double>);
+      return o;
+    };
+    if (need(1) > RES_STATIC_BYTES)
+      fail(RSS_EINVAL, "n = " + std::to_string(n) + " does not fit the static scratch of " +
+                           std::to_string(RES_STATIC_BYTES >> 20) + " MiB (about 4 bytes per point)");
+    int S = residual_slices(tb);
+    while (S > 1 && need(S) > RES_STATIC_BYTES) --S;
+    std::vector<double> hp((size_t)n * 2);
+    HIPCHK(hipMemcpyAsync(hp.data(), points, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const std::vector<int> perm = spatial_order(hp.data(), n);
+    size_t o = 0;
+    int* d_perm = (int*)(base + o);
+    o += up256((size_t)n * sizeof(int));
+    ResDesc* d_desc = (ResDesc*)(base + o);
+    o += up256(sizeof(ResDesc));
+    ResBlock* d_blk = (ResBlock*)(base + o);
+    o += up256((size_t)tb * S * sizeof(ResBlock));
+    ResBlock* d_sum = nullptr;
+    cx<double>* d_part = nullptr;
+    if (S > 1) {
+      d_sum = (ResBlock*)(base + o);
+      o += up256((size_t)tb * sizeof(ResBlock));
+      d_part = (cx<double>*)(base + o);
+    }
+    ResDesc e;
+    e.kp = kp;
+    e.P = points;
+    e.n = n;
+    e.X = (const cx<double>*)X;
+    e.B = (const cx<double>*)B;
+    e.R = (cx<double>*)R;
+    e.part = d_part;
+    e.tperm = d_perm;
+    e.nrhs = nrhs;
+    e.S = S;
+    std::vector<ResBlock> blk, sum;
+    for (int64_t t = 0; t < tb; ++t) {
+      for (int sp = 0; sp < S; ++sp) blk.push_back({0, (int)t, sp});
+      if (S > 1) sum.push_back({0, (int)t, 0});
+    }
+    HIPCHK(hipMemcpyAsync(d_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_desc, &e, sizeof(ResDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_blk, blk.data(), blk.size() * sizeof(ResBlock), hipMemcpyHostToDevice, st));
+    if (S > 1)
+      HIPCHK(hipMemcpyAsync(d_sum, sum.data(), sum.size() * sizeof(ResBlock), hipMemcpyHostToDevice, st));
+    launch_residual(d_desc, d_blk, (int)blk.size(), d_sum, (int)sum.size(), nrhs, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));  // the host tables above must outlive the copies
+  });
+}
+
 int rss_set_stream(rss_handle h, void* stream) {
   if (!h || !stream) {
     g_err = "null argument";

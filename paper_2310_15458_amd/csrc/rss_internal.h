@@ -275,6 +275,11 @@ struct ResBlock {
 };
 // source slices for a launch with this many 256-target blocks in total
 int residual_slices(int64_t target_blocks);
+// the allocation-free residual's scratch: device address of the current
+// device's copy (nullptr if it cannot be obtained), RES_STATIC_BYTES long
+constexpr size_t RES_STATIC_BYTES = (size_t)64 << 20;
+constexpr int RES_STATIC_MAXDEV = 64;
+void* residual_static_scratch();
 // blk: every (problem, target block, slice); sum_blk: slice 0 of the target
 // blocks of problems with S > 1
 void launch_residual(const ResDesc* d, const ResBlock* blk, int nblk, const ResBlock* sum_blk,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "rss_internal.h"
 
@@ -189,6 +190,26 @@ __global__ __launch_bounds__(256) void k_residual_sum(const ResDesc* dd, const R
     for (int sp = 0; sp < D.S; ++sp) v = v - D.part[((int64_t)sp * 16 + c) * n + i];
     D.R[i + (int64_t)(c0 + c) * n] = v;
   }
+}
+
+// Scratch of the allocation-free residual (rss_residual_static): its tables,
+// target order and partial sums, in one array of every device the library
+// runs on (held until the process ends).  Host code reaches it only through
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[RES_STATIC_BYTES];
+
+void* residual_static_scratch() {
+  static std::mutex mu;
+  static void* ptr[RES_STATIC_MAXDEV] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= RES_STATIC_MAXDEV) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    ptr[dev] = p;
+  }
+  return ptr[dev];
 }
 
 int residual_slices(int64_t target_blocks) {

@@ -50,6 +50,7 @@ class rss_stats(ctypes.Structure):
 
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
            "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
+           "rss_residual_static",
            "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
@@ -113,6 +114,8 @@ def load():
                                      ctypes.c_void_p]
     lib.rss_residual.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.rss_residual_static.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.rss_factor_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_int64), P(rss_kernel),
                                      ctypes.c_double, ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
     lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
@@ -327,6 +330,20 @@ def residual(kern, points_dev, X, B):
     _check(load().rss_residual(ctypes.byref(k), ctypes.c_void_p(points_dev.data_ptr()), n,
                                ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                                ctypes.c_void_p(R.data_ptr()), nrhs, _stream_ptr(None)))
+    return R
+
+
+def residual_static(kern, points_dev, X, B):
+    """rss_residual_static: R = B - A X like residual(), with no device
+    allocation inside the library (its scratch is a static device array)."""
+    import torch
+    n = points_dev.shape[0]
+    nrhs = 1 if X.dim() == 1 else X.shape[1]
+    R = torch.empty((nrhs, n), dtype=torch.complex128, device=X.device).t()
+    k = make_kernel(kern)
+    _check(load().rss_residual_static(ctypes.byref(k), ctypes.c_void_p(points_dev.data_ptr()), n,
+                                      ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                      ctypes.c_void_p(R.data_ptr()), nrhs, _stream_ptr(None)))
     return R
 
 

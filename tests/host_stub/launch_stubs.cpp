@@ -51,6 +51,7 @@ template void launch_solve_bwd<R>(const SolveProb<R>*, const Phase<R>&, int, int
 template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t);
 I(double) I(float)
 void launch_kernel_block(const KParams&, const double*, const int*, int64_t, const int*, int64_t, cx<double>*, hipStream_t) {}
+void* residual_static_scratch() { return nullptr; }
 int residual_slices(int64_t target_blocks) { return target_blocks >= 1024 ? 1 : 4; }
 void launch_residual(const ResDesc*, const ResBlock*, int, const ResBlock*, int, int, hipStream_t) {}
 void launch_colnorms(const cx<double>*, int64_t, int nrhs, double* out, hipStream_t) { for (int i = 0; i < nrhs; ++i) out[i] = 1.0; }

@@ -77,8 +77,8 @@ def factor_literal(P, kern, tol, leaf, n_proxy=0, proxy_radius=1.25, min_depth=2
             Nidx = np.concatenate([active[x] for x in Nb]) if Nb else np.zeros(0, np.int64)
             G = tree.proxy_points(d, b, npx, proxy_radius)
             C = np.vstack([A[np.ix_(Midx, I)], A[np.ix_(I, Midx)].conj().T,
-                           kern.weight * kernels.kernel_values(kern, G, P[I]),
-                           (kern.weight * kernels.kernel_values(kern, P[I], G)).conj().T])
+                           kernels.proxy_entries(kern, G, P, I),
+                           kernels.proxy_entries_t(kern, G, P, I)])
             Sl, Rl, T = cpqr.interpolative_decomposition(C, tol, I)
             nu0 = np.sqrt(np.sum(np.abs(C) ** 2, axis=0)).max()
             skel[(d, b)] = I[Sl].copy()

@@ -13,12 +13,24 @@ Kernels:
   algebra reduces to a dense LU solve.
 
 The kernel description is any object with attributes ``kind``, ``kappa``,
-``weight``, ``diag`` and ``q``.
+``weight``, ``diag`` and ``q``, and optionally the paper's discretizations
+(Sec. 5): ``cell_diag`` with the cell side ``h`` puts the cell integral of K
+on the diagonal (eqs. e:a1i, e:b2), and ``bump_a`` > 0 the scattering
+potential b(x) = exp(-bump_a |x - bump_c|^2) (Sec. 5.2):
+
+    A_ij = w s_i s_j K(x_i, x_j)  (i != j),   s_i = sqrt(b(x_i)) (1 without a bump),
+    A_ii = d + (w / h^2) s_i^2 c(h)  with c(h) the cell integral (0 without cell_diag).
+
+First-kind Laplace (eqs. e:a1, e:a1i): w = h^2, d = 0, cell_diag.
+Lippmann-Schwinger Helmholtz (eqs. e:b1, e:b2): w = h^2 kappa^2, d = 1,
+cell_diag and the bump.  Both stay symmetric (A_ij = A_ji).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.special
+
+from . import cells
 
 
 def kernel_values(kern, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
@@ -41,10 +53,37 @@ def kernel_values(kern, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     raise ValueError(f"unknown kernel kind {kern.kind!r}")
 
 
+def point_scale(kern, X: np.ndarray) -> np.ndarray:
+    """s(x) = sqrt(b(x)) of the scattering potential, or ones without one."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 2)
+    a = float(getattr(kern, "bump_a", 0.0))
+    if a <= 0.0:
+        return np.ones(X.shape[0])
+    c = getattr(kern, "bump_c", (0.5, 0.5))
+    r2 = (X[:, 0] - c[0]) ** 2 + (X[:, 1] - c[1]) ** 2
+    return np.exp(-0.5 * a * r2)
+
+
+_CELL = {}
+
+
+def diagonal(kern, X: np.ndarray) -> np.ndarray:
+    """A_ii for the points X (rows): d, plus (w / h^2) s_i^2 c(h) with the cell
+    integral when ``cell_diag`` is set."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 2)
+    out = np.full(X.shape[0], complex(kern.diag))
+    if getattr(kern, "cell_diag", False):
+        key = (kern.kind, float(kern.kappa), float(kern.h))
+        if key not in _CELL:
+            _CELL[key] = cells.cell_integral(kern)
+        out = out + (kern.weight / kern.h ** 2) * point_scale(kern, X) ** 2 * _CELL[key]
+    return out
+
+
 def entries(kern, P: np.ndarray, I: np.ndarray, J: np.ndarray) -> np.ndarray:
     """The block A[I, J] of the system matrix for global index arrays I, J into
-    the point array P: w K(x_i, x_j) where i != j and d where i == j
-    (eq. e:aij with a constant diagonal)."""
+    the point array P: w s_i s_j K(x_i, x_j) where i != j and the diagonal
+    rule where i == j (eq. e:aij)."""
     I = np.asarray(I, dtype=np.int64)
     J = np.asarray(J, dtype=np.int64)
     if I.size == 0 or J.size == 0:
@@ -52,14 +91,29 @@ def entries(kern, P: np.ndarray, I: np.ndarray, J: np.ndarray) -> np.ndarray:
     same = I[:, None] == J[None, :]
     with np.errstate(divide="ignore", invalid="ignore"):
         A = kern.weight * kernel_values(kern, P[I], P[J])
-    A[same] = kern.diag
+    if getattr(kern, "bump_a", 0.0) > 0.0:
+        A = A * point_scale(kern, P[I])[:, None] * point_scale(kern, P[J])[None, :]
+    if same.any():
+        dg = diagonal(kern, P[I])
+        ii, jj = np.nonzero(same)
+        A[ii, jj] = dg[ii]
     return A
 
 
 def proxy_entries(kern, G: np.ndarray, P: np.ndarray, I: np.ndarray) -> np.ndarray:
-    """w K(y_p, x_i) for proxy points y_p (rows) against box points x_i
-    (Sec. 2.3, the matrix K_proxy,B of eq. e:proxy); never the diagonal rule."""
-    return kern.weight * kernel_values(kern, G, P[np.asarray(I, dtype=np.int64)])
+    """w K(y_p, x_i) s_i for proxy points y_p (rows) against box points x_i
+    (Sec. 2.3, the matrix K_proxy,B of eq. e:proxy); never the diagonal rule.
+    The column scale s_i of the box points is that of A's columns; a row scale
+    of the far field does not change the column ID."""
+    I = np.asarray(I, dtype=np.int64)
+    return kern.weight * kernel_values(kern, G, P[I]) * point_scale(kern, P[I])[None, :]
+
+
+def proxy_entries_t(kern, G: np.ndarray, P: np.ndarray, I: np.ndarray) -> np.ndarray:
+    """(w s_i K(x_i, y_p))^* : the transposed proxy block of eq. e:con's second
+    half, rows p, columns i."""
+    I = np.asarray(I, dtype=np.int64)
+    return (kern.weight * point_scale(kern, P[I])[:, None] * kernel_values(kern, P[I], G)).conj().T
 
 
 def dense_matrix(kern, P: np.ndarray) -> np.ndarray:

@@ -36,7 +36,8 @@ def direct_matvec(kern, P, X, block: int = 2048):
 
 
 def grid_generator(kern, n: int) -> np.ndarray:
-    """g on the (2n-1) x (2n-1) offset lattice, indexed [dy + n - 1, dx + n - 1]."""
+    """g on the (2n-1) x (2n-1) offset lattice, indexed [dy + n - 1, dx + n - 1]:
+    w K(h |(dx, dy)|), and 0 at the origin (the diagonal is added apart)."""
     h = 1.0 / n
     d = np.arange(-(n - 1), n)
     DX, DY = np.meshgrid(d, d, indexing="xy")
@@ -44,17 +45,21 @@ def grid_generator(kern, n: int) -> np.ndarray:
     with np.errstate(divide="ignore", invalid="ignore"):
         g = kern.weight * kernels.kernel_values(kern, pts, np.zeros((1, 2)))[:, 0]
     g = g.reshape(2 * n - 1, 2 * n - 1)
-    g[n - 1, n - 1] = kern.diag
+    g[n - 1, n - 1] = 0.0
     return g
 
 
 def fft_matvec(kern, n: int, X):
     """A x for the n x n cell-centre grid with user index iy*n + ix, via a
-    2n x 2n circulant embedding."""
+    2n x 2n circulant embedding: A x = s * (G (s * x)) + diag(A) * x with G
+    the Toeplitz part (zero diagonal) and s the point scale."""
     X = np.asarray(X, dtype=np.complex128)
     sq = X.ndim == 1
     if sq:
         X = X[:, None]
+    P = _grid_points(n)
+    s = kernels.point_scale(kern, P)
+    dg = kernels.diagonal(kern, P)
     g = grid_generator(kern, n)
     m = 2 * n
     c = np.zeros((m, m), dtype=np.complex128)
@@ -65,10 +70,18 @@ def fft_matvec(kern, n: int, X):
     out = np.empty_like(X)
     for j in range(X.shape[1]):
         xp = np.zeros((m, m), dtype=np.complex128)
-        xp[:n, :n] = X[:, j].reshape(n, n)
+        xp[:n, :n] = (s * X[:, j]).reshape(n, n)
         y = np.fft.ifft2(cf * np.fft.fft2(xp))
-        out[:, j] = y[:n, :n].ravel()
+        out[:, j] = s * y[:n, :n].ravel() + dg * X[:, j]
     return out[:, 0] if sq else out
+
+
+def _grid_points(n: int) -> np.ndarray:
+    """cell centres ((ix + 1/2) h, (iy + 1/2) h) in user order iy * n + ix"""
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
 
 
 def relres(Ax, B) -> float:

@@ -146,7 +146,7 @@ def _compression_matrix(st: _State, kern, P, b, npx, c_r, counter):
     G = tree.proxy_points(d, b, npx, c_r)
     rows.append(kernels.proxy_entries(kern, G, P, I))
     # K(B, proxy)^*: entry (p, i) = conj(w K(x_i, y_p))
-    rows.append((kern.weight * kernels.kernel_values(kern, P[I], G)).conj().T)
+    rows.append(kernels.proxy_entries_t(kern, G, P, I))
     counter[0] += 2 * npx * I.size
     return np.vstack(rows) if rows else np.zeros((0, I.size), complex)
 

@@ -37,6 +37,14 @@ class Kernel:
     weight: float = 1.0
     diag: float = 1.0
     q: int = 2
+    # the paper's discretizations (Sec. 5): the cell integral of K over an
+    # h x h cell on the diagonal, scaled by (weight / h^2) s_i^2, and the
+    # scattering potential b(x) = exp(-bump_a |x - bump_c|^2) scaling entry
+    # (i, j) by s_i s_j = sqrt(b(x_i) b(x_j)) (bump_a = 0: none)
+    cell_diag: bool = False
+    h: float = 0.0
+    bump_a: float = 0.0
+    bump_c: tuple = (0.5, 0.5)
 
 
 def grid_points(n: int) -> np.ndarray:
@@ -52,6 +60,30 @@ def grid_points(n: int) -> np.ndarray:
 def grid_kernel(kind: str, n: int, kappa: float = 0.0, diag: float = 1.0) -> Kernel:
     """Kernel with weight w = h^2 = 1/n^2 and constant diagonal."""
     return Kernel(kind=kind, kappa=float(kappa), weight=1.0 / (n * n), diag=float(diag))
+
+
+def paper_laplace(n: int) -> Kernel:
+    """First-kind Laplace (eqs. e:a1, e:a1i): w = h^2, diagonal = the cell
+    integral of -log(r) / (2 pi)."""
+    h = 1.0 / n
+    return Kernel(kind=LAPLACE, weight=h * h, diag=0.0, cell_diag=True, h=h)
+
+
+def paper_helmholtz(n: int, kappa: float) -> Kernel:
+    """Lippmann-Schwinger Helmholtz (eqs. e:b1, e:b2), symmetrized: w = h^2
+    kappa^2, entries scaled by sqrt(b_i b_j), diagonal 1 + kappa^2 b_i times
+    the cell integral of (i/4) H0(kappa r), Gaussian bump b(x) =
+    exp(-32 |x - (1/2, 1/2)|^2) (Sec. 5.2)."""
+    h = 1.0 / n
+    return Kernel(kind=HELMHOLTZ, kappa=float(kappa), weight=h * h * kappa * kappa, diag=1.0,
+                  cell_diag=True, h=h, bump_a=32.0, bump_c=(0.5, 0.5))
+
+
+def uniform_rhs(N: int, nrhs: int, seed: int) -> np.ndarray:
+    """Standard uniform right-hand sides (Tab. t:notations: "b is a standard
+    uniform random vector"), complex128 with zero imaginary part, Fortran order."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.random((N, nrhs)).astype(np.complex128))
 
 
 def rhs(N: int, nrhs: int, seed: int, complex_parts: bool = True) -> np.ndarray:

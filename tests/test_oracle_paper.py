@@ -1,0 +1,151 @@
+"""Pins for the paper's own matrices and the preconditioned Krylov iterations
+(Sec. 5: first-kind Laplace, eqs. e:a1 / e:a1i; symmetrized Lippmann-Schwinger
+Helmholtz with a Gaussian bump, eqs. e:b1 / e:b2; PCG / GMRES with the
+factorization as preconditioner, Tabs. t:notations, t:laplace2).
+
+* The self-cell integrals (closed form / one-dimensional reduction) equal a
+  direct two-dimensional quadrature of the kernel over the cell.
+* The discrete operator converges to the continuous integral operator: at the
+  domain centre, (A 1)_c approaches 1 + kappa^2 sqrt(b_c) int K sqrt(b) dy (LS)
+  or int K dy (Laplace), computed by adaptive quadrature, at second order in h.
+  A wrong weight, point scale or diagonal breaks the convergence.
+* The matrices are symmetric and the FFT product equals the dense product.
+* PCG (Laplace) and GMRES (LS Helmholtz) preconditioned by the RS-S factorization
+  reach relres 1e-12 in a handful of iterations and the dense solution.
+* Tab. t:laplace2's trend: the factorization's relres follows the tolerance
+  (relres / eps between 0.1 and 1000) and fewer iterations are needed as eps
+  decreases.
+"""
+import math
+import types
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+import scipy.special
+
+from oracle import cells, kernels, krylov, matvec, rss
+from paper_2310_15458_amd import workloads as W
+
+
+@pytest.mark.parametrize("h", [1 / 8, 1 / 64, 1 / 512])
+def test_cell_integrals_match_2d_quadrature(h):
+    lap = cells.laplace_cell(h)
+    ref = cells.cell_integral_2d(types.SimpleNamespace(kind="laplace"), h)
+    assert abs(lap - ref) <= 1e-13 * abs(ref)
+    for kappa in (25.0, 50.0, 200.0):
+        hm = cells.helmholtz_cell(h, kappa)
+        ref = cells.cell_integral_2d(types.SimpleNamespace(kind="helmholtz", kappa=kappa), h)
+        assert abs(hm - ref) <= 1e-12 * abs(ref), (kappa, hm, ref)
+
+
+def _continuous_centre(kern_kind, kappa, bump):
+    """the integral operator applied to mu = 1 at the centre (1/2, 1/2)"""
+    c = (0.5, 0.5)
+
+    def K(r):
+        if kern_kind == "laplace":
+            return complex(-math.log(r) / (2 * math.pi))
+        return complex(0.25j * scipy.special.hankel1(0, kappa * r))
+
+    def sb(x, y):
+        return math.exp(-16.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2)) if bump else 1.0
+
+    out = 0j
+    # polar coordinates around the centre, four quadrants of the square
+    for part in (0, 1):
+        def f(r, t):
+            x, y = c[0] + r * math.cos(t), c[1] + r * math.sin(t)
+            v = K(r) * sb(x, y) * r
+            return v.real if part == 0 else v.imag
+
+        def rmax(t):
+            ct, st = abs(math.cos(t)), abs(math.sin(t))
+            return 0.5 / max(ct, st)
+        val = 0.0
+        for q in range(8):
+            val += scipy.integrate.dblquad(f, q * math.pi / 4, (q + 1) * math.pi / 4, 0.0, rmax,
+                                           epsabs=1e-15, epsrel=1e-12)[0]
+        out += val if part == 0 else 1j * val
+    if kern_kind == "laplace":
+        return out
+    return 1.0 + kappa ** 2 * sb(*c) * out
+
+
+@pytest.mark.parametrize("kind", ["laplace", "helmholtz"])
+def test_discretization_converges_to_the_integral_operator(kind):
+    kappa = 10.0
+    ref = _continuous_centre(kind, kappa, bump=(kind == "helmholtz"))
+    errs = []
+    for n in (16, 32, 64):
+        P = W.grid_points(n)
+        k = W.paper_laplace(n) if kind == "laplace" else W.paper_helmholtz(n, kappa)
+        # the four points nearest the centre, symmetric around it
+        i = [(n // 2 - 1) * n + n // 2 - 1, (n // 2 - 1) * n + n // 2, (n // 2) * n + n // 2 - 1,
+             (n // 2) * n + n // 2]
+        ones = np.ones(n * n, complex)
+        # the mean over 4 points symmetric about the centre: first-order offsets cancel
+        y = matvec.fft_matvec(k, n, ones)[i].mean()
+        errs.append(abs(y - ref))
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3, errs
+
+
+@pytest.mark.parametrize("which", ["laplace", "helmholtz"])
+def test_paper_matrices_symmetric_fft_and_diagonal(which):
+    n = 24
+    P = W.grid_points(n)
+    k = W.paper_laplace(n) if which == "laplace" else W.paper_helmholtz(n, 25.0)
+    A = kernels.dense_matrix(k, P)
+    # symmetric to rounding (the two scale factors multiply in either order)
+    assert np.all(np.abs(A - A.T) <= 4e-16 * np.abs(A))
+    X = W.rhs(n * n, 3, 1)
+    ref = A @ X
+    assert np.abs(matvec.fft_matvec(k, n, X) - ref).max() <= 1e-13 * np.abs(ref).max()
+    h = 1.0 / n
+    c = cells.cell_integral(k)
+    if which == "laplace":
+        assert np.allclose(np.diag(A), c, rtol=1e-15, atol=0)
+        assert np.isclose(A[0, 1], -(h * h) / (2 * math.pi) * math.log(h), rtol=1e-14)
+    else:
+        b = np.exp(-32.0 * ((P[:, 0] - 0.5) ** 2 + (P[:, 1] - 0.5) ** 2))
+        assert np.allclose(np.diag(A), 1.0 + 25.0 ** 2 * b * c, rtol=1e-14, atol=0)
+        ref01 = h * h * 625.0 * math.sqrt(b[0] * b[1]) * 0.25j * scipy.special.hankel1(0, 25.0 * h)
+        assert np.isclose(A[0, 1], ref01, rtol=1e-14)
+
+
+@pytest.mark.parametrize("which", ["laplace", "helmholtz"])
+def test_krylov_preconditioned_by_the_factorization(which):
+    n, leaf = 32, 16
+    P = W.grid_points(n)
+    k = W.paper_laplace(n) if which == "laplace" else W.paper_helmholtz(n, 25.0)
+    F = rss.factor(P, k, 1e-6, leaf)
+    b = W.uniform_rhs(n * n, 1, 0)[:, 0]
+    mv = lambda v: matvec.fft_matvec(k, n, v)  # noqa: E731
+    solver = krylov.pcg if which == "laplace" else krylov.gmres
+    x, it, hist = solver(mv, lambda v: rss.solve(F, v), b, tol=1e-12, maxit=50)
+    assert hist[-1] <= 1e-12 and it <= 6, (it, hist)
+    assert matvec.relres(mv(x), b) <= 1e-11
+    xd = scipy.linalg.solve(kernels.dense_matrix(k, P), b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-9
+    # without the preconditioner far more iterations are needed
+    _, it0, _ = solver(mv, lambda v: v, b, tol=1e-12, maxit=4 * it)
+    assert it0 > 2 * it
+
+
+def test_relres_follows_tolerance_like_the_paper():
+    # Tab. t:laplace2 (first-kind Laplace, PCG to 1e-12): relres / eps ~ 1e2
+    # at eps 1e-6 .. 1e-12 and n_it 4-6 -> 2; at this size the ratio is smaller
+    n, leaf = 64, 64
+    P = W.grid_points(n)
+    k = W.paper_laplace(n)
+    b = W.uniform_rhs(n * n, 1, 0)[:, 0]
+    mv = lambda v: matvec.fft_matvec(k, n, v)  # noqa: E731
+    rr, its = {}, {}
+    for eps in (1e-6, 1e-9):
+        F = rss.factor(P, k, eps, leaf)
+        rr[eps] = matvec.relres(mv(rss.solve(F, b)), b)
+        _, its[eps], _ = krylov.pcg(mv, lambda v: rss.solve(F, v), b, tol=1e-12, maxit=50)
+        assert 0.1 * eps <= rr[eps] <= 1000 * eps, (eps, rr[eps])
+    assert rr[1e-9] < 1e-2 * rr[1e-6]
+    assert its[1e-9] <= its[1e-6] <= 6

@@ -52,9 +52,21 @@ typedef enum {
 typedef struct {
   rss_kernel_kind kind;
   double kappa;           /* Helmholtz wavenumber (> 0) */
-  double weight;          /* w: off-diagonal entries are w K(x_i, x_j) (quadrature weight h^2) */
-  double diag;            /* d: diagonal entries A_ii */
+  double weight;          /* w: off-diagonal entries are w s_i s_j K(x_i, x_j) (quadrature weight h^2) */
+  double diag;            /* d: diagonal entries A_ii = d (+ the cell term below) */
   int q;                  /* degree of the degenerate kernel */
+  /* The paper's discretizations (Sec. 5); all zero: s = 1, A_ii = d.
+   *   cell_diag != 0: A_ii = d + (w / h^2) s_i^2 c(h) with c(h) the integral of K
+   *     over an h x h cell centred at the point (eqs. e:a1i, e:b2), computed by the
+   *     library (Laplace and Helmholtz kernels; h > 0 required).
+   *   bump_a > 0: scattering potential b(x) = exp(-bump_a |x - bump_c|^2) and point
+   *     scale s_i = sqrt(b(x_i)) (the symmetrized Lippmann-Schwinger form, eq. e:b1).
+   * First-kind Laplace (eqs. e:a1, e:a1i): w = h^2, d = 0, cell_diag.  LS Helmholtz
+   * (eqs. e:b1, e:b2): w = h^2 kappa^2, d = 1, cell_diag, bump_a = 32, bump_c = (1/2, 1/2). */
+  int cell_diag;
+  double h;
+  double bump_a;
+  double bump_c[2];
 } rss_kernel;
 
 typedef enum {
@@ -240,6 +252,60 @@ int rss_residual(const rss_kernel* k, const double* points, int64_t n, const voi
  */
 int rss_residual_static(const rss_kernel* k, const double* points, int64_t n, const void* X,
                         const void* B, void* R, int nrhs, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Products with A on a uniform grid, and factorization-preconditioned CG /  */
+/* GMRES (Sec. 5, Tab. t:notations n_it).                                    */
+/* ------------------------------------------------------------------------- */
+typedef struct rss_gridop* rss_gridop_t;
+
+/*
+ * rss_gridop_create -- the product with A for the n x n grid of cell centres
+ * x = (x0 + (ix + 1/2) h, y0 + (iy + 1/2) h), point index iy n + ix (Sec. 5:
+ * A is block-Toeplitz with Toeplitz blocks there, applied by FFT of a
+ * circulant embedding of side the power of two >= 2n - 1).
+ *   k      : kernel and entry rule as in rss_factor (Laplace or Helmholtz).
+ *   n      : 1 .. 2048.   stream : hipStream_t of the operator's own calls
+ *            (NULL: one the operator creates).
+ * Holds ~(2n)^2 complex128 of device memory plus a work array that grows to
+ * nrhs n (2n) entries.  Not for concurrent use from several threads.
+ */
+int rss_gridop_create(const rss_kernel* k, int n, double x0, double y0, double h, void* stream,
+                      rss_gridop_t* out);
+/* rss_gridop_apply -- Y = A X; X, Y: device complex128, n^2 x nrhs column-major. */
+int rss_gridop_apply(rss_gridop_t op, const void* X, void* Y, int nrhs);
+/* rss_gridop_residual -- R = B - A X (R may alias B). */
+int rss_gridop_residual(rss_gridop_t op, const void* X, const void* B, void* R, int nrhs);
+/* rss_gridop_free -- release the operator (NULL is a no-op). */
+void rss_gridop_free(rss_gridop_t op);
+
+/*
+ * rss_set_residual_op -- refined solves of this handle (rss_solve,
+ * rss_solve_batch) take their residual r = b - A x from the grid operator
+ * (FFT, FP64) instead of the on-the-fly O(n^2) sum.  op must describe the same
+ * matrix (points in the operator's order, the same kernel) and outlive its use;
+ * NULL restores the on-the-fly residual.  RSS_EINVAL if the sizes differ.
+ */
+int rss_set_residual_op(rss_handle h, rss_gridop_t op);
+
+typedef struct {
+  int iters;              /* iterations taken (the largest over the columns) */
+  double relres;          /* max over columns of ||A x - b|| / ||b||, A by the grid operator */
+  double t_ms;            /* wall time on the handle's stream */
+} rss_krylov_stats;
+
+/*
+ * rss_krylov -- solve A x = b by a Krylov method preconditioned by the
+ * factorization, as Sec. 5 does: method 0 conjugate gradients (for Hermitian
+ * positive definite A, e.g. first-kind Laplace), method 1 GMRES without
+ * restart (right preconditioning; e.g. Lippmann-Schwinger Helmholtz).
+ * Products with A by the grid operator, the preconditioner F^{-1} applied in
+ * the handle's precision.  B: device complex128, n x nrhs column-major, the
+ * right-hand sides in, the solutions out; columns iterate together until each
+ * reaches ||r|| <= tol ||b|| or maxit iterations.  st may be NULL.
+ */
+int rss_krylov(rss_handle h, rss_gridop_t A, void* B, int nrhs, int method, double tol, int maxit,
+               rss_krylov_stats* st);
 
 /*
  * rss_set_stream -- move a handle's later work to another stream (hipStream_t;

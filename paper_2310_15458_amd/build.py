@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librss.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["rss_kernels.hip", "rss_id.hip", "rss_residual.hip", "rss_host.cpp", "rss_server.cpp"]
+SOURCES = ["rss_kernels.hip", "rss_id.hip", "rss_residual.hip", "rss_fft.hip", "rss_host.cpp", "rss_server.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

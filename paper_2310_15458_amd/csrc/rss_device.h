@@ -70,6 +70,13 @@ struct KParams {
   int kind;  // 0 Laplace, 1 Helmholtz, 2 degenerate
   int q;
   double kappa, weight, diag;
+  // the paper's discretizations (Sec. 5): point scale s = sqrt(b) of the
+  // scattering potential b(x) = exp(-bump_a |x - (bcx, bcy)|^2) when bump != 0,
+  // and the diagonal diag + s^2 (cdre + i cdim), (cdre, cdim) = (weight / h^2)
+  // times the cell integral of K (0 without cell_diag)
+  int bump;
+  double bump_a, bcx, bcy;
+  double cdre, cdim;
 };
 
 // H0^(1)(x) = J0(x) + i Y0(x) for x > 0, in two parts.
@@ -159,11 +166,27 @@ __device__ __forceinline__ cx<double> kernel_raw(const KParams& kp, double xi, d
   return {-0.25 * y0, 0.25 * j0};
 }
 
-// Matrix entry a(i, j): w K off the diagonal (gi != gj), d on it.
+// s(x) = sqrt(b(x)) of the scattering potential (1 without one)
+__device__ __forceinline__ double point_scale(const KParams& kp, double x, double y) {
+  if (!kp.bump) return 1.0;
+  const double dx = x - kp.bcx, dy = y - kp.bcy;
+  return exp(-0.5 * kp.bump_a * (dx * dx + dy * dy));
+}
+
+// A_ii at a point of scale s
+__device__ __forceinline__ cx<double> diag_entry(const KParams& kp, double s) {
+  const double s2 = s * s;
+  return {kp.diag + s2 * kp.cdre, s2 * kp.cdim};
+}
+
+// Matrix entry a(i, j) (eq. e:aij): w s_i s_j K off the diagonal (gi != gj),
+// the diagonal rule on it.
 __device__ __forceinline__ cx<double> entry(const KParams& kp, const double* P, int gi, int gj) {
-  if (gi == gj) return {kp.diag, 0.0};
+  if (gi == gj) return diag_entry(kp, point_scale(kp, P[2 * gi], P[2 * gi + 1]));
   cx<double> k = kernel_raw(kp, P[2 * gi], P[2 * gi + 1], P[2 * gj], P[2 * gj + 1]);
-  return {kp.weight * k.x, kp.weight * k.y};
+  double w = kp.weight;
+  if (kp.bump) w *= point_scale(kp, P[2 * gi], P[2 * gi + 1]) * point_scale(kp, P[2 * gj], P[2 * gj + 1]);
+  return {w * k.x, w * k.y};
 }
 
 // ---------------------------------------------------------------------------

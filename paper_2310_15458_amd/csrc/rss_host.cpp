@@ -17,6 +17,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -430,6 +431,40 @@ struct ApplyGraphBase {
   virtual ~ApplyGraphBase() {}
 };
 
+// Product with A on a uniform grid by FFT (launch_grid_apply): the generator's
+// transform, the point scales and diagonal, and a work array grown on demand.
+struct rss_gridop {
+  GridDesc g{};
+  rss_kernel kern{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cx<double>* ghat = nullptr;
+  cx<double>* tw = nullptr;
+  double* scale = nullptr;
+  cx<double>* diag = nullptr;
+  cx<double>* work = nullptr;
+  size_t work_elems = 0;
+  ~rss_gridop() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : {(void*)ghat, (void*)tw, (void*)scale, (void*)diag, (void*)work})
+      if (p) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  // Y = A X (mode 0) or B - A X (mode 1) on stream st; ld = n^2
+  void apply(const cx<double>* X, const cx<double>* B, cx<double>* Y, int nrhs, int mode, hipStream_t st) {
+    const size_t need = (size_t)nrhs * g.n * g.M;
+    if (need > work_elems) {
+      HIPCHK(hipStreamSynchronize(st));
+      if (work) HIPCHK(hipFree(work));
+      work = nullptr;
+      work_elems = 0;
+      HIPCHK(hipMalloc((void**)&work, need * sizeof(cx<double>)));
+      work_elems = need;
+    }
+    launch_grid_apply(g, X, B, Y, (int64_t)g.n * g.n, nrhs, work, mode, st);
+  }
+};
+
 struct rss_ctx {
   int64_t N = 0;
   rss_kernel kern{};
@@ -459,6 +494,7 @@ struct rss_ctx {
   rss_stats stats{};
   Prof prof;
   int* d_err = nullptr;
+  rss_gridop* gridop = nullptr;  // refinement residual by FFT (rss_set_residual_op), not owned
   // captured applies per (sizeof(R), nrhs), at most MAX_GRAPHS (least recently
   // used dropped); declared last, so destroyed before the arena that owns the
   // factors they read
@@ -469,6 +505,48 @@ struct rss_ctx {
 
 namespace {
 
+// Integral of K over the h x h cell centred at the origin (eqs. e:a1i, e:b2).
+// The square is 8 congruent triangles 0 <= t <= pi/4, 0 <= r <= a / cos t
+// (a = h/2), so c = 8 int_0^{pi/4} F(a / cos t) dt with F(rho) = int_0^rho K(r) r dr:
+//  Laplace K = -log(r)/(2 pi): F(rho) = -(rho^2 log rho / 2 - rho^2 / 4) / (2 pi)
+//    and, in closed form, c = -(a^2/pi) (2 log a + log 2 - 3 + pi/2);
+//  Helmholtz K = (i/4) H0^(1)(kappa r): d/dz [z H1(z)] = z H0(z) and z H1(z) -> -2i/pi,
+//    so F(rho) = (i/4) (rho H1(kappa rho) / kappa + 2i / (pi kappa^2)); the smooth
+//    integral over t by 64-point Gauss-Legendre quadrature.
+std::complex<double> cell_integral(const rss_kernel& k) {
+  const double a = 0.5 * k.h;
+  if (k.kind == RSS_LAPLACE2D)
+    return {-(a * a / M_PI) * (2.0 * std::log(a) + std::log(2.0) - 3.0 + 0.5 * M_PI), 0.0};
+  constexpr int NG = 64;
+  double sum_re = 0.0, sum_im = 0.0;
+  for (int i = 1; i <= NG; ++i) {
+    // i-th root of the Legendre polynomial P_NG by Newton's method
+    double x = std::cos(M_PI * (i - 0.25) / (NG + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= NG; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = NG * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    const double wgt = 2.0 / ((1.0 - x * x) * dp * dp);
+    const double t = 0.125 * M_PI * (x + 1.0);  // [-1, 1] -> [0, pi/4]
+    const double rho = a / std::cos(t), z = k.kappa * rho;
+    const double j1 = std::cyl_bessel_j(1.0, z), y1 = std::cyl_neumann(1.0, z);
+    // (i/4) (rho (j1 + i y1) / kappa + 2i / (pi kappa^2))
+    const double in_re = rho * j1 / k.kappa, in_im = rho * y1 / k.kappa + 2.0 / (M_PI * k.kappa * k.kappa);
+    sum_re += wgt * (-0.25 * in_im);
+    sum_im += wgt * (0.25 * in_re);
+  }
+  const double scale = 8.0 * 0.125 * M_PI;  // 8 triangles, dt = (pi/8) dx
+  return {scale * sum_re, scale * sum_im};
+}
+
 KParams to_kp(const rss_kernel& k) {
   KParams p;
   p.kind = (int)k.kind;
@@ -476,6 +554,16 @@ KParams to_kp(const rss_kernel& k) {
   p.kappa = k.kappa;
   p.weight = k.weight;
   p.diag = k.diag;
+  p.bump = k.bump_a > 0 ? 1 : 0;
+  p.bump_a = k.bump_a;
+  p.bcx = k.bump_c[0];
+  p.bcy = k.bump_c[1];
+  p.cdre = p.cdim = 0.0;
+  if (k.cell_diag) {
+    const std::complex<double> c = cell_integral(k) * (k.weight / (k.h * k.h));
+    p.cdre = c.real();
+    p.cdim = c.imag();
+  }
   return p;
 }
 
@@ -490,6 +578,11 @@ void validate(const double* points, int64_t n, const rss_kernel* k, double tol, 
   if (k->kind == RSS_HELMHOLTZ2D && !(k->kappa > 0)) fail(RSS_EINVAL, "kappa must be > 0");
   if (k->kind == RSS_DEGENERATE && (k->q < 0 || k->q > 16)) fail(RSS_EINVAL, "q out of range");
   if (!std::isfinite(k->weight) || !std::isfinite(k->diag)) fail(RSS_EINVAL, "non-finite weight/diag");
+  if (k->cell_diag && (k->kind == RSS_DEGENERATE || !(k->h > 0) || !std::isfinite(k->h)))
+    fail(RSS_EINVAL, "cell_diag needs the Laplace or Helmholtz kernel and h > 0");
+  if (!(k->bump_a >= 0) || !std::isfinite(k->bump_a) || !std::isfinite(k->bump_c[0]) ||
+      !std::isfinite(k->bump_c[1]))
+    fail(RSS_EINVAL, "bad scattering potential parameters");
   for (int64_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(points[i])) fail(RSS_EINVAL, "non-finite point coordinate");
   // coincident points would put K(0) (log 0, H0(0)) into the matrix: sort the
@@ -2047,17 +2140,23 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
           apply_batch<double>(LH, Z, Lnr, s);
           for (int p : live) launch_add_c128(st[p].x, st[p].r, (int64_t)H[p]->N * nr[p], s);
         }
-        // residuals r = b - A x (FP64, on the fly), every live problem in one launch
+        // residuals r = b - A x in FP64: by FFT for handles with a grid
+        // operator (rss_set_residual_op), else on the fly, every such live
+        // problem in one launch
         {
           std::vector<ResProblem> rp;
           for (int p : live) {
+            if (H[p]->gridop) {
+              H[p]->gridop->apply(st[p].x, st[p].b, st[p].r, nr[p], 1, s);
+              continue;
+            }
             if (!H[p]->d_tperm) {
               const std::vector<int> perm = spatial_order(H[p]->h_points.data(), H[p]->N);
               H[p]->d_tperm = H[p]->arena.up(perm, s);
             }
             rp.push_back({H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p], H[p]->d_tperm});
           }
-          residual_batch(rp, rscr, s);
+          if (!rp.empty()) residual_batch(rp, rscr, s);
         }
         for (int p : live) {
           launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
@@ -2110,6 +2209,304 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
 }
 
 int rss_solve(rss_handle h, void* B, int nrhs) { return rss_solve_batch(1, &h, &B, &nrhs); }
+
+int rss_gridop_create(const rss_kernel* k, int n, double x0, double y0, double h, void* stream,
+                      rss_gridop_t* out) {
+  if (out) *out = nullptr;
+  rss_gridop* op = nullptr;
+  const int rc = run([&] {
+    if (!out || !k) fail(RSS_EINVAL, "null argument");
+    if (n < 1 || n > 2048) fail(RSS_EINVAL, "grid side must be 1 .. 2048");
+    if (!(h > 0) || !std::isfinite(h) || !std::isfinite(x0) || !std::isfinite(y0))
+      fail(RSS_EINVAL, "bad grid origin or spacing");
+    const double pt[2] = {x0 + 0.5 * h, y0 + 0.5 * h};
+    validate(pt, 1, k, 1.0, 1);
+    if (k->kind == RSS_DEGENERATE) fail(RSS_EUNSUPPORTED, "the grid product needs a translation-invariant kernel");
+    op = new rss_gridop();
+    op->kern = *k;
+    int logm = 1;
+    while ((1 << logm) < 2 * n - 1) ++logm;
+    GridDesc& g = op->g;
+    g.n = n;
+    g.M = 1 << logm;
+    g.logm = logm;
+    g.x0 = x0;
+    g.y0 = y0;
+    g.h = h;
+    g.kp = to_kp(*k);
+    if (stream) {
+      op->stream = (hipStream_t)stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
+      op->own_stream = true;
+    }
+    const size_t mm = (size_t)g.M * g.M, nn = (size_t)n * n;
+    HIPCHK(hipMalloc((void**)&op->ghat, mm * sizeof(cx<double>)));
+    HIPCHK(hipMalloc((void**)&op->tw, (size_t)(g.M / 2) * sizeof(cx<double>)));
+    HIPCHK(hipMalloc((void**)&op->scale, nn * sizeof(double)));
+    HIPCHK(hipMalloc((void**)&op->diag, nn * sizeof(cx<double>)));
+    std::vector<cx<double>> tw(g.M / 2);
+    for (int i = 0; i < g.M / 2; ++i) {
+      const double t = -2.0 * M_PI * (double)i / g.M;
+      tw[i] = cx<double>{std::cos(t), std::sin(t)};
+    }
+    HIPCHK(hipMemcpyAsync(op->tw, tw.data(), tw.size() * sizeof(cx<double>), hipMemcpyHostToDevice, op->stream));
+    g.tw = op->tw;
+    g.ghat = op->ghat;
+    g.scale = op->scale;
+    g.diag = op->diag;
+    launch_grid_setup(g, op->ghat, op->scale, op->diag, op->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(op->stream));
+  });
+  if (rc != RSS_OK) {
+    delete op;
+    return rc;
+  }
+  *out = op;
+  return RSS_OK;
+}
+
+int rss_gridop_apply(rss_gridop_t op, const void* X, void* Y, int nrhs) {
+  return run([&] {
+    if (!op || !X || !Y) fail(RSS_EINVAL, "null argument");
+    if (nrhs < 1) fail(RSS_EINVAL, "nrhs must be >= 1");
+    op->apply((const cx<double>*)X, nullptr, (cx<double>*)Y, nrhs, 0, op->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(op->stream));
+  });
+}
+
+int rss_gridop_residual(rss_gridop_t op, const void* X, const void* B, void* R, int nrhs) {
+  return run([&] {
+    if (!op || !X || !B || !R) fail(RSS_EINVAL, "null argument");
+    if (nrhs < 1) fail(RSS_EINVAL, "nrhs must be >= 1");
+    op->apply((const cx<double>*)X, (const cx<double>*)B, (cx<double>*)R, nrhs, 1, op->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(op->stream));
+  });
+}
+
+void rss_gridop_free(rss_gridop_t op) { delete op; }
+
+int rss_set_residual_op(rss_handle h, rss_gridop_t op) {
+  return run([&] {
+    if (!h) fail(RSS_EINVAL, "null handle");
+    if (op && (int64_t)op->g.n * op->g.n != h->N) fail(RSS_EINVAL, "the grid operator has another size");
+    h->gridop = op;
+  });
+}
+
+namespace {
+// z = F^{-1} r for one handle (complex128 in and out, r kept), in the handle's precision
+void precond_apply(rss_ctx* h, const cx<double>* r, cx<double>* z, int nrhs, cx<float>* zc, hipStream_t s) {
+  const size_t tot = (size_t)h->N * nrhs;
+  std::vector<rss_ctx*> H{h};
+  std::vector<int> nr{nrhs};
+  if (h->precision == RSS_FP64) {
+    HIPCHK(hipMemcpyAsync(z, r, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+    std::vector<cx<double>*> Z{z};
+    apply_batch<double>(H, Z, nr, s);
+  } else {
+    launch_cast_c64(r, h->N, nrhs, zc, s);
+    std::vector<cx<float>*> Z{zc};
+    apply_batch<float>(H, Z, nr, s);
+    HIPCHK(hipMemsetAsync(z, 0, tot * sizeof(cx<double>), s));
+    launch_axpy_from_c64(zc, h->N, nrhs, nullptr, z, s);
+  }
+}
+
+// per-column conj(x).y, to the host
+std::vector<std::complex<double>> coldots(const cx<double>* X, const cx<double>* Y, int64_t N, int nrhs,
+                                          cx<double>* part, cx<double>* dout, hipStream_t s) {
+  launch_cdot(X, Y, N, nrhs, part, dout, s);
+  std::vector<std::complex<double>> v(nrhs);
+  HIPCHK(hipMemcpyAsync(v.data(), dout, nrhs * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+cx<double>* up_scalars(const std::vector<std::complex<double>>& v, cx<double>* d, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+  return d;
+}
+}  // namespace
+
+int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, double tol, int maxit,
+               rss_krylov_stats* st) {
+  return run([&] {
+    if (!h || !A || !Bv) fail(RSS_EINVAL, "null argument");
+    if (nrhs < 1 || maxit < 1 || !(tol > 0) || (method != 0 && method != 1))
+      fail(RSS_EINVAL, "bad Krylov arguments");
+    if ((int64_t)A->g.n * A->g.n != h->N) fail(RSS_EINVAL, "the grid operator has another size");
+    const hipStream_t s = h->stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    const int64_t N = h->N;
+    const size_t tot = (size_t)N * nrhs, vb = tot * sizeof(cx<double>);
+    cx<double>* B = (cx<double>*)Bv;
+    Scratch scr;
+    cx<double>* b = (cx<double>*)scr.alloc(vb);
+    cx<double>* x = (cx<double>*)scr.alloc(vb);
+    cx<double>* z = (cx<double>*)scr.alloc(vb);
+    cx<double>* q = (cx<double>*)scr.alloc(vb);
+    cx<float>* zc = h->precision == RSS_FP64 ? nullptr : (cx<float>*)scr.alloc(tot * sizeof(cx<float>));
+    cx<double>* part = (cx<double>*)scr.alloc((size_t)KRYLOV_DOT_BLOCKS * nrhs * sizeof(cx<double>));
+    cx<double>* dout = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
+    cx<double>* sa = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
+    cx<double>* sb = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
+    HIPCHK(hipMemcpyAsync(b, B, vb, hipMemcpyDeviceToDevice, s));
+    std::vector<double> bn(nrhs);
+    {
+      const auto d = coldots(b, b, N, nrhs, part, dout, s);
+      for (int c = 0; c < nrhs; ++c) bn[c] = std::sqrt(std::max(0.0, d[c].real()));
+    }
+    int iters = 0;
+    if (method == 0) {
+      // preconditioned conjugate gradients, the columns in lock step
+      cx<double>* r = (cx<double>*)scr.alloc(vb);
+      cx<double>* pv = (cx<double>*)scr.alloc(vb);
+      HIPCHK(hipMemsetAsync(x, 0, vb, s));
+      HIPCHK(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, s));
+      precond_apply(h, r, z, nrhs, zc, s);
+      HIPCHK(hipMemcpyAsync(pv, z, vb, hipMemcpyDeviceToDevice, s));
+      std::vector<std::complex<double>> rz = coldots(r, z, N, nrhs, part, dout, s);
+      std::vector<char> act(nrhs, 1);
+      for (int c = 0; c < nrhs; ++c)
+        if (!(bn[c] > 0)) act[c] = 0;
+      for (int it = 0; it < maxit; ++it) {
+        if (std::find(act.begin(), act.end(), 1) == act.end()) break;
+        A->apply(pv, nullptr, q, nrhs, 0, s);
+        const auto pq = coldots(pv, q, N, nrhs, part, dout, s);
+        std::vector<std::complex<double>> al(nrhs), mal(nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+          al[c] = act[c] && std::abs(pq[c]) > 0 ? rz[c] / pq[c] : 0.0;
+          mal[c] = -al[c];
+        }
+        launch_caxpby(pv, x, N, nrhs, up_scalars(al, sa, s), nullptr, s);
+        launch_caxpby(q, r, N, nrhs, up_scalars(mal, sb, s), nullptr, s);
+        iters = it + 1;
+        const auto rr = coldots(r, r, N, nrhs, part, dout, s);
+        for (int c = 0; c < nrhs; ++c)
+          if (act[c] && std::sqrt(std::max(0.0, rr[c].real())) <= tol * bn[c]) act[c] = 0;
+        if (std::find(act.begin(), act.end(), 1) == act.end()) break;
+        precond_apply(h, r, z, nrhs, zc, s);
+        const auto rzn = coldots(r, z, N, nrhs, part, dout, s);
+        std::vector<std::complex<double>> be(nrhs);
+        for (int c = 0; c < nrhs; ++c) be[c] = act[c] && std::abs(rz[c]) > 0 ? rzn[c] / rz[c] : 0.0;
+        launch_caxpby(z, pv, N, nrhs, nullptr, up_scalars(be, sa, s), s);
+        rz = rzn;
+      }
+    } else {
+      // right-preconditioned GMRES (no restart), Arnoldi by classical
+      // Gram-Schmidt applied twice, the columns in lock step
+      const int64_t vstride = (int64_t)tot;
+      cx<double>* V = (cx<double>*)scr.alloc((size_t)(maxit + 1) * vb);
+      cx<double>* hcoef = (cx<double>*)scr.alloc((size_t)(maxit + 1) * nrhs * sizeof(cx<double>));
+      using C = std::complex<double>;
+      std::vector<std::vector<C>> H((size_t)nrhs, std::vector<C>((size_t)(maxit + 1) * maxit, 0.0));
+      std::vector<std::vector<C>> cs(nrhs, std::vector<C>(maxit)), sn(nrhs, std::vector<C>(maxit));
+      std::vector<std::vector<C>> gg(nrhs, std::vector<C>(maxit + 1, 0.0));
+      std::vector<int> kc(nrhs, 0);  // Arnoldi steps that count for each column
+      std::vector<char> act(nrhs, 1);
+      auto Hat = [&](int c, int i, int j) -> C& { return H[c][(size_t)j * (maxit + 1) + i]; };
+      HIPCHK(hipMemsetAsync(V, 0, vb, s));
+      {
+        std::vector<C> inv(nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+          inv[c] = bn[c] > 0 ? 1.0 / bn[c] : 0.0;
+          gg[c][0] = bn[c];
+          if (!(bn[c] > 0)) act[c] = 0;
+        }
+        launch_caxpby(b, V, N, nrhs, up_scalars(inv, sa, s), nullptr, s);
+      }
+      for (int k = 0; k < maxit; ++k) {
+        if (std::find(act.begin(), act.end(), 1) == act.end()) break;
+        cx<double>* w = V + (size_t)(k + 1) * vstride;
+        precond_apply(h, V + (size_t)k * vstride, z, nrhs, zc, s);
+        A->apply(z, nullptr, w, nrhs, 0, s);
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<C> hv((size_t)(k + 1) * nrhs);
+          for (int j = 0; j <= k; ++j) {
+            const auto d = coldots(V + (size_t)j * vstride, w, N, nrhs, part, dout, s);
+            for (int c = 0; c < nrhs; ++c) {
+              hv[(size_t)j * nrhs + c] = d[c];
+              Hat(c, j, k) += d[c];
+            }
+          }
+          HIPCHK(hipMemcpyAsync(hcoef, hv.data(), hv.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+          launch_lincomb_sub(V, vstride, k + 1, hcoef, w, N, nrhs, s);
+        }
+        const auto ww = coldots(w, w, N, nrhs, part, dout, s);
+        std::vector<C> inv(nrhs);
+        for (int c = 0; c < nrhs; ++c) {
+          const double hn = std::sqrt(std::max(0.0, ww[c].real()));
+          Hat(c, k + 1, k) = hn;
+          inv[c] = hn > 0 ? 1.0 / hn : 0.0;
+        }
+        launch_caxpby(w, w, N, nrhs, up_scalars(inv, sa, s), up_scalars(std::vector<C>(nrhs, 0.0), sb, s), s);
+        iters = k + 1;
+        for (int c = 0; c < nrhs; ++c) {
+          if (!act[c]) continue;
+          // rotations G_i = [[conj(c_i), conj(s_i)], [-s_i, c_i]] (unitary)
+          for (int i = 0; i < k; ++i) {
+            const C t = std::conj(cs[c][i]) * Hat(c, i, k) + std::conj(sn[c][i]) * Hat(c, i + 1, k);
+            Hat(c, i + 1, k) = -sn[c][i] * Hat(c, i, k) + cs[c][i] * Hat(c, i + 1, k);
+            Hat(c, i, k) = t;
+          }
+          const C a = Hat(c, k, k), cc = Hat(c, k + 1, k);
+          const double den = std::sqrt(std::norm(a) + std::norm(cc));
+          cs[c][k] = den > 0 ? a / den : C(1.0);
+          sn[c][k] = den > 0 ? cc / den : C(0.0);
+          Hat(c, k, k) = den;
+          Hat(c, k + 1, k) = 0.0;
+          gg[c][k + 1] = -sn[c][k] * gg[c][k];
+          gg[c][k] = std::conj(cs[c][k]) * gg[c][k];
+          kc[c] = k + 1;
+          if (std::abs(gg[c][k + 1]) <= tol * bn[c] || std::abs(ww[c]) == 0.0) act[c] = 0;
+        }
+      }
+      // y = R^{-1} g per column, u = sum_j y_j V_j, x = F^{-1} u
+      std::vector<C> ycoef((size_t)(maxit + 1) * nrhs, 0.0);
+      int kmax = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        const int m = kc[c];
+        kmax = std::max(kmax, m);
+        std::vector<C> y(m);
+        for (int i = m - 1; i >= 0; --i) {
+          C acc = gg[c][i];
+          for (int j = i + 1; j < m; ++j) acc -= Hat(c, i, j) * y[j];
+          y[i] = acc / Hat(c, i, i);
+        }
+        for (int i = 0; i < m; ++i) ycoef[(size_t)i * nrhs + c] = -y[i];
+      }
+      HIPCHK(hipMemsetAsync(q, 0, vb, s));
+      HIPCHK(hipMemcpyAsync(hcoef, ycoef.data(), (size_t)kmax * nrhs * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+      launch_lincomb_sub(V, vstride, kmax, hcoef, q, N, nrhs, s);
+      precond_apply(h, q, x, nrhs, zc, s);
+    }
+    // the true relative residual of the result
+    A->apply(x, b, q, nrhs, 1, s);
+    const auto rr = coldots(q, q, N, nrhs, part, dout, s);
+    double worst = 0.0;
+    for (int c = 0; c < nrhs; ++c)
+      worst = std::max(worst, bn[c] > 0 ? std::sqrt(std::max(0.0, rr[c].real())) / bn[c] : 0.0);
+    HIPCHK(hipMemcpyAsync(B, x, vb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) {
+      st->iters = iters;
+      st->relres = worst;
+      st->t_ms = ms;
+    }
+  });
+}
 
 void rss_free(rss_handle h) { destroy_ctx(h); }
 

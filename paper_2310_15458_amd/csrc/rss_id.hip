@@ -109,7 +109,7 @@ __device__ __forceinline__ void dd_sqrt(double ah, double al, double& h, double&
 // sum over the chunk's rows y of Y of  Re(y)^T Re(y) + Im(y)^T Im(y)  for 256
 // 4 x 4 tiles of the upper triangle.  Rows of Y: the M boxes of B (distance 2,
 // ascending offset order, each box's active rows), then the n_proxy proxy
-// points w K(y_p, x_j).  Rows are staged in LDS GRAM_SR at a time, as FP64.
+// points w K(y_p, x_j) s_j (s the point scale of the box's columns).  Rows are staged in LDS GRAM_SR at a time, as FP64.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_SR = 16;
 
@@ -195,9 +195,11 @@ __global__ __launch_bounds__(256) void k_gram(const Prob<R>* probs, Phase<R> ph,
           double sn, cs;
           sincos(th, &sn, &cs);
           const int g = I[j];
-          const cx<double> k = kernel_raw(kp, cxx + rad * cs, cyy + rad * sn, pr.P[2 * g], pr.P[2 * g + 1]);
-          // the stored precision of the form (entries of Y are rounded like the blocks)
-          const cx<R> v = from_d<R>(kp.weight * k.x, kp.weight * k.y);
+          const double px = pr.P[2 * g], py = pr.P[2 * g + 1];
+          const cx<double> k = kernel_raw(kp, cxx + rad * cs, cyy + rad * sn, px, py);
+          // w K(y_p, x_j) s_j; rounded to the stored precision like the blocks
+          const double w = kp.weight * point_scale(kp, px, py);
+          const cx<R> v = from_d<R>(w * k.x, w * k.y);
           re = (double)v.x;
           im = (double)v.y;
         }

@@ -294,6 +294,33 @@ void launch_cast_c64(const cx<double>* V, int64_t n, int nrhs, cx<float>* out, h
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_t s);
 
+// Product with A on a uniform n x n grid of cell centres (x0 + (ix + 1/2) h,
+// y0 + (iy + 1/2) h), user index iy n + ix, by FFT of an M x M circulant
+// embedding of the Toeplitz part (M the power of two >= 2n - 1)
+struct GridDesc {
+  int n, M, logm;
+  double x0, y0, h;
+  KParams kp;
+  const cx<double>* ghat;  // M x M, row-major [ky][kx]: FFT2 of the generator
+  const cx<double>* tw;    // M / 2 twiddles exp(-2 pi i k / M)
+  const double* scale;     // n^2 point scales
+  const cx<double>* diag;  // n^2 diagonal entries
+};
+// generator transform (into C, which becomes ghat), point scales and diagonal
+void launch_grid_setup(const GridDesc& g, cx<double>* C, double* scale, cx<double>* diag, hipStream_t s);
+// Y = A X (mode 0) or Y = B - A X (mode 1), X, B, Y: n^2 x nrhs (ld), T: nrhs n M work
+void launch_grid_apply(const GridDesc& g, const cx<double>* X, const cx<double>* B, cx<double>* Y, int64_t ld,
+                       int nrhs, cx<double>* T, int mode, hipStream_t s);
+// Krylov vector kernels: per-column conj(x).y (part: 64 nrhs entries of work),
+// Y = a X + b Y with per-column a, b (null = 1), Y -= sum_j h_j V_j
+void launch_cdot(const cx<double>* X, const cx<double>* Y, int64_t N, int nrhs, cx<double>* part,
+                 cx<double>* out, hipStream_t s);
+void launch_caxpby(const cx<double>* X, cx<double>* Y, int64_t N, int nrhs, const cx<double>* a,
+                   const cx<double>* b, hipStream_t s);
+void launch_lincomb_sub(const cx<double>* V, int64_t vstride, int k, const cx<double>* h, cx<double>* Y,
+                        int64_t N, int nrhs, hipStream_t s);
+constexpr int KRYLOV_DOT_BLOCKS = 64;
+
 // set on the solve server's worker threads: batches of several handles there
 // reuse tuned solve tiles but do not tune (see rss_set_autotune)
 extern thread_local bool g_server_thread;

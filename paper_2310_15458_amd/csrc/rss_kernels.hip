@@ -93,8 +93,9 @@ void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStr
 
 // ---------------------------------------------------------------------------
 // compression matrix (eqs. e:con, e:proxy):
-//   C = [A_{M,B}; A_{B,M}^*; w K(proxy, B); (w K(B, proxy))^*]
-// M boxes in ascending id order, rows of each in its active order.
+//   C = [A_{M,B}; A_{B,M}^*; w K(proxy, B) S_B; (w S_B K(B, proxy))^*]
+// (S_B the point scales of the box), M boxes in ascending id order, rows of
+// each in its active order.
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(256) void k_build_C(const Prob<R>* probs, Phase<R> ph) {
@@ -170,12 +171,13 @@ __global__ __launch_bounds__(256) void k_build_C(const Prob<R>* probs, Phase<R> 
       const double gx = cxx + rad * cs, gy = cyy + rad * sn;
       const int g = I[j];
       const double px = P[2 * g], py = P[2 * g + 1];
+      const double w = kp.weight * point_scale(kp, px, py);
       if (!second) {
         const cx<double> k = kernel_raw(kp, gx, gy, px, py);
-        val = from_d<R>(kp.weight * k.x, kp.weight * k.y);
+        val = from_d<R>(w * k.x, w * k.y);
       } else {
         const cx<double> k = kernel_raw(kp, px, py, gx, gy);
-        val = from_d<R>(kp.weight * k.x, -(kp.weight * k.y));
+        val = from_d<R>(w * k.x, -(w * k.y));
       }
     }
     C[row + (int64_t)j * m] = val;

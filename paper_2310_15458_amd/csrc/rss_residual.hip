@@ -67,7 +67,7 @@ constexpr int RES_TSTRIDE = 2 * (RSS_BESSEL_DEG + 1);  // doubles per interval o
 #endif
 
 __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* dd, const ResBlock* blk, int c0) {
-  __shared__ double sx[RES_SB], sy[RES_SB];
+  __shared__ double sx[RES_SB], sy[RES_SB], ssc[RES_SB];
   __shared__ cx<double> xs[RES_SB * 16];
   __shared__ __align__(16) double stab[RSS_BESSEL_NSEG * RES_TSTRIDE];
   const ResBlock bb = blk[blockIdx.x];
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
   const int li = lane & 15, lk = lane >> 4;
   // this lane's target in each of the wave's groups of 16: the A-operand row
   const int64_t base = (int64_t)bb.tb * 256 + (int64_t)blockIdx.y * RES_TPB + wv * 16 * RES_RG;
-  double tx[RES_RG], ty[RES_RG];
+  double tx[RES_RG], ty[RES_RG], tsc[RES_RG];
   int64_t ti[RES_RG];
 #pragma unroll
   for (int g = 0; g < RES_RG; ++g) {
@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
     ti[g] = lin < n ? (D.tperm ? (int64_t)D.tperm[lin] : lin) : -1;
     tx[g] = ti[g] >= 0 ? D.P[2 * ti[g]] : 0.0;
     ty[g] = ti[g] >= 0 ? D.P[2 * ti[g] + 1] : 0.0;
+    tsc[g] = point_scale(kp, tx[g], ty[g]);  // the point scale s_i of the paper's potential (1 without)
   }
   const int64_t ntile = (n + 255) / 256, per = (ntile + D.S - 1) / D.S;
   const int64_t lo = (int64_t)bb.sp * per * 256, hi = min(n, lo + per * 256);
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
       const int64_t sj = t0 + threadIdx.x;
       sx[threadIdx.x] = sj < hi ? D.P[2 * sj] : 0.0;
       sy[threadIdx.x] = sj < hi ? D.P[2 * sj + 1] : 0.0;
+      ssc[threadIdx.x] = point_scale(kp, sx[threadIdx.x], sy[threadIdx.x]);
     }
     for (int e = threadIdx.x; e < RES_SB * 16; e += 256) {
       const int sl = e >> 4, c = e & 15;
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
         cx<double> a = czero<double>();
         if (sv && ti[g] >= 0) {
           if (sg == ti[g]) {
-            a = cx<double>{kp.diag, 0.0};
+            a = diag_entry(kp, tsc[g]);
           } else if (kp.kind == 1) {
             const double x = __dmul_rn(kp.kappa, dist_pos(tx[g], ty[g], px, py));
             if (x < RSS_BESSEL_XA) {
@@ -148,6 +150,10 @@ __global__ __launch_bounds__(256, RSS_RES_MINW) void k_residual(const ResDesc* d
           } else {
             const cx<double> kv = kernel_raw(kp, tx[g], ty[g], px, py);
             a = cx<double>{kp.weight * kv.x, kp.weight * kv.y};
+          }
+          if (kp.bump && sg != ti[g]) {
+            const double sc = tsc[g] * ssc[sl];
+            a = cx<double>{a.x * sc, a.y * sc};
           }
         }
         k1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, xv.x, k1[g], 0, 0, 0);

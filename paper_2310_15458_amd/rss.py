@@ -24,7 +24,8 @@ _KIND = {"laplace": 0, "helmholtz": 1, "degenerate": 2}
 
 class rss_kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("kappa", ctypes.c_double), ("weight", ctypes.c_double),
-                ("diag", ctypes.c_double), ("q", ctypes.c_int)]
+                ("diag", ctypes.c_double), ("q", ctypes.c_int), ("cell_diag", ctypes.c_int),
+                ("h", ctypes.c_double), ("bump_a", ctypes.c_double), ("bump_c", ctypes.c_double * 2)]
 
 
 class rss_options(ctypes.Structure):
@@ -50,10 +51,15 @@ class rss_stats(ctypes.Structure):
 
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
            "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
-           "rss_residual_static",
+           "rss_residual_static", "rss_gridop_create", "rss_gridop_apply", "rss_gridop_residual",
+           "rss_gridop_free", "rss_set_residual_op", "rss_krylov",
            "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
+
+
+class rss_krylov_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("t_ms", ctypes.c_double)]
 
 
 class rss_server_options(ctypes.Structure):
@@ -116,6 +122,16 @@ def load():
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.rss_residual_static.argtypes = [P(rss_kernel), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    lib.rss_gridop_create.argtypes = [P(rss_kernel), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_void_p, P(ctypes.c_void_p)]
+    lib.rss_gridop_apply.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.rss_gridop_residual.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int]
+    lib.rss_gridop_free.argtypes = [ctypes.c_void_p]
+    lib.rss_gridop_free.restype = None
+    lib.rss_set_residual_op.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.rss_krylov.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_int, P(rss_krylov_stats)]
     lib.rss_factor_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_int64), P(rss_kernel),
                                      ctypes.c_double, ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
     lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
@@ -146,9 +162,16 @@ def _check(rc):
 
 
 def make_kernel(kern) -> rss_kernel:
-    """From any object with kind/kappa/weight/diag/q (e.g. workloads.Kernel)."""
-    return rss_kernel(_KIND[kern.kind], float(kern.kappa), float(kern.weight), float(kern.diag),
-                      int(getattr(kern, "q", 2)))
+    """From any object with kind/kappa/weight/diag/q and optionally
+    cell_diag/h/bump_a/bump_c (e.g. workloads.Kernel)."""
+    k = rss_kernel(_KIND[kern.kind], float(kern.kappa), float(kern.weight), float(kern.diag),
+                   int(getattr(kern, "q", 2)))
+    k.cell_diag = 1 if getattr(kern, "cell_diag", False) else 0
+    k.h = float(getattr(kern, "h", 0.0))
+    k.bump_a = float(getattr(kern, "bump_a", 0.0))
+    c = getattr(kern, "bump_c", (0.5, 0.5))
+    k.bump_c[0], k.bump_c[1] = float(c[0]), float(c[1])
+    return k
 
 
 def _stream_ptr(stream):
@@ -345,6 +368,69 @@ def residual_static(kern, points_dev, X, B):
                                       ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
                                       ctypes.c_void_p(R.data_ptr()), nrhs, _stream_ptr(None)))
     return R
+
+
+class GridOperator:
+    """rss_gridop_*: the product with A on the n x n grid of cell centres of
+    [x0, x0 + n h] x [y0, y0 + n h] by FFT (the workloads' grids: x0 = y0 = 0,
+    h = 1/n)."""
+
+    def __init__(self, kern, n: int, x0: float = 0.0, y0: float = 0.0, h: float = 0.0, stream=None):
+        k = make_kernel(kern)
+        out = ctypes.c_void_p()
+        _check(load().rss_gridop_create(ctypes.byref(k), int(n), float(x0), float(y0),
+                                        float(h) if h else 1.0 / n, _stream_ptr(stream), ctypes.byref(out)))
+        self._op = out
+        self.n = n
+
+    def apply(self, X):
+        """A X for a complex128 column-major CUDA tensor X (n^2 x nrhs)."""
+        import torch
+        nrhs = 1 if X.dim() == 1 else X.shape[1]
+        Y = torch.empty((nrhs, X.shape[0]), dtype=torch.complex128, device=X.device).t()
+        if X.dim() == 1:
+            Y = Y[:, 0]
+        _check(load().rss_gridop_apply(self._op, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                       nrhs))
+        return Y
+
+    def residual(self, X, B):
+        import torch
+        nrhs = 1 if X.dim() == 1 else X.shape[1]
+        R = torch.empty((nrhs, X.shape[0]), dtype=torch.complex128, device=X.device).t()
+        if X.dim() == 1:
+            R = R[:, 0]
+        _check(load().rss_gridop_residual(self._op, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                          ctypes.c_void_p(R.data_ptr()), nrhs))
+        return R
+
+    def close(self):
+        if getattr(self, "_op", None):
+            load().rss_gridop_free(self._op)
+            self._op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_residual_op(fact, op):
+    """rss_set_residual_op: refined solves of `fact` take their residual from
+    the grid operator `op` (None: the on-the-fly residual)."""
+    _check(load().rss_set_residual_op(fact._h, op._op if op is not None else None))
+
+
+def krylov(fact, op, B, method: str = "cg", tol: float = 1e-12, maxit: int = 100) -> dict:
+    """rss_krylov: CG ("cg") or GMRES ("gmres") preconditioned by the
+    factorization, products by the grid operator; B (complex128 column-major
+    CUDA tensor) is overwritten with the solution."""
+    st = rss_krylov_stats()
+    nrhs = fact._b(B)
+    _check(load().rss_krylov(fact._h, op._op, ctypes.c_void_p(B.data_ptr()), nrhs,
+                             0 if method == "cg" else 1, float(tol), int(maxit), ctypes.byref(st)))
+    return {"iters": st.iters, "relres": st.relres, "t_ms": st.t_ms}
 
 
 def solve_batch(facts, Bs):

@@ -52,6 +52,11 @@ template void launch_root_apply<R>(const RootApply<R>*, int, int, int, GemmDesc<
 I(double) I(float)
 void launch_kernel_block(const KParams&, const double*, const int*, int64_t, const int*, int64_t, cx<double>*, hipStream_t) {}
 void* residual_static_scratch() { return nullptr; }
+void launch_grid_setup(const GridDesc&, cx<double>*, double*, cx<double>*, hipStream_t) {}
+void launch_grid_apply(const GridDesc&, const cx<double>*, const cx<double>*, cx<double>*, int64_t, int, cx<double>*, int, hipStream_t) {}
+void launch_cdot(const cx<double>*, const cx<double>*, int64_t, int nrhs, cx<double>*, cx<double>* out, hipStream_t) { for (int i = 0; i < nrhs; ++i) out[i] = cx<double>{1.0, 0.0}; }
+void launch_caxpby(const cx<double>*, cx<double>*, int64_t, int, const cx<double>*, const cx<double>*, hipStream_t) {}
+void launch_lincomb_sub(const cx<double>*, int64_t, int, const cx<double>*, cx<double>*, int64_t, int, hipStream_t) {}
 int residual_slices(int64_t target_blocks) { return target_blocks >= 1024 ? 1 : 4; }
 void launch_residual(const ResDesc*, const ResBlock*, int, const ResBlock*, int, int, hipStream_t) {}
 void launch_colnorms(const cx<double>*, int64_t, int nrhs, double* out, hipStream_t) { for (int i = 0; i < nrhs; ++i) out[i] = 1.0; }

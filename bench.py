@@ -41,10 +41,33 @@ FP64_PEAK_TF = 78.6
 FP32_MFMA_PEAK_TF = 157.3
 
 
+def host_description():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def host_threads():
+    """the host cores this process may use (the GPU machine grants a share of them)"""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = int(os.environ.get("OMP_NUM_THREADS", n) or n)
+    return max(1, min(n, cap))
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a bounded sample of the same workload: the
     128 x 128 corner of the 512^2 grid (same h, kappa, weight, tol, leaf, proxy
-    count), FP64 factorization, BLAS limited to one thread."""
+    count), FP64 factorization, timed with BLAS limited to one thread and with
+    all the host threads this process may use."""
     import threadpoolctl
     from oracle import rss as orss
     from paper_2310_15458_amd import workloads as W
@@ -55,14 +78,49 @@ def cpu_baseline():
     iy = np.arange(w.n * w.n) // w.n
     sel = (ix < side) & (iy < side)
     Ps = P[sel]
-    with threadpoolctl.threadpool_limits(1):
-        t0 = time.perf_counter()
-        orss.factor(Ps, w.kernel, w.tol, w.leaf, orss.Options(n_proxy=w.n_proxy),
-                    root=(0.0, 0.0, side / w.n))
-        dt = time.perf_counter() - t0
-    return {"value": Ps.shape[0] / dt, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+    res = {}
+    for nt in (1, host_threads()):
+        with threadpoolctl.threadpool_limits(nt):
+            t0 = time.perf_counter()
+            orss.factor(Ps, w.kernel, w.tol, w.leaf, orss.Options(n_proxy=w.n_proxy),
+                        root=(0.0, 0.0, side / w.n))
+            res[nt] = time.perf_counter() - t0
+    nt_all = max(res)
+    best = min(res, key=lambda k: res[k])
+    return {"value": Ps.shape[0] / res[best], "unit": "unknowns/s", "cores": best, "kind": "oracle",
             "sample": f"FP64 factorization of the {side}x{side} corner of the 512^2 grid "
-                      f"({Ps.shape[0]} unknowns, same h/kappa/tol/leaf), {dt:.1f} s"}
+                      f"({Ps.shape[0]} unknowns, same h/kappa/tol/leaf)",
+            "threads": {str(k): {"seconds": v, "unknowns_per_s": Ps.shape[0] / v} for k, v in res.items()},
+            "host": host_description(), "blas_threads_all": nt_all}
+
+
+def paper_matrices(torch, rss, W, n=512, eps=1e-6):
+    """The paper's own matrices (Sec. 5) at N = n^2: first-kind Laplace
+    (eqs. e:a1, e:a1i) solved by CG and Lippmann-Schwinger Helmholtz kappa = 25
+    (eqs. e:b1, e:b2) by GMRES, each preconditioned by its FP64 factorization,
+    to relres 1e-12 (Tab. t:notations n_it), uniform random b (seed 0)."""
+    out = {}
+    for name, kern, method in (("laplace_first_kind", W.paper_laplace(n), "cg"),
+                               ("lippmann_schwinger_k25", W.paper_helmholtz(n, 25.0), "gmres")):
+        P = W.grid_points(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rss.Factorization(P, kern, eps, 64, n_proxy=64 if kern.kind == "laplace" else 128)
+        t_fact = time.perf_counter() - t0
+        op = rss.GridOperator(kern, n)
+        b = W.uniform_rhs(n * n, 1, 0)
+        x1 = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()
+        F.apply(x1)
+        relres1 = float(np.linalg.norm(op.residual(x1, torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t())
+                                       .cpu().numpy()) / np.linalg.norm(b))
+        Bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()
+        st = rss.krylov(F, op, Bd, method=method, tol=1e-12, maxit=100)
+        out[name] = {"N": n * n, "eps": eps, "method": method, "t_factor_ms": t_fact * 1e3,
+                     "relres_one_apply": relres1, "n_it": st["iters"], "relres": st["relres"],
+                     "t_krylov_ms": st["t_ms"]}
+        op.close()
+        F.close()
+    return out
 
 
 def batched_sweep(torch, rss, W, reps=2):
@@ -146,6 +204,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-paper", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on one GPU only (the path is single-device); "
@@ -166,7 +225,9 @@ def main():
     work = torch.empty_like(B)
     single = torch.empty_like(B)
 
-    def step(record):
+    gop = rss.GridOperator(w.kernel, w.n)  # the FFT product on the grid (residual variant)
+
+    def step(record, keep=False):
         t = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -178,6 +239,16 @@ def main():
         rc32 = F32.solve(work)
         t["solve32"] = time.perf_counter() - t0
         i32 = F32.info()
+        x32 = work.cpu().numpy() if keep else None
+        # the same solve with the refinement residual by FFT
+        rss.set_residual_op(F32, gop)
+        work.copy_(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F32.solve(work)
+        t["solve32_fft"] = time.perf_counter() - t0
+        i32f = F32.info()
+        rss.set_residual_op(F32, None)
         lat32 = []
         for _ in range(SOLVE_REPS):
             single.copy_(B)
@@ -197,6 +268,15 @@ def main():
         rc64 = F64.solve(work)
         t["solve64"] = time.perf_counter() - t0
         i64 = F64.info()
+        x64 = work.cpu().numpy() if keep else None
+        rss.set_residual_op(F64, gop)
+        work.copy_(B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F64.solve(work)
+        t["solve64_fft"] = time.perf_counter() - t0
+        i64f = F64.info()
+        rss.set_residual_op(F64, None)
         lat64 = []
         for _ in range(SOLVE_REPS):
             single.copy_(B)
@@ -206,24 +286,33 @@ def main():
             lat64.append(time.perf_counter() - t0)
         F64.close()
         if record is not None:
-            record.append({"t": t, "i32": i32, "i64": i64, "rc": (rc32, rc64),
-                           "lat32": lat32, "lat64": lat64})
+            record.append({"t": t, "i32": i32, "i64": i64, "i32f": i32f, "i64f": i64f, "rc": (rc32, rc64),
+                           "lat32": lat32, "lat64": lat64, "x32": x32, "x64": x64})
 
     for _ in range(args.warmup):
         step(None)
     recs = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step(recs)
+    for i in range(args.steps):
+        step(recs, keep=(i == args.steps - 1))
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
+    gop.close()
+    # relres of the last step's results by the oracle's exact FFT product (host)
+    from oracle import matvec as omv
+    orr32 = omv.relres(omv.fft_matvec(w.kernel, w.n, recs[-1]["x32"]), B_host)
+    orr64 = omv.relres(omv.fft_matvec(w.kernel, w.n, recs[-1]["x64"]), B_host)
+    for r in recs:
+        del r["x32"], r["x64"]
     N = w.N
     f32 = sum(r["t"]["fact32"] for r in recs)
     f64 = sum(r["t"]["fact64"] for r in recs)
     s32 = [r["t"]["solve32"] for r in recs]
     s64 = [r["t"]["solve64"] for r in recs]
+    s32f = [r["t"]["solve32_fft"] for r in recs]
+    s64f = [r["t"]["solve64_fft"] for r in recs]
     lat32 = np.array([x for r in recs for x in r["lat32"]]) * 1e3  # ms
     lat64 = np.array([x for r in recs for x in r["lat64"]]) * 1e3
     i32, i64 = recs[-1]["i32"], recs[-1]["i64"]
@@ -298,18 +387,26 @@ def main():
             "t_factor_ms": f32 / len(recs) * 1e3,
             "t_solve_to_1e-10_ms": float(np.median(s32) * 1e3),
             "time_to_solution_unknowns_per_s": N / (f32 / len(recs) + float(np.median(s32))),
-            "relres": i32["last_relres"], "refine_steps": i32["last_iters"],
+            "relres": i32["last_relres"], "relres_oracle_fft": orr32, "refine_steps": i32["last_iters"],
             "apply_p50_ms": float(np.percentile(lat32, 50)), "apply_p99_ms": float(np.percentile(lat32, 99)),
             "device_GB": i32["device_bytes"] / 1e9,
+            "fft_residual": {"t_solve_to_1e-10_ms": float(np.median(s32f) * 1e3),
+                             "time_to_solution_unknowns_per_s": N / (f32 / len(recs) + float(np.median(s32f))),
+                             "relres": recs[-1]["i32f"]["last_relres"],
+                             "refine_steps": recs[-1]["i32f"]["last_iters"]},
         },
         "fp64": {
             "factor_unknowns_per_s": N * len(recs) / f64,
             "t_factor_ms": f64 / len(recs) * 1e3,
             "t_solve_to_1e-10_ms": float(np.median(s64) * 1e3),
             "time_to_solution_unknowns_per_s": N / (f64 / len(recs) + float(np.median(s64))),
-            "relres": i64["last_relres"], "refine_steps": i64["last_iters"],
+            "relres": i64["last_relres"], "relres_oracle_fft": orr64, "refine_steps": i64["last_iters"],
             "apply_p50_ms": float(np.percentile(lat64, 50)), "apply_p99_ms": float(np.percentile(lat64, 99)),
             "device_GB": i64["device_bytes"] / 1e9,
+            "fft_residual": {"t_solve_to_1e-10_ms": float(np.median(s64f) * 1e3),
+                             "time_to_solution_unknowns_per_s": N / (f64 / len(recs) + float(np.median(s64f))),
+                             "relres": recs[-1]["i64f"]["last_relres"],
+                             "refine_steps": recs[-1]["i64f"]["last_iters"]},
         },
         "ranks_fp32": [round(i32["rank_sum"][d] / max(1, i32["box_count"][d]), 2) for d in range(2, i32["depth"] + 1)],
         "ranks_fp64": [round(i64["rank_sum"][d] / max(1, i64["box_count"][d]), 2) for d in range(2, i64["depth"] + 1)],
@@ -320,6 +417,8 @@ def main():
         "cpu_baseline": None,
     }
     out["batched"] = batched_sweep(torch, rss, W)
+    if not args.no_paper:
+        out["paper_matrices"] = paper_matrices(torch, rss, W)
     if not args.no_serving:
         out["serving"] = serving(torch, rss, W)
     if not args.no_cpu_baseline:

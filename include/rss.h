@@ -200,6 +200,8 @@ typedef struct {
   double device_bytes;    /* device memory held by the handle */
   double t_class_ms[12];  /* per kernel class, summed over launches (rss_options.profile) */
   int64_t n_class[12];    /* launches per kernel class */
+  int id_retries;         /* 1 if the factorization was redone with the single-workgroup QR
+                             after a multi-workgroup barrier timed out (boxes above 192 points) */
 } rss_stats;
 
 /* rss_info -- statistics of a factorization (host struct filled). */

@@ -495,6 +495,7 @@ struct rss_ctx {
   Prof prof;
   int* d_err = nullptr;
   rss_gridop* gridop = nullptr;  // refinement residual by FFT (rss_set_residual_op), not owned
+  bool no_mg = false;            // factor without the multi-workgroup QR (after a barrier timeout)
   // captured applies per (sizeof(R), nrhs), at most MAX_GRAPHS (least recently
   // used dropped); declared last, so destroyed before the arena that owns the
   // factors they read
@@ -730,6 +731,24 @@ int gram_nmax() {
   }();
   return v;
 }
+
+// Bounded wait of the multi-workgroup QR's per-box barriers (spins of about
+// 0.1 us); the environment variable RSS_MG_SPIN_LIMIT (read once) sets another
+// value (tests force timeouts with a tiny one).
+unsigned mg_spin_limit() {
+  static const unsigned v = [] {
+    const char* e = std::getenv("RSS_MG_SPIN_LIMIT");
+    if (!e || !*e) return 1u << 24;
+    const long x = std::atol(e);
+    return (unsigned)std::max(1L, std::min(x, (long)(1u << 30)));
+  }();
+  return v;
+}
+
+// A per-box barrier of the multi-workgroup QR gave up (other streams kept its
+// workgroups from being resident together); the factorization is redone
+// without that kernel.
+struct MgTimeout {};
 
 // Per-problem state while a batch is being factored.
 struct Work {
@@ -1071,7 +1090,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
     // multi-workgroup ID for colours with few boxes: G workgroups per box
     int Gc[9], Gmax = 1;
     for (int c = 0; c < 9; ++c) {
-      Gc[c] = M[c].box.empty() ? 1 : cpqr_mg_groups<R>((int)M[c].box.size(), nmax, mmax);
+      Gc[c] = (M[c].box.empty() || H[0]->no_mg) ? 1 : cpqr_mg_groups<R>((int)M[c].box.size(), nmax, mmax);
       Gmax = std::max(Gmax, Gc[c] * (int)M[c].box.size());
     }
     double* pnorm = (double*)scr.alloc((size_t)Gmax * nmax * sizeof(double));
@@ -1121,7 +1140,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       } else {
         prof.run(RSS_K_BUILD_C, s, [&] { launch_build_C<R>(d_probs, ph, chunks, s); });
         prof.run(RSS_K_ID, s, [&] {
-          if (Gc[c] < 2 || !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, s))
+          if (Gc[c] < 2 ||
+              !launch_cpqr_mg<R>(d_probs, ph, nmax, mmax, Gc[c], pnorm, pdot, bars, d_err, mg_spin_limit(), s))
             launch_cpqr<R>(d_probs, ph, nmax, mmax, s);
         });
       }
@@ -1450,7 +1470,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   int err = 0;
   HIPCHK(hipMemcpy(&err, d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
-  if (err & ERRF_TIMEOUT) fail(RSS_EHIP, "a per-box device barrier timed out");
+  if (err & ERRF_TIMEOUT) throw MgTimeout{};
   for (int p = 0; p < np; ++p) {
     rss_ctx* h = H[p];
     Work& w = W[p];
@@ -1965,9 +1985,20 @@ int rss_factor_ex(const double* points, int64_t n, const rss_kernel* k, double t
   rss_ctx* h = nullptr;
   const int rc = run([&] {
     if (!out) fail(RSS_EINVAL, "null output handle pointer");
-    h = make_ctx(points, n, k, tol, leaf, opt, nullptr);
-    std::vector<rss_ctx*> H{h};
-    factor_handles(H);
+    for (int attempt = 0;; ++attempt) {
+      h = make_ctx(points, n, k, tol, leaf, opt, nullptr);
+      h->no_mg = attempt > 0;
+      std::vector<rss_ctx*> H{h};
+      try {
+        factor_handles(H);
+        h->stats.id_retries = attempt;
+        break;
+      } catch (const MgTimeout&) {
+        if (attempt > 0) fail(RSS_EHIP, "a per-box device barrier timed out");
+        destroy_ctx(h);
+        h = nullptr;
+      }
+    }
   });
   if (rc != RSS_OK) {
     destroy_ctx(h);
@@ -1984,9 +2015,21 @@ int rss_factor_batch(int nprob, const double* const* points, const int64_t* n,
   const int rc = run([&] {
     if (nprob < 1 || !points || !n || !kernels || !out) fail(RSS_EINVAL, "bad batch arguments");
     for (int p = 0; p < nprob; ++p) out[p] = nullptr;
-    for (int p = 0; p < nprob; ++p)
-      H.push_back(make_ctx(points[p], n[p], &kernels[p], tol, leaf, opt, p ? H[0] : nullptr));
-    factor_handles(H);
+    for (int attempt = 0;; ++attempt) {
+      for (int p = 0; p < nprob; ++p) {
+        H.push_back(make_ctx(points[p], n[p], &kernels[p], tol, leaf, opt, p ? H[0] : nullptr));
+        H.back()->no_mg = attempt > 0;
+      }
+      try {
+        factor_handles(H);
+        for (auto* h : H) h->stats.id_retries = attempt;
+        break;
+      } catch (const MgTimeout&) {
+        if (attempt > 0) fail(RSS_EHIP, "a per-box device barrier timed out");
+        for (auto it = H.rbegin(); it != H.rend(); ++it) destroy_ctx(*it);
+        H.clear();
+      }
+    }
   });
   if (rc != RSS_OK) {
     for (auto* h : H) destroy_ctx(h);

@@ -180,9 +180,10 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax);
 // redundant counts of a level (0: the level's panels do not fit in LDS)
 template <class R>
 int solve_group(int kmax, int rmax, int nrhs);
+// spin_limit bounds each per-box barrier wait (a timeout sets ERRF_TIMEOUT)
 template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
-                    double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s);
+                    double* pnorm, double* pdot, unsigned* bars, int* err, unsigned spin_limit, hipStream_t s);
 // Interpolative decomposition through a double-double Gram matrix (boxes of
 // at most GRAM_NMAX points): partial Gram matrices of row chunks, their sum,
 // and the pivoted Cholesky factorization with T = R11^{-1} R12.

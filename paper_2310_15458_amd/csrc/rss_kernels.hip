@@ -442,8 +442,9 @@ void launch_cpqr(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, h
 // (timeout -> error flag, the kernel still exits).  The launch keeps all
 // G x boxes workgroups co-resident.
 // ---------------------------------------------------------------------------
-// bounded wait: ~seconds, long enough for concurrent work on other streams to drain
-constexpr unsigned MG_SPIN_LIMIT = 1u << 24;
+// bounded wait (the launch's spin limit, ~seconds by default): long enough for
+// concurrent work on other streams to drain; a timeout sets the error flag and
+// the host redoes the factorization with the single-workgroup QR
 
 // LDS of k_cpqr_mg before the staged Householder vector: three double and two
 // int arrays of nmax entries, 16-byte aligned
@@ -454,14 +455,14 @@ __host__ __device__ constexpr size_t mg_head_bytes(int nmax) {
 template <class R>
 constexpr int mg_vcap() { return (int)((48 * 1024) / sizeof(cx<R>)); }
 
-__device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* err) {
+__device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* err, unsigned spin_limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
     atomicAdd(bar, 1u);
     unsigned spins = 0;
     while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++spins > MG_SPIN_LIMIT) {
+      if (++spins > spin_limit) {
         atomicOr(err, ERRF_TIMEOUT);
         break;
       }
@@ -475,7 +476,7 @@ __device__ __forceinline__ void mg_barrier(unsigned* bar, unsigned target, int* 
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> ph, int G, int nmax,
                                                 int vcap, double* pnorm, double* pdot,
-                                                unsigned* bars, int* err) {
+                                                unsigned* bars, int* err, unsigned spin_limit) {
   constexpr int CH = RSS_CPQR_MG_CH, CB = RSS_CPQR_MG_CB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
     if (lane == 0) pn[(size_t)g * nmax + c] = s;
   }
   for (int c = threadIdx.x; c < n; c += NT) perm[c] = c;
-  mg_barrier(bar, (++nbar) * G, err);
+  mg_barrier(bar, (++nbar) * G, err, spin_limit);
   int k = 0;
   const int jmax = m < n ? m : n;
   for (int j = 0; j < jmax; ++j) {
@@ -631,7 +632,7 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
         }
       }
     }
-    mg_barrier(bar, (++nbar) * G, err);
+    mg_barrier(bar, (++nbar) * G, err, spin_limit);
     for (int c = j + 1 + threadIdx.x; c < n; c += NT) {
       const int q = perm[c];
       double sr = 0.0, si = 0.0;
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(NT) void k_cpqr_mg(const Prob<R>* probs, Phase<R> p
     }
     __syncthreads();
     if (threadIdx.x == 0 && j >= r0 && j < r1) C[j + (int64_t)pc * m] = cx<R>{(R)alr, (R)ali};
-    mg_barrier(bar, (++nbar) * G, err);
+    mg_barrier(bar, (++nbar) * G, err, spin_limit);
     k = j + 1;
   }
   // every workgroup leaves the last barrier with the same k and perm; the G
@@ -747,16 +748,15 @@ __global__ void k_fill_u32(unsigned* p, int n) {
 template <class R>
 int cpqr_mg_groups(int nbox, int nmax, int mmax) {
   constexpr int NT = RSS_CPQR_MG_NT;
-  static int cap = -1;
-  if (cap < 0) {
-    int dev = 0, cus = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int per = 0;
-    const size_t shm = mg_head_bytes(nmax) + (size_t)mg_vcap<R>() * sizeof(cx<R>);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cpqr_mg<R, NT>, NT, shm);
-    cap = cus * (per > 0 ? 1 : 0);  // one workgroup per compute unit: always co-resident
-  }
+  // one workgroup per compute unit (co-resident when nothing else runs), if
+  // this call's LDS allows a workgroup at all
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int per = 0;
+  const size_t shm = mg_head_bytes(nmax) + (size_t)mg_vcap<R>() * sizeof(cx<R>);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cpqr_mg<R, NT>, NT, shm);
+  const int cap = cus * (per > 0 ? 1 : 0);
   int G = cap / (nbox > 0 ? nbox : 1);
   G = min(G, max(1, mmax / 128));
   // measured at N=512^2: 8 per box beats 4 for phases of up to 16 boxes
@@ -768,14 +768,14 @@ int cpqr_mg_groups(int nbox, int nmax, int mmax) {
 
 template <class R>
 bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax, int G,
-                    double* pnorm, double* pdot, unsigned* bars, int* err, hipStream_t s) {
+                    double* pnorm, double* pdot, unsigned* bars, int* err, unsigned spin_limit, hipStream_t s) {
   constexpr int NT = RSS_CPQR_MG_NT;
   if (ph.nbox == 0 || G < 2) return false;
   hipLaunchKernelGGL(k_fill_u32, dim3((ph.nbox + 255) / 256), dim3(256), 0, s, bars, ph.nbox);
   const int vcap = std::min(mg_vcap<R>(), (mmax + G - 1) / G);
   const size_t shm = mg_head_bytes(nmax) + (size_t)vcap * sizeof(cx<R>);
   hipLaunchKernelGGL((k_cpqr_mg<R, NT>), dim3(ph.nbox * G), dim3(NT), shm, s, probs, ph, G, nmax,
-                     vcap, pnorm, pdot, bars, err);
+                     vcap, pnorm, pdot, bars, err, spin_limit);
   return true;
 }
 
@@ -2482,7 +2482,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template int solve_group<R>(int, int, int);                                                        \
   template bool solve_fused_fits<R>(int, int, int);                                                  \
   template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*,  \
-                                  unsigned*, int*, hipStream_t);
+                                  unsigned*, int*, unsigned, hipStream_t);
 
 RSS_INST(double)
 RSS_INST(float)

@@ -46,7 +46,7 @@ class rss_stats(ctypes.Structure):
                 ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("last_relres", ctypes.c_double), ("last_iters", ctypes.c_int),
                 ("device_bytes", ctypes.c_double), ("t_class_ms", ctypes.c_double * 12),
-                ("n_class", ctypes.c_int64 * 12)]
+                ("n_class", ctypes.c_int64 * 12), ("id_retries", ctypes.c_int)]
 
 
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",

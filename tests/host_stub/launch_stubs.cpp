@@ -8,7 +8,7 @@ template <class R> void launch_build_C(const Prob<R>*, const Phase<R>&, int, hip
 template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, hipStream_t) {}
 template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
 template <class R> int solve_group(int, int, int nrhs) { return nrhs < 16 ? nrhs : 16; }
-template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t) { return true; }
+template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, unsigned, hipStream_t) { return true; }
 template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 int gram_tile_groups(int nmax) { return nmax > 64 ? 3 : 1; }
 template <class R> void launch_gram(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
@@ -37,7 +37,7 @@ template void launch_chol<R>(const Prob<R>*, const Phase<R>&, const GramWs&, int
 template int cpqr_mg_groups<R>(int, int, int); \
 template int solve_group<R>(int, int, int); \
 template bool solve_fused_fits<R>(int, int, int); \
-template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, hipStream_t); \
+template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, unsigned, hipStream_t); \
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
 template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \

@@ -342,3 +342,58 @@ def test_full_size_fp32_refined(torch_cuda):
     print(f"{w.name}: FP32+refine relres {rr:.3e} (library {info['last_relres']:.3e}, "
           f"{info['last_iters']} steps)", flush=True)
     assert rc == 0 and rr <= 1e-10
+
+
+_HOUSEHOLDER_CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import rss as orss
+from paper_2310_15458_amd import rss, workloads as W
+import torch
+rss.load()
+n, leaf = 48, 9
+P = W.grid_points(n)
+k = W.grid_kernel("laplace", n)
+Fo = orss.factor(P, k, 1e-6, leaf)
+F = rss.Factorization(P, k, 1e-6, leaf)
+bad = 0
+for d in range(Fo.tree.D, 1, -1):
+    got = F.skeletons(d)
+    for (dd, b), sk in Fo.skeletons.items():
+        if dd == d and not np.array_equal(got[b], sk):
+            bad += 1
+B = W.rhs(n * n, 1, 7)
+Bd = torch.from_numpy(B.T.copy()).cuda().t()
+F.apply(Bd)
+x = Bd.cpu().numpy()
+xo = orss.solve(Fo, B)
+print(json.dumps({"bad": bad, "err": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
+                  "retries": F.info()["id_retries"]}))
+"""
+
+
+@pytest.mark.parametrize("spin", [None, "1"])
+def test_householder_id_and_forced_barrier_timeout(torch_cuda, spin):
+    """Boxes above the Gram path's limit take column-pivoted Householder QR,
+    with several workgroups per box in phases with few boxes.  RSS_GRAM_NMAX=0
+    sends every box there; RSS_MG_SPIN_LIMIT=1 makes the multi-workgroup
+    barriers give up at once (forced from the host: every kernel still ends),
+    and the factorization must be redone with the single-workgroup QR and
+    still give the oracle's skeletons and solution."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, RSS_GRAM_NMAX="0")
+    if spin:
+        env["RSS_MG_SPIN_LIMIT"] = spin
+    print(f"child: Householder ID, spin limit {spin}", flush=True)
+    res = subprocess.run([sys.executable, "-c", _HOUSEHOLDER_CHILD, root], env=env, capture_output=True,
+                         text=True, timeout=240)
+    assert res.returncode == 0, res.stderr[-3000:]
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    print(out, flush=True)
+    assert out["bad"] == 0 and out["err"] < 1e-10
+    assert out["retries"] == (1 if spin else 0)

@@ -153,16 +153,19 @@ def batched_sweep(torch, rss, W, reps=2):
             "apply_ms": float(np.median(ta) * 1e3), "apply_unknowns_per_s": tot / float(np.median(ta))}
 
 
-def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
-    """A scaled request stream through the solve server (rss_server_*): the
-    generator and mix of the serving workload (Poisson arrivals, 20% factor
-    jobs, Helmholtz kappa ~ U[10,60], FP32+refine to 1e-10, 200 GB budget, LRU),
-    with fewer requests, sides {128, 256} and nrhs <= 16 so that it runs in
-    seconds (every solve pays O(N^2) FP64 residuals).  The arrival rate is
-    `load` times the capacity measured on one factor and one solve per side.
-    Before that, one solve per side and right-hand-side bucket (1, 2, 4, 8, 16)
-    lets the solve-tile autotuner settle its one-time choices for those level
-    shapes, as a long-running server would have done before this stream."""
+def serving(torch, rss, W, count=300, sides=(128, 256, 512), max_nrhs=256, load=0.7, budget=32e9):
+    """A request stream through the solve server (rss_server_*) with the
+    serving workload's mix and size classes: Poisson arrivals, 20% factor
+    jobs on n x n grids, n in {128, 256, 512}, Helmholtz kappa ~ U[10,60],
+    solves with nrhs ~ U{1..256}, FP32+refine to 1e-10 with the FFT grid
+    residual, LRU eviction.  Fewer requests than the full stream (300) and a
+    32 GB budget (24 GB of resident factorizations, 8 GB of solve buffers)
+    so that it runs in under a minute and the LRU policy evicts.  The
+    right-hand sides are drawn on the device.  The arrival rate is ``load``
+    times the capacity measured on one factor job and one solve of nrhs 128
+    per side.  Before that, one solve per side and right-hand-side bucket
+    lets the solve-tile autotuner settle its one-time choices for those
+    level shapes, as a long-running server would have done."""
     from paper_2310_15458_amd import serve
     t_f, t_s = [], []
     for n in sides:
@@ -171,29 +174,31 @@ def serving(torch, rss, W, count=100, sides=(128, 256), max_nrhs=16, load=0.7):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = rss.Factorization(P, k, 1e-6, 64, precision="fp32")
+        op = rss.GridOperator(k, n)
+        rss.set_residual_op(F, op)
         t1 = time.perf_counter()
         nb = 1
         while nb <= max_nrhs:  # the autotuner's one-time tuning for this side
-            Bw = torch.from_numpy(np.ascontiguousarray(W.rhs(n * n, nb, 6).T)).cuda().t()
-            F.solve(Bw)
+            F.solve(serve.device_normals(torch, 6, n * n, nb))
             nb *= 2
-        Bh = W.rhs(n * n, max_nrhs // 2, 5)
-        B = torch.from_numpy(np.ascontiguousarray(Bh.T)).cuda().t()
+        B = serve.device_normals(torch, 5, n * n, max_nrhs // 2)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         F.solve(B)
         t3 = time.perf_counter()
         F.close()
+        op.close()
         t_f.append(t1 - t0)
         t_s.append(t3 - t2)
     mean_service = 0.2 * float(np.mean(t_f)) + 0.8 * float(np.mean(t_s))
     rate = load / mean_service
     reqs = W.request_stream(count, rate, seed=4, sides=sides, max_nrhs=max_nrhs)
-    res, *_ = serve.run_stream(reqs, 200e9, precision="fp32")
+    res, *_ = serve.run_stream(reqs, budget, precision="fp32", grid_residual=True, device_rhs=True)
     res["rate_per_s"] = rate
     res["stream"] = (f"{count} requests, Poisson rate {rate:.2f}/s (= {load} x measured capacity), "
                      f"sides {list(sides)}, nrhs U{{1..{max_nrhs}}}, 20% factor jobs, seed 4, "
-                     f"FP32+refine to 1e-10, budget 200 GB, solve tiles tuned before the stream")
+                     f"FP32+refine to 1e-10 with the FFT residual, budget {budget / 1e9:.0f} GB, "
+                     f"solve tiles tuned before the stream")
     return res
 
 

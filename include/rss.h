@@ -318,18 +318,19 @@ int rss_set_stream(rss_handle h, void* stream);
 /*
  * rss_set_graphs -- process-wide switch (default on) for the captured solve
  * sweeps of Sec. 2.6: with it on, an apply of a single handle (rss_apply,
- * rss_solve and each refinement step, a server batch of one) replays a HIP
+ * rss_solve and each refinement step) replays a HIP
  * graph of all its launches, captured on the handle's first apply with that
  * nrhs and kept until rss_free (at most 4 per handle, the least recently used
  * dropped; their descriptors and workspace are device memory beyond
  * rss_stats.device_bytes); the vectors are reached through descriptor
  * tables in device memory that each call rewrites before the replay.  Off:
  * every apply launches its kernels directly (the same kernels, same results).
- * Batches of several handles always launch directly.  The capture runs in
- * thread-local mode on the handle's stream (library-created streams are
- * non-blocking); a caller-supplied blocking stream should not meet legacy
- * default-stream work from other threads during a first apply, or graphs
- * should be switched off.  enable: 0 or 1; returns the previous setting.
+ * Batches of several handles, and every apply of the solve server, always
+ * launch directly.  The capture runs in thread-local mode on the handle's
+ * stream, but HIP still rejects some calls (frees among them) made by other
+ * threads while it lasts: a program that calls the library from several
+ * threads at once should switch graphs off (the server needs nothing: it
+ * never captures).  enable: 0 or 1; returns the previous setting.
  */
 int rss_set_graphs(int enable);
 
@@ -359,22 +360,34 @@ int rss_set_autotune(int enable);
 /* ------------------------------------------------------------------------- */
 /* Solve server: factorizations stay resident in device memory; factor and   */
 /* solve requests are served with continuous batching (a factor worker and a */
-/* solve worker on separate streams).                                        */
+/* solve worker on separate streams, so factor and solve work overlap).      */
+/* The solve worker advances every solve in flight by one step at a time --  */
+/* one batched application of the factored inverses (Sec. 2.6) over all of   */
+/* them, then one residual per solve -- admitting newly arrived solves at    */
+/* every step boundary (up to max_batch in flight) and retiring each as soon */
+/* as it has converged.                                                      */
 /* ------------------------------------------------------------------------- */
 typedef struct rss_server* rss_server_t;
 
 typedef struct {
-  double budget_bytes;    /* device memory the resident factorizations may hold; new factor
-                             jobs wait for room, least-recently-used unpinned ones are evicted
-                             (the size of a job is estimated from the largest bytes per
-                             unknown seen so far; an empty server always admits a job) */
+  double budget_bytes;    /* device memory of the server.  Three quarters are for resident
+                             factorizations: new factor jobs wait for room, least-recently-used
+                             unpinned ones are evicted (the size of a job is estimated from the
+                             largest bytes per unknown seen so far; an empty server always
+                             admits a job).  One quarter is for the working buffers of solves
+                             in flight (about 72 bytes per unknown and right-hand side with
+                             refinement in FP32, 64 in FP64): a solve waits until its buffers
+                             fit (a solve alone is always admitted) */
   int precision;          /* rss_precision of every factorization */
   double tol;             /* ID tolerance (Def. 1) */
   int leaf;               /* points per leaf box */
   int n_proxy;            /* 0 -> per-kernel default */
   double refine_tol;      /* as rss_options */
   int max_refine;         /* as rss_options */
-  int max_batch;          /* most solves in one batched sweep; 0 -> 64 */
+  int max_batch;          /* most solves in flight (one batched step); 0 -> 64 */
+  int grid_residual;      /* nonzero: a factorization whose points form a uniform grid of cell
+                             centres (rows of n x n cells, point index iy n + ix) refines with the
+                             FFT grid product (rss_gridop_*) as its residual */
 } rss_server_options;
 
 typedef struct {
@@ -384,13 +397,17 @@ typedef struct {
   double t_submit, t_start, t_end;  /* seconds since the server started */
   double relres;          /* refined solves: max column relative residual; else -1 */
   int iters;              /* refinement steps */
-  int batch;              /* solves in the batched sweep that served it */
+  int batch;              /* solves in flight in the step that completed it */
 } rss_completion;
 
 typedef struct {
+  /* batches: batched steps run; batched_solves: sum over steps of the solves in flight;
+     max_batch_seen: most solves in one step */
   int64_t factored, evictions, batches, batched_solves, max_batch_seen, resident, pending;
-  double used_bytes, peak_bytes;
+  double used_bytes, peak_bytes;   /* resident factorizations: now, and the most */
   double solved_unknowns; /* sum over completed solves of n * nrhs */
+  double inflight_bytes, inflight_peak_bytes;  /* working buffers of solves in flight */
+  int64_t refactors;      /* evicted factorizations factored again for a solve */
 } rss_server_stats;
 
 /* rss_server_create -- start the workers.  Returns RSS_EINVAL on bad options. */
@@ -398,9 +415,12 @@ int rss_server_create(const rss_server_options* o, rss_server_t* out);
 /* rss_server_factor -- queue a factorization (points: host n x 2, copied); *id names it. */
 int rss_server_factor(rss_server_t s, const double* points, int64_t n, const rss_kernel* k,
                       int64_t* id);
-/* rss_server_solve -- queue a solve against factorization id (queued or resident; it is
- * pinned until the solve completes).  B: device complex128 n x nrhs column-major,
- * overwritten with the solution; the caller must not touch it before completion. */
+/* rss_server_solve -- queue a solve against factorization id, pinning it until the solve
+ * completes.  A factorization that was evicted is factored again first (the server keeps
+ * every problem's points and kernel on the host; that factor job reports no completion).
+ * B: device complex128 n x nrhs column-major, overwritten with the solution; the caller
+ * must not touch it before completion.  RSS_EINVAL for an unknown id or one whose
+ * factorization failed. */
 int rss_server_solve(rss_server_t s, int64_t id, void* B, int nrhs, int64_t* req);
 /* rss_server_poll -- take up to cap completions, waiting up to wait_ms for the first. */
 int rss_server_poll(rss_server_t s, rss_completion* out, int cap, int wait_ms, int* count);

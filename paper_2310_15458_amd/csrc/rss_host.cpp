@@ -450,9 +450,12 @@ struct rss_gridop {
       if (p) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
-  // Y = A X (mode 0) or B - A X (mode 1) on stream st; ld = n^2
+  // Y = A X (mode 0) or B - A X (mode 1) on stream st; ld = n^2; columns in
+  // chunks of at most 16 (the work array holds one chunk)
   void apply(const cx<double>* X, const cx<double>* B, cx<double>* Y, int nrhs, int mode, hipStream_t st) {
-    const size_t need = (size_t)nrhs * g.n * g.M;
+    constexpr int CH = 16;
+    const int64_t ld = (int64_t)g.n * g.n;
+    const size_t need = (size_t)std::min(nrhs, CH) * g.n * g.M;
     if (need > work_elems) {
       HIPCHK(hipStreamSynchronize(st));
       if (work) HIPCHK(hipFree(work));
@@ -461,7 +464,12 @@ struct rss_gridop {
       HIPCHK(hipMalloc((void**)&work, need * sizeof(cx<double>)));
       work_elems = need;
     }
-    launch_grid_apply(g, X, B, Y, (int64_t)g.n * g.n, nrhs, work, mode, st);
+    for (int c0 = 0; c0 < nrhs; c0 += CH)
+      launch_grid_apply(g, X + c0 * ld, B ? B + c0 * ld : nullptr, Y + c0 * ld, ld, std::min(CH, nrhs - c0),
+                        work, mode, st);
+  }
+  double device_bytes() const {
+    return (double)g.M * g.M * 16 + (double)g.M * 8 + (double)g.n * g.n * 24 + (double)work_elems * 16;
   }
 };
 
@@ -1468,7 +1476,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   int err = 0;
-  HIPCHK(hipMemcpy(&err, d_err, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
   if (err & ERRF_TIMEOUT) throw MgTimeout{};
   for (int p = 0; p < np; ++p) {
@@ -1821,11 +1830,13 @@ void maybe_autotune(ApplyPlan<R>& plan, const std::vector<rss_ctx*>& H, const st
 // ld N_p), on stream s: one launch per (height, colour) and direction.  A
 // batch of one handle replays that handle's captured graph for this nrhs
 // (captured on first use); a batch of several handles launches its merged
-// plan directly.
+// plan directly, and so do the server's threads: HIP rejects frees and other
+// calls made on one thread while another thread captures, and the server's
+// factor worker runs beside its solve worker.
 template <class R>
 void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
                  const std::vector<int>& nrhs, hipStream_t s) {
-  if (H.size() == 1 && g_use_graphs.load()) {
+  if (H.size() == 1 && g_use_graphs.load() && !g_server_thread) {
     rss_ctx* h = H[0];
     const std::pair<int, int> key{(int)sizeof(R), nrhs[0]};
     auto it = h->graphs.find(key);
@@ -1866,6 +1877,154 @@ void apply_batch(const std::vector<rss_ctx*>& H, const std::vector<cx<R>*>& Z,
   plan.launch(s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));  // scratch descriptors are freed on return
+}
+
+// One refined solve in progress: the refinement of rss_solve
+//   x = F^{-1} b, then x += F^{-1} (b - A x) until max_j ||r_j|| / ||b_j|| <= refine_tol
+// (at most refine_steps corrections), advanced one step at a time, so that a
+// caller (the solve server) can add and retire solves between steps.  Without
+// refinement (refine_steps < 0) a job is one application.  The residual comes
+// from the handle's grid operator (rss_set_residual_op) or the on-the-fly sum.
+struct RefineJob {
+  rss_ctx* h = nullptr;
+  cx<double>* B = nullptr;  // the caller's right-hand sides, the solution on finish
+  int nrhs = 0;
+  Scratch mem;
+  cx<double>*b = nullptr, *x = nullptr, *r = nullptr;
+  cx<double>* xb = nullptr;  // best iterate so far, when it is not the current x
+  double* nrm = nullptr;
+  cx<float>* z = nullptr;
+  std::vector<double> bn, rn;
+  double relres = 1.0;
+  double best = HUGE_VAL;    // relres of the best iterate
+  bool best_is_x = false;    // the best iterate is the current x (else xb)
+  bool refine = true;
+  int it = 0;
+  bool done = false;
+};
+
+RefineJob* refine_begin_impl(rss_ctx* h, void* Bv, int nrhs, hipStream_t s) {
+  std::unique_ptr<RefineJob> j(new RefineJob());
+  j->h = h;
+  j->B = (cx<double>*)Bv;
+  j->nrhs = nrhs;
+  j->refine = h->refine_steps >= 0;
+  const size_t tot = (size_t)h->N * nrhs;
+  j->b = (cx<double>*)j->mem.alloc(tot * sizeof(cx<double>));
+  j->x = (cx<double>*)j->mem.alloc(tot * sizeof(cx<double>));
+  j->r = (cx<double>*)j->mem.alloc(tot * sizeof(cx<double>));
+  j->nrm = (double*)j->mem.alloc((size_t)nrhs * 2 * sizeof(double));
+  j->z = h->precision == RSS_FP32_REFINE ? (cx<float>*)j->mem.alloc(tot * sizeof(cx<float>)) : nullptr;
+  HIPCHK(hipMemcpyAsync(j->b, Bv, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(j->x, 0, tot * sizeof(cx<double>), s));
+  HIPCHK(hipMemcpyAsync(j->r, Bv, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+  j->bn.resize(nrhs);
+  j->rn.resize(nrhs);
+  launch_colnorms(j->b, h->N, nrhs, j->nrm + nrhs, s);
+  HIPCHK(hipMemcpyAsync(j->bn.data(), j->nrm + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h->stats.last_iters = 0;
+  return j.release();
+}
+
+// one step of every job (same precision): the corrections d = F^{-1} r in
+// one batched application, x += d, then r = b - A x (jobs with grid
+// operators by FFT, the others in one on-the-fly launch) and the convergence
+// test; jobs without refinement end after their application
+void refine_step_impl(const std::vector<RefineJob*>& live, hipStream_t s) {
+  if (live.empty()) return;
+  const bool fp32 = live[0]->h->precision == RSS_FP32_REFINE;
+  std::vector<rss_ctx*> LH;
+  std::vector<int> Lnr;
+  for (auto* j : live) {
+    if (j->h->precision != live[0]->h->precision) fail(RSS_EINVAL, "a step must share the precision");
+    LH.push_back(j->h);
+    Lnr.push_back(j->nrhs);
+  }
+  if (fp32) {
+    std::vector<cx<float>*> Z;
+    for (auto* j : live) {
+      launch_colnorms(j->r, j->h->N, j->nrhs, j->nrm, s);
+      launch_scale_to_c64(j->r, j->h->N, j->nrhs, j->nrm, j->z, s);
+      Z.push_back(j->z);
+    }
+    apply_batch<float>(LH, Z, Lnr, s);
+    for (auto* j : live) launch_axpy_from_c64(j->z, j->h->N, j->nrhs, j->nrm, j->x, s);
+  } else {
+    std::vector<cx<double>*> Z;
+    for (auto* j : live) Z.push_back(j->r);
+    apply_batch<double>(LH, Z, Lnr, s);
+    for (auto* j : live) launch_add_c128(j->x, j->r, (int64_t)j->h->N * j->nrhs, s);
+  }
+  std::vector<RefineJob*> res;
+  for (auto* j : live) {
+    if (!j->refine) {
+      j->done = true;
+      j->best_is_x = true;
+      j->relres = -1.0;
+    } else {
+      res.push_back(j);
+    }
+  }
+  if (res.empty()) return;
+  {
+    Scratch rscr;
+    std::vector<ResProblem> rp;
+    for (auto* j : res) {
+      rss_ctx* h = j->h;
+      if (h->gridop) {
+        h->gridop->apply(j->x, j->b, j->r, j->nrhs, 1, s);
+        continue;
+      }
+      if (!h->d_tperm) {
+        const std::vector<int> perm = spatial_order(h->h_points.data(), h->N);
+        h->d_tperm = h->arena.up(perm, s);
+      }
+      rp.push_back({h->kp, h->d_P, h->N, j->x, j->b, j->r, j->nrhs, h->d_tperm});
+    }
+    if (!rp.empty()) residual_batch(rp, rscr, s);
+    for (auto* j : res) {
+      launch_colnorms(j->r, j->h->N, j->nrhs, j->nrm, s);
+      HIPCHK(hipMemcpyAsync(j->rn.data(), j->nrm, j->nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  for (auto* j : res) {
+    j->relres = 0.0;
+    for (int c = 0; c < j->nrhs; ++c)
+      j->relres = std::max(j->relres, j->bn[c] > 0 ? j->rn[c] / j->bn[c] : 0.0);
+    if (j->relres <= j->h->opt.refine_tol || j->it >= j->h->refine_steps) j->done = true;
+    // a NaN relres never counts as an improvement
+    const bool better = j->relres < j->best;
+    if (better) j->best = j->relres;
+    if (better && !j->done) {
+      // x changes in the next step: keep a copy of this iterate
+      const size_t tot = (size_t)j->h->N * j->nrhs;
+      if (!j->xb) j->xb = (cx<double>*)j->mem.alloc(tot * sizeof(cx<double>));
+      HIPCHK(hipMemcpyAsync(j->xb, j->x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+    }
+    j->best_is_x = better;
+    if (!j->done) j->it++;
+  }
+}
+
+// the best iterate to B and the handle's statistics; RSS_ENOCONV when the
+// refinement missed refine_tol
+int refine_finish_impl(RefineJob* j, hipStream_t s) {
+  const size_t tot = (size_t)j->h->N * j->nrhs;
+  // the best iterate: the last one unless refinement stalled or diverged
+  const cx<double>* xo = (j->best_is_x || !j->xb) ? j->x : j->xb;
+  HIPCHK(hipMemcpyAsync(j->B, xo, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));  // the job's buffers are freed with it
+  if (!j->best_is_x && j->xb) j->relres = j->best;
+  j->h->stats.last_relres = j->relres;
+  j->h->stats.last_iters = j->it;
+  if (j->refine && !(j->relres <= j->h->opt.refine_tol)) {
+    g_err = "refinement did not reach refine_tol";
+    return RSS_ENOCONV;
+  }
+  return RSS_OK;
 }
 
 int run(const std::function<void()>& f) {
@@ -1976,6 +2135,41 @@ void factor_handles(std::vector<rss_ctx*>& H) {
 }
 
 }  // namespace
+
+// The refinement steps for the solve server (rss_server.cpp): status codes in
+// place of exceptions, jobs as opaque pointers.
+namespace rss {
+int refine_begin(rss_handle h, void* B, int nrhs, void** job) {
+  *job = nullptr;
+  return run([&] {
+    if (!h || !B || nrhs < 1) fail(RSS_EINVAL, "bad solve arguments");
+    *job = refine_begin_impl(h, B, nrhs, h->stream);
+  });
+}
+int refine_step(void* const* jobs, int n) {
+  if (n < 1) return RSS_OK;
+  return run([&] {
+    std::vector<RefineJob*> live;
+    for (int i = 0; i < n; ++i) live.push_back((RefineJob*)jobs[i]);
+    refine_step_impl(live, live[0]->h->stream);
+  });
+}
+bool refine_done(const void* job) { return ((const RefineJob*)job)->done; }
+int refine_finish(void* job, double* relres, int* iters) {
+  RefineJob* j = (RefineJob*)job;
+  int code = RSS_OK;
+  const int rc = run([&] { code = refine_finish_impl(j, j->h->stream); });
+  if (relres) *relres = j->relres;
+  if (iters) *iters = j->it;
+  delete j;
+  return rc != RSS_OK ? rc : code;
+}
+void refine_free(void* job) {
+  RefineJob* j = (RefineJob*)job;
+  if (j && j->h) (void)hipStreamSynchronize(j->h->stream);
+  delete j;
+}
+}  // namespace rss
 
 extern "C" {
 
@@ -2123,122 +2317,19 @@ int rss_solve_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
       }
       for (auto* h : H) h->stats.last_relres = -1.0;
     } else {
-      // x = F^{-1} b, then x += F^{-1} (b - A x) with the FP64 on-the-fly residual,
-      // each problem until max_j ||r_j|| / ||b_j|| <= its refine_tol
-      struct St {
-        cx<double>*b, *x, *r;
-        cx<double>* xb = nullptr;  // best iterate so far, when it is not the current x
-        double* nrm;
-        cx<float>* z;
-        std::vector<double> bn, rn;
-        double relres = 1.0;
-        double best = HUGE_VAL;    // relres of the best iterate
-        bool best_is_x = false;    // the best iterate is the current x (else xb)
-        int it = 0;
-        bool done = false;
-      };
-      std::vector<St> st(nh);
-      for (int p = 0; p < nh; ++p) {
-        const size_t tot = (size_t)H[p]->N * nr[p];
-        St& q = st[p];
-        q.b = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
-        q.x = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
-        q.r = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
-        q.nrm = (double*)scr.alloc((size_t)nr[p] * 2 * sizeof(double));
-        q.z = fp32 ? (cx<float>*)scr.alloc(tot * sizeof(cx<float>)) : nullptr;
-        HIPCHK(hipMemcpyAsync(q.b, B[p], tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemsetAsync(q.x, 0, tot * sizeof(cx<double>), s));
-        HIPCHK(hipMemcpyAsync(q.r, B[p], tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-        q.bn.resize(nr[p]);
-        q.rn.resize(nr[p]);
-        launch_colnorms(q.b, H[p]->N, nr[p], q.nrm + nr[p], s);
-        HIPCHK(hipMemcpyAsync(q.bn.data(), q.nrm + nr[p], nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
-      }
-      HIPCHK(hipStreamSynchronize(s));
-      Scratch rscr;  // residual partial sums, reused every iteration
+      // x = F^{-1} b, then x += F^{-1} (b - A x) with the FP64 residual, each
+      // problem until max_j ||r_j|| / ||b_j|| <= its refine_tol
+      std::vector<std::unique_ptr<RefineJob>> jobs;
+      for (int p = 0; p < nh; ++p) jobs.emplace_back(refine_begin_impl(H[p], B[p], nr[p], s));
       for (;;) {
-        std::vector<int> live;
-        for (int p = 0; p < nh; ++p)
-          if (!st[p].done) live.push_back(p);
+        std::vector<RefineJob*> live;
+        for (auto& j : jobs)
+          if (!j->done) live.push_back(j.get());
         if (live.empty()) break;
-        std::vector<rss_ctx*> LH;
-        std::vector<int> Lnr;
-        for (int p : live) {
-          LH.push_back(H[p]);
-          Lnr.push_back(nr[p]);
-        }
-        // corrections d = F^{-1} r for every live problem in one batched sweep
-        if (fp32) {
-          std::vector<cx<float>*> Z;
-          for (int p : live) {
-            launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
-            launch_scale_to_c64(st[p].r, H[p]->N, nr[p], st[p].nrm, st[p].z, s);
-            Z.push_back(st[p].z);
-          }
-          apply_batch<float>(LH, Z, Lnr, s);
-          for (int p : live) launch_axpy_from_c64(st[p].z, H[p]->N, nr[p], st[p].nrm, st[p].x, s);
-        } else {
-          std::vector<cx<double>*> Z;
-          for (int p : live) Z.push_back(st[p].r);
-          apply_batch<double>(LH, Z, Lnr, s);
-          for (int p : live) launch_add_c128(st[p].x, st[p].r, (int64_t)H[p]->N * nr[p], s);
-        }
-        // residuals r = b - A x in FP64: by FFT for handles with a grid
-        // operator (rss_set_residual_op), else on the fly, every such live
-        // problem in one launch
-        {
-          std::vector<ResProblem> rp;
-          for (int p : live) {
-            if (H[p]->gridop) {
-              H[p]->gridop->apply(st[p].x, st[p].b, st[p].r, nr[p], 1, s);
-              continue;
-            }
-            if (!H[p]->d_tperm) {
-              const std::vector<int> perm = spatial_order(H[p]->h_points.data(), H[p]->N);
-              H[p]->d_tperm = H[p]->arena.up(perm, s);
-            }
-            rp.push_back({H[p]->kp, H[p]->d_P, H[p]->N, st[p].x, st[p].b, st[p].r, nr[p], H[p]->d_tperm});
-          }
-          if (!rp.empty()) residual_batch(rp, rscr, s);
-        }
-        for (int p : live) {
-          launch_colnorms(st[p].r, H[p]->N, nr[p], st[p].nrm, s);
-          HIPCHK(hipMemcpyAsync(st[p].rn.data(), st[p].nrm, nr[p] * sizeof(double), hipMemcpyDeviceToHost, s));
-        }
-        HIPCHK(hipStreamSynchronize(s));
-        rscr.clear();
-        for (int p : live) {
-          St& q = st[p];
-          q.relres = 0.0;
-          for (int j = 0; j < nr[p]; ++j) q.relres = std::max(q.relres, q.bn[j] > 0 ? q.rn[j] / q.bn[j] : 0.0);
-          if (q.relres <= H[p]->opt.refine_tol || q.it >= H[p]->refine_steps) q.done = true;
-          // a NaN relres never counts as an improvement
-          const bool better = q.relres < q.best;
-          if (better) q.best = q.relres;
-          if (better && !q.done) {
-            // x changes in the next step: keep a copy of this iterate
-            const size_t tot = (size_t)H[p]->N * nr[p];
-            if (!q.xb) q.xb = (cx<double>*)scr.alloc(tot * sizeof(cx<double>));
-            HIPCHK(hipMemcpyAsync(q.xb, q.x, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-          }
-          q.best_is_x = better;
-          if (!q.done) q.it++;
-        }
+        refine_step_impl(live, s);
       }
-      for (int p = 0; p < nh; ++p) {
-        const size_t tot = (size_t)H[p]->N * nr[p];
-        St& q = st[p];
-        // the best iterate: the last one unless refinement stalled or diverged
-        const cx<double>* xo = (q.best_is_x || !q.xb) ? q.x : q.xb;
-        HIPCHK(hipMemcpyAsync(B[p], xo, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-        if (!q.best_is_x && q.xb) q.relres = q.best;
-        H[p]->stats.last_relres = st[p].relres;
-        H[p]->stats.last_iters = st[p].it;
-        if (!(st[p].relres <= H[p]->opt.refine_tol)) {
-          g_err = "refinement did not reach refine_tol";
-          code = RSS_ENOCONV;
-        }
-      }
+      for (auto& j : jobs)
+        if (refine_finish_impl(j.get(), s) != RSS_OK) code = RSS_ENOCONV;
     }
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));

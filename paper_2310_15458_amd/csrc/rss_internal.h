@@ -8,6 +8,8 @@
 
 #include "rss_device.h"
 
+struct rss_ctx;  // a factorization handle (the C ABI's rss_handle)
+
 namespace rss {
 
 // One depth of the quadtree during factorization.
@@ -321,6 +323,16 @@ void launch_caxpby(const cx<double>* X, cx<double>* Y, int64_t N, int nrhs, cons
 void launch_lincomb_sub(const cx<double>* V, int64_t vstride, int k, const cx<double>* h, cx<double>* Y,
                         int64_t N, int nrhs, hipStream_t s);
 constexpr int KRYLOV_DOT_BLOCKS = 64;
+
+// refined solves a step at a time (the solve server's continuous batching):
+// begin copies the right-hand sides; one step of several jobs (one precision)
+// runs one batched application and one residual for all; finish writes the
+// best iterate back, fills relres / iterations and frees the job
+int refine_begin(::rss_ctx* h, void* B, int nrhs, void** job);
+int refine_step(void* const* jobs, int n);
+bool refine_done(const void* job);
+int refine_finish(void* job, double* relres, int* iters);
+void refine_free(void* job);
 
 // set on the solve server's worker threads: batches of several handles there
 // reuse tuned solve tiles but do not tune (see rss_set_autotune)

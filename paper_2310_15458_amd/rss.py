@@ -65,7 +65,7 @@ class rss_krylov_stats(ctypes.Structure):
 class rss_server_options(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_double), ("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("leaf", ctypes.c_int), ("n_proxy", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("max_refine", ctypes.c_int), ("max_batch", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("max_batch", ctypes.c_int), ("grid_residual", ctypes.c_int)]
 
 
 class rss_completion(ctypes.Structure):
@@ -78,7 +78,9 @@ class rss_server_stats(ctypes.Structure):
     _fields_ = [("factored", ctypes.c_int64), ("evictions", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("batched_solves", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64),
                 ("resident", ctypes.c_int64), ("pending", ctypes.c_int64), ("used_bytes", ctypes.c_double),
-                ("peak_bytes", ctypes.c_double), ("solved_unknowns", ctypes.c_double)]
+                ("peak_bytes", ctypes.c_double), ("solved_unknowns", ctypes.c_double),
+                ("inflight_bytes", ctypes.c_double), ("inflight_peak_bytes", ctypes.c_double),
+                ("refactors", ctypes.c_int64)]
 
 _lib = None
 
@@ -451,11 +453,12 @@ class Server:
     continuous batching of solves, device-memory budget with LRU eviction."""
 
     def __init__(self, budget_bytes: float, precision: str = "fp32", tol: float = 1e-6, leaf: int = 64,
-                 n_proxy: int = 0, refine_tol: float = 0.0, max_refine: int = 0, max_batch: int = 64):
+                 n_proxy: int = 0, refine_tol: float = 0.0, max_refine: int = 0, max_batch: int = 64,
+                 grid_residual: bool = False):
         o = rss_server_options(float(budget_bytes),
                                RSS_FP32_REFINE if precision in ("fp32", "fp32_refine") else RSS_FP64,
                                float(tol), int(leaf), int(n_proxy), float(refine_tol), int(max_refine),
-                               int(max_batch))
+                               int(max_batch), 1 if grid_residual else 0)
         h = ctypes.c_void_p()
         _check(load().rss_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._s = h

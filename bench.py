@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -121,6 +122,51 @@ def paper_matrices(torch, rss, W, n=512, eps=1e-6):
         op.close()
         F.close()
     return out
+
+
+def _ls_case(torch, rss, W, n, kappa, eps, unprec_maxit=0):
+    """One LS Helmholtz problem (eqs. e:b1, e:b2) at N = n^2: FP64
+    factorization (timed after a warm-up factorization of the same size), the
+    relres of one application, GMRES preconditioned by it to 1e-12 (n_it), and
+    optionally GMRES(20) without a preconditioner (Tab. t:h2's last column)."""
+    P = W.grid_points(n)
+    kern = W.paper_helmholtz(n, kappa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = rss.Factorization(P, kern, eps, 64)
+    t_fact = time.perf_counter() - t0
+    info = F.info()
+    op = rss.GridOperator(kern, n)
+    b = W.uniform_rhs(n * n, 1, 0)
+    B = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()
+    x1 = B.clone()
+    F.apply(x1)
+    relres1 = float(torch.linalg.norm(op.residual(x1, B)) / torch.linalg.norm(B))
+    X = B.clone()
+    st = rss.krylov(F, op, X, method="gmres", tol=1e-12, maxit=100)
+    out = {"N": n * n, "kappa": kappa, "eps": eps, "t_factor_ms": t_fact * 1e3,
+           "ranks": [round(a / c, 1) for a, c in zip(info["rank_sum"], info["box_count"]) if c],
+           "device_GB": info["device_bytes"] / 1e9, "relres_one_apply": relres1,
+           "n_it": st["iters"], "relres": st["relres"], "t_solve_ms": st["t_ms"]}
+    F.close()
+    if unprec_maxit:
+        X = B.clone()
+        s0 = rss.krylov(None, op, X, method="gmres", tol=1e-12, maxit=unprec_maxit, restart=20)
+        out.update({"n_it_unpreconditioned": s0["iters"], "relres_unpreconditioned": s0["relres"],
+                    "t_unpreconditioned_ms": s0["t_ms"]})
+    op.close()
+    return out
+
+
+def tolerance_and_frequency(torch, rss, W):
+    """Tab. t:cpp's tolerance sweep (LS Helmholtz kappa = 25, eps 1e-3 ...
+    1e-12) at N = 512^2, and Tab. t:h2's rising frequency kappa = pi sqrt(N) / 16
+    (32 points per wavelength) at N = 256^2, 512^2, 1024^2 with eps = 1e-6,
+    including the GMRES(20) count without a preconditioner."""
+    _ls_case(torch, rss, W, 512, 25.0, 1e-6)  # warm-up: module load, first-use tuning
+    sweep = [_ls_case(torch, rss, W, 512, 25.0, eps) for eps in (1e-3, 1e-6, 1e-9, 1e-12)]
+    freq = [_ls_case(torch, rss, W, n, math.pi * n / 16, 1e-6, unprec_maxit=3000) for n in (256, 512, 1024)]
+    return {"tolerance_sweep_ls_k25_n512": sweep, "rising_frequency_eps1e-6": freq}
 
 
 def batched_sweep(torch, rss, W, reps=2):
@@ -424,6 +470,7 @@ def main():
     out["batched"] = batched_sweep(torch, rss, W)
     if not args.no_paper:
         out["paper_matrices"] = paper_matrices(torch, rss, W)
+        out["tolerance_and_frequency"] = tolerance_and_frequency(torch, rss, W)
     if not args.no_serving:
         out["serving"] = serving(torch, rss, W)
     if not args.no_cpu_baseline:

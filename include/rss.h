@@ -310,6 +310,18 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* B, int nrhs, int method, doub
                rss_krylov_stats* st);
 
 /*
+ * rss_krylov_ex -- rss_krylov with restarts and an optional preconditioner:
+ * restart m > 0 runs GMRES(m) (each cycle of at most m steps starts again
+ * from the true residual b - A x; m = 0: no restart; ignored by CG); h may
+ * be NULL for the unpreconditioned iteration (Tab. t:h2 counts GMRES(20)
+ * iterations without a preconditioner), the work then runs on `stream` (a
+ * hipStream_t; NULL: the grid operator's stream).  maxit bounds the total
+ * number of iterations over all cycles.
+ */
+int rss_krylov_ex(rss_handle h, rss_gridop_t A, void* B, int nrhs, int method, double tol, int maxit,
+                  int restart, void* stream, rss_krylov_stats* st);
+
+/*
  * rss_set_stream -- move a handle's later work to another stream (hipStream_t;
  * NULL is not allowed).  The caller orders it after work already queued.
  */

@@ -2466,19 +2466,19 @@ cx<double>* up_scalars(const std::vector<std::complex<double>>& v, cx<double>* d
 }
 }  // namespace
 
-int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, double tol, int maxit,
-               rss_krylov_stats* st) {
+int rss_krylov_ex(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, double tol, int maxit,
+                  int restart, void* stream, rss_krylov_stats* st) {
   return run([&] {
-    if (!h || !A || !Bv) fail(RSS_EINVAL, "null argument");
-    if (nrhs < 1 || maxit < 1 || !(tol > 0) || (method != 0 && method != 1))
+    if (!A || !Bv) fail(RSS_EINVAL, "null argument");
+    if (nrhs < 1 || maxit < 1 || !(tol > 0) || (method != 0 && method != 1) || restart < 0)
       fail(RSS_EINVAL, "bad Krylov arguments");
-    if ((int64_t)A->g.n * A->g.n != h->N) fail(RSS_EINVAL, "the grid operator has another size");
-    const hipStream_t s = h->stream;
+    const int64_t N = (int64_t)A->g.n * A->g.n;
+    if (h && h->N != N) fail(RSS_EINVAL, "the grid operator has another size");
+    const hipStream_t s = h ? h->stream : (stream ? (hipStream_t)stream : A->stream);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    const int64_t N = h->N;
     const size_t tot = (size_t)N * nrhs, vb = tot * sizeof(cx<double>);
     cx<double>* B = (cx<double>*)Bv;
     Scratch scr;
@@ -2486,11 +2486,18 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, dou
     cx<double>* x = (cx<double>*)scr.alloc(vb);
     cx<double>* z = (cx<double>*)scr.alloc(vb);
     cx<double>* q = (cx<double>*)scr.alloc(vb);
-    cx<float>* zc = h->precision == RSS_FP64 ? nullptr : (cx<float>*)scr.alloc(tot * sizeof(cx<float>));
+    cx<float>* zc = (h && h->precision != RSS_FP64) ? (cx<float>*)scr.alloc(tot * sizeof(cx<float>)) : nullptr;
     cx<double>* part = (cx<double>*)scr.alloc((size_t)KRYLOV_DOT_BLOCKS * nrhs * sizeof(cx<double>));
     cx<double>* dout = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
     cx<double>* sa = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
     cx<double>* sb = (cx<double>*)scr.alloc((size_t)nrhs * sizeof(cx<double>));
+    // z = M^{-1} r: the factorization, or the identity without one
+    auto precond = [&](const cx<double>* r, cx<double>* out) {
+      if (h)
+        precond_apply(h, r, out, nrhs, zc, s);
+      else
+        HIPCHK(hipMemcpyAsync(out, r, vb, hipMemcpyDeviceToDevice, s));
+    };
     HIPCHK(hipMemcpyAsync(b, B, vb, hipMemcpyDeviceToDevice, s));
     std::vector<double> bn(nrhs);
     {
@@ -2498,13 +2505,13 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, dou
       for (int c = 0; c < nrhs; ++c) bn[c] = std::sqrt(std::max(0.0, d[c].real()));
     }
     int iters = 0;
+    HIPCHK(hipMemsetAsync(x, 0, vb, s));
     if (method == 0) {
       // preconditioned conjugate gradients, the columns in lock step
       cx<double>* r = (cx<double>*)scr.alloc(vb);
       cx<double>* pv = (cx<double>*)scr.alloc(vb);
-      HIPCHK(hipMemsetAsync(x, 0, vb, s));
       HIPCHK(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, s));
-      precond_apply(h, r, z, nrhs, zc, s);
+      precond(r, z);
       HIPCHK(hipMemcpyAsync(pv, z, vb, hipMemcpyDeviceToDevice, s));
       std::vector<std::complex<double>> rz = coldots(r, z, N, nrhs, part, dout, s);
       std::vector<char> act(nrhs, 1);
@@ -2526,7 +2533,7 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, dou
         for (int c = 0; c < nrhs; ++c)
           if (act[c] && std::sqrt(std::max(0.0, rr[c].real())) <= tol * bn[c]) act[c] = 0;
         if (std::find(act.begin(), act.end(), 1) == act.end()) break;
-        precond_apply(h, r, z, nrhs, zc, s);
+        precond(r, z);
         const auto rzn = coldots(r, z, N, nrhs, part, dout, s);
         std::vector<std::complex<double>> be(nrhs);
         for (int c = 0; c < nrhs; ++c) be[c] = act[c] && std::abs(rz[c]) > 0 ? rzn[c] / rz[c] : 0.0;
@@ -2534,92 +2541,113 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, dou
         rz = rzn;
       }
     } else {
-      // right-preconditioned GMRES (no restart), Arnoldi by classical
-      // Gram-Schmidt applied twice, the columns in lock step
+      // right-preconditioned GMRES(m), m = restart (0: no restart), Arnoldi by
+      // classical Gram-Schmidt applied twice, the columns in lock step; each
+      // cycle starts from the true residual r = b - A x
+      const int m = restart > 0 ? std::min(restart, maxit) : maxit;
       const int64_t vstride = (int64_t)tot;
-      cx<double>* V = (cx<double>*)scr.alloc((size_t)(maxit + 1) * vb);
-      cx<double>* hcoef = (cx<double>*)scr.alloc((size_t)(maxit + 1) * nrhs * sizeof(cx<double>));
+      cx<double>* V = (cx<double>*)scr.alloc((size_t)(m + 1) * vb);
+      cx<double>* hcoef = (cx<double>*)scr.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
       using C = std::complex<double>;
-      std::vector<std::vector<C>> H((size_t)nrhs, std::vector<C>((size_t)(maxit + 1) * maxit, 0.0));
-      std::vector<std::vector<C>> cs(nrhs, std::vector<C>(maxit)), sn(nrhs, std::vector<C>(maxit));
-      std::vector<std::vector<C>> gg(nrhs, std::vector<C>(maxit + 1, 0.0));
-      std::vector<int> kc(nrhs, 0);  // Arnoldi steps that count for each column
       std::vector<char> act(nrhs, 1);
-      auto Hat = [&](int c, int i, int j) -> C& { return H[c][(size_t)j * (maxit + 1) + i]; };
-      HIPCHK(hipMemsetAsync(V, 0, vb, s));
-      {
-        std::vector<C> inv(nrhs);
-        for (int c = 0; c < nrhs; ++c) {
-          inv[c] = bn[c] > 0 ? 1.0 / bn[c] : 0.0;
-          gg[c][0] = bn[c];
-          if (!(bn[c] > 0)) act[c] = 0;
+      for (int c = 0; c < nrhs; ++c)
+        if (!(bn[c] > 0)) act[c] = 0;
+      std::vector<double> rn = bn;  // residual norms at the start of the cycle
+      HIPCHK(hipMemcpyAsync(V, b, vb, hipMemcpyDeviceToDevice, s));  // r_0 = b (x_0 = 0)
+      while (iters < maxit && std::find(act.begin(), act.end(), 1) != act.end()) {
+        const int mc = std::min(m, maxit - iters);
+        std::vector<std::vector<C>> H((size_t)nrhs, std::vector<C>((size_t)(mc + 1) * mc, 0.0));
+        std::vector<std::vector<C>> cs(nrhs, std::vector<C>(mc)), sn(nrhs, std::vector<C>(mc));
+        std::vector<std::vector<C>> gg(nrhs, std::vector<C>(mc + 1, 0.0));
+        std::vector<int> kc(nrhs, 0);  // Arnoldi steps of this cycle that count for each column
+        std::vector<char> run_c = act;
+        auto Hat = [&](int c, int i, int j) -> C& { return H[c][(size_t)j * (mc + 1) + i]; };
+        {
+          std::vector<C> inv(nrhs);
+          for (int c = 0; c < nrhs; ++c) {
+            inv[c] = run_c[c] && rn[c] > 0 ? 1.0 / rn[c] : 0.0;
+            gg[c][0] = rn[c];
+          }
+          // V_0 = r / ||r|| (V_0 holds r on entry)
+          launch_caxpby(V, V, N, nrhs, up_scalars(inv, sa, s), up_scalars(std::vector<C>(nrhs, 0.0), sb, s), s);
         }
-        launch_caxpby(b, V, N, nrhs, up_scalars(inv, sa, s), nullptr, s);
-      }
-      for (int k = 0; k < maxit; ++k) {
-        if (std::find(act.begin(), act.end(), 1) == act.end()) break;
-        cx<double>* w = V + (size_t)(k + 1) * vstride;
-        precond_apply(h, V + (size_t)k * vstride, z, nrhs, zc, s);
-        A->apply(z, nullptr, w, nrhs, 0, s);
-        for (int pass = 0; pass < 2; ++pass) {
-          std::vector<C> hv((size_t)(k + 1) * nrhs);
-          for (int j = 0; j <= k; ++j) {
-            const auto d = coldots(V + (size_t)j * vstride, w, N, nrhs, part, dout, s);
-            for (int c = 0; c < nrhs; ++c) {
-              hv[(size_t)j * nrhs + c] = d[c];
-              Hat(c, j, k) += d[c];
+        for (int k = 0; k < mc; ++k) {
+          if (std::find(run_c.begin(), run_c.end(), 1) == run_c.end()) break;
+          cx<double>* w = V + (size_t)(k + 1) * vstride;
+          precond(V + (size_t)k * vstride, z);
+          A->apply(z, nullptr, w, nrhs, 0, s);
+          for (int pass = 0; pass < 2; ++pass) {
+            std::vector<C> hv((size_t)(k + 1) * nrhs);
+            for (int j = 0; j <= k; ++j) {
+              const auto d = coldots(V + (size_t)j * vstride, w, N, nrhs, part, dout, s);
+              for (int c = 0; c < nrhs; ++c) {
+                hv[(size_t)j * nrhs + c] = d[c];
+                Hat(c, j, k) += d[c];
+              }
             }
+            HIPCHK(hipMemcpyAsync(hcoef, hv.data(), hv.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+            launch_lincomb_sub(V, vstride, k + 1, hcoef, w, N, nrhs, s);
           }
-          HIPCHK(hipMemcpyAsync(hcoef, hv.data(), hv.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
-          launch_lincomb_sub(V, vstride, k + 1, hcoef, w, N, nrhs, s);
-        }
-        const auto ww = coldots(w, w, N, nrhs, part, dout, s);
-        std::vector<C> inv(nrhs);
-        for (int c = 0; c < nrhs; ++c) {
-          const double hn = std::sqrt(std::max(0.0, ww[c].real()));
-          Hat(c, k + 1, k) = hn;
-          inv[c] = hn > 0 ? 1.0 / hn : 0.0;
-        }
-        launch_caxpby(w, w, N, nrhs, up_scalars(inv, sa, s), up_scalars(std::vector<C>(nrhs, 0.0), sb, s), s);
-        iters = k + 1;
-        for (int c = 0; c < nrhs; ++c) {
-          if (!act[c]) continue;
-          // rotations G_i = [[conj(c_i), conj(s_i)], [-s_i, c_i]] (unitary)
-          for (int i = 0; i < k; ++i) {
-            const C t = std::conj(cs[c][i]) * Hat(c, i, k) + std::conj(sn[c][i]) * Hat(c, i + 1, k);
-            Hat(c, i + 1, k) = -sn[c][i] * Hat(c, i, k) + cs[c][i] * Hat(c, i + 1, k);
-            Hat(c, i, k) = t;
+          const auto ww = coldots(w, w, N, nrhs, part, dout, s);
+          std::vector<C> inv(nrhs);
+          for (int c = 0; c < nrhs; ++c) {
+            const double hn = std::sqrt(std::max(0.0, ww[c].real()));
+            Hat(c, k + 1, k) = hn;
+            inv[c] = hn > 0 ? 1.0 / hn : 0.0;
           }
-          const C a = Hat(c, k, k), cc = Hat(c, k + 1, k);
-          const double den = std::sqrt(std::norm(a) + std::norm(cc));
-          cs[c][k] = den > 0 ? a / den : C(1.0);
-          sn[c][k] = den > 0 ? cc / den : C(0.0);
-          Hat(c, k, k) = den;
-          Hat(c, k + 1, k) = 0.0;
-          gg[c][k + 1] = -sn[c][k] * gg[c][k];
-          gg[c][k] = std::conj(cs[c][k]) * gg[c][k];
-          kc[c] = k + 1;
-          if (std::abs(gg[c][k + 1]) <= tol * bn[c] || std::abs(ww[c]) == 0.0) act[c] = 0;
+          launch_caxpby(w, w, N, nrhs, up_scalars(inv, sa, s), up_scalars(std::vector<C>(nrhs, 0.0), sb, s), s);
+          iters++;
+          for (int c = 0; c < nrhs; ++c) {
+            if (!run_c[c]) continue;
+            // rotations G_i = [[conj(c_i), conj(s_i)], [-s_i, c_i]] (unitary)
+            for (int i = 0; i < k; ++i) {
+              const C t = std::conj(cs[c][i]) * Hat(c, i, k) + std::conj(sn[c][i]) * Hat(c, i + 1, k);
+              Hat(c, i + 1, k) = -sn[c][i] * Hat(c, i, k) + cs[c][i] * Hat(c, i + 1, k);
+              Hat(c, i, k) = t;
+            }
+            const C a = Hat(c, k, k), cc = Hat(c, k + 1, k);
+            const double den = std::sqrt(std::norm(a) + std::norm(cc));
+            cs[c][k] = den > 0 ? a / den : C(1.0);
+            sn[c][k] = den > 0 ? cc / den : C(0.0);
+            Hat(c, k, k) = den;
+            Hat(c, k + 1, k) = 0.0;
+            gg[c][k + 1] = -sn[c][k] * gg[c][k];
+            gg[c][k] = std::conj(cs[c][k]) * gg[c][k];
+            kc[c] = k + 1;
+            if (std::abs(gg[c][k + 1]) <= tol * bn[c] || std::abs(ww[c]) == 0.0) run_c[c] = 0;
+          }
         }
-      }
-      // y = R^{-1} g per column, u = sum_j y_j V_j, x = F^{-1} u
-      std::vector<C> ycoef((size_t)(maxit + 1) * nrhs, 0.0);
-      int kmax = 0;
-      for (int c = 0; c < nrhs; ++c) {
-        const int m = kc[c];
-        kmax = std::max(kmax, m);
-        std::vector<C> y(m);
-        for (int i = m - 1; i >= 0; --i) {
-          C acc = gg[c][i];
-          for (int j = i + 1; j < m; ++j) acc -= Hat(c, i, j) * y[j];
-          y[i] = acc / Hat(c, i, i);
+        // y = R^{-1} g per column, u = sum_j y_j V_j, x += M^{-1} u
+        std::vector<C> ycoef((size_t)(mc + 1) * nrhs, 0.0);
+        int kmax = 0;
+        for (int c = 0; c < nrhs; ++c) {
+          const int mm = kc[c];
+          kmax = std::max(kmax, mm);
+          std::vector<C> y(mm);
+          for (int i = mm - 1; i >= 0; --i) {
+            C acc = gg[c][i];
+            for (int j = i + 1; j < mm; ++j) acc -= Hat(c, i, j) * y[j];
+            y[i] = acc / Hat(c, i, i);
+          }
+          for (int i = 0; i < mm; ++i) ycoef[(size_t)i * nrhs + c] = -y[i];
         }
-        for (int i = 0; i < m; ++i) ycoef[(size_t)i * nrhs + c] = -y[i];
+        if (kmax > 0) {
+          HIPCHK(hipMemsetAsync(q, 0, vb, s));
+          HIPCHK(hipMemcpyAsync(hcoef, ycoef.data(), (size_t)kmax * nrhs * sizeof(cx<double>),
+                                hipMemcpyHostToDevice, s));
+          launch_lincomb_sub(V, vstride, kmax, hcoef, q, N, nrhs, s);
+          precond(q, z);
+          launch_add_c128(x, z, (int64_t)tot, s);
+        }
+        // the next cycle's residual, and which columns still iterate
+        A->apply(x, b, V, nrhs, 1, s);
+        const auto rr = coldots(V, V, N, nrhs, part, dout, s);
+        for (int c = 0; c < nrhs; ++c) {
+          rn[c] = std::sqrt(std::max(0.0, rr[c].real()));
+          if (act[c] && rn[c] <= tol * bn[c]) act[c] = 0;
+        }
+        if (kmax == 0) break;  // no progress possible (breakdown in every column)
       }
-      HIPCHK(hipMemsetAsync(q, 0, vb, s));
-      HIPCHK(hipMemcpyAsync(hcoef, ycoef.data(), (size_t)kmax * nrhs * sizeof(cx<double>), hipMemcpyHostToDevice, s));
-      launch_lincomb_sub(V, vstride, kmax, hcoef, q, N, nrhs, s);
-      precond_apply(h, q, x, nrhs, zc, s);
     }
     // the true relative residual of the result
     A->apply(x, b, q, nrhs, 1, s);
@@ -2640,6 +2668,15 @@ int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, dou
       st->t_ms = ms;
     }
   });
+}
+
+int rss_krylov(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, double tol, int maxit,
+               rss_krylov_stats* st) {
+  if (!h) {
+    g_err = "null handle";
+    return RSS_EINVAL;
+  }
+  return rss_krylov_ex(h, A, Bv, nrhs, method, tol, maxit, 0, nullptr, st);
 }
 
 void rss_free(rss_handle h) { destroy_ctx(h); }

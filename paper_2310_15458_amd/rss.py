@@ -52,7 +52,7 @@ class rss_stats(ctypes.Structure):
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
            "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
            "rss_residual_static", "rss_gridop_create", "rss_gridop_apply", "rss_gridop_residual",
-           "rss_gridop_free", "rss_set_residual_op", "rss_krylov",
+           "rss_gridop_free", "rss_set_residual_op", "rss_krylov", "rss_krylov_ex",
            "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
@@ -134,6 +134,9 @@ def load():
     lib.rss_set_residual_op.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.rss_krylov.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                ctypes.c_double, ctypes.c_int, P(rss_krylov_stats)]
+    lib.rss_krylov_ex.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  P(rss_krylov_stats)]
     lib.rss_factor_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_int64), P(rss_kernel),
                                      ctypes.c_double, ctypes.c_int, P(rss_options), P(ctypes.c_void_p)]
     lib.rss_apply_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
@@ -424,14 +427,19 @@ def set_residual_op(fact, op):
     _check(load().rss_set_residual_op(fact._h, op._op if op is not None else None))
 
 
-def krylov(fact, op, B, method: str = "cg", tol: float = 1e-12, maxit: int = 100) -> dict:
-    """rss_krylov: CG ("cg") or GMRES ("gmres") preconditioned by the
-    factorization, products by the grid operator; B (complex128 column-major
-    CUDA tensor) is overwritten with the solution."""
+def krylov(fact, op, B, method: str = "cg", tol: float = 1e-12, maxit: int = 100, restart: int = 0,
+           stream=None) -> dict:
+    """rss_krylov_ex: CG ("cg") or GMRES ("gmres"; GMRES(restart) when
+    restart > 0) preconditioned by the factorization ``fact`` (None: no
+    preconditioner), products by the grid operator; B (complex128
+    column-major CUDA tensor) is overwritten with the solution."""
     st = rss_krylov_stats()
-    nrhs = fact._b(B)
-    _check(load().rss_krylov(fact._h, op._op, ctypes.c_void_p(B.data_ptr()), nrhs,
-                             0 if method == "cg" else 1, float(tol), int(maxit), ctypes.byref(st)))
+    nrhs = 1 if B.dim() == 1 else B.shape[1]
+    if fact is not None:
+        fact._b(B)
+    _check(load().rss_krylov_ex(fact._h if fact is not None else None, op._op, ctypes.c_void_p(B.data_ptr()),
+                                nrhs, 0 if method == "cg" else 1, float(tol), int(maxit), int(restart),
+                                _stream_ptr(stream), ctypes.byref(st)))
     return {"iters": st.iters, "relres": st.relres, "t_ms": st.t_ms}
 
 

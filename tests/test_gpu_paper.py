@@ -152,3 +152,78 @@ def test_refinement_with_the_fft_residual(torch_cuda):
     rss.set_residual_op(F, None)
     op.close()
     F.close()
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-9, 1e-12])
+def test_tolerance_sweep_parity(torch_cuda, eps):
+    """Tab. t:cpp's tolerance sweep (LS Helmholtz, kappa = 25) at a size the
+    oracle factors in seconds: the oracle's skeleton sets at every depth and
+    its solution to 1e-10."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n, leaf = 48, 36
+    P = W.grid_points(n)
+    k = W.paper_helmholtz(n, 25.0)
+    print(f"LS Helmholtz n={n} eps={eps:g}", flush=True)
+    Fo = orss.factor(P, k, eps, leaf)
+    F = rss.Factorization(P, k, eps, leaf)
+    for d in range(Fo.tree.D, 1, -1):
+        got = F.skeletons(d)
+        for (dd, b), sk in Fo.skeletons.items():
+            if dd == d:
+                assert np.array_equal(got[b], sk), (d, b)
+    B = W.uniform_rhs(n * n, 2, 0)
+    Bd = _dev(torch, B)
+    F.apply(Bd)
+    x = Bd.cpu().numpy()
+    xo = orss.solve(Fo, B)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-10
+    F.close()
+
+
+def test_unpreconditioned_gmres_matches_oracle(torch_cuda):
+    """Tab. t:h2's last column: GMRES(20) without a preconditioner, products
+    by the FFT grid operator; the oracle's step count (+-1) and relres 1e-10
+    measured by the oracle's product."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n, kappa = 24, 50.0
+    k = W.paper_helmholtz(n, kappa)
+    b = W.uniform_rhs(n * n, 1, 0)[:, 0]
+    mv = lambda v: omv.fft_matvec(k, n, v)  # noqa: E731
+    _, it_o, _ = okry.gmres(mv, lambda v: v, b, tol=1e-10, maxit=2000, restart=20)
+    op = rss.GridOperator(k, n)
+    Bd = _dev(torch, b[:, None])
+    st = rss.krylov(None, op, Bd, method="gmres", tol=1e-10, maxit=2000, restart=20)
+    x = Bd.cpu().numpy()[:, 0]
+    rr = omv.relres(mv(x), b)
+    print(f"GMRES(20) n_it {st['iters']} (oracle {it_o}), relres {rr:.2e}", flush=True)
+    assert it_o > 40 and abs(st["iters"] - it_o) <= 1
+    assert rr <= 1.5e-10 and st["relres"] <= 1.5e-10
+    op.close()
+
+
+def test_unpreconditioned_gmres_count_matches_tab_h2(torch_cuda):
+    """The paper's printed GMRES(20) count without a preconditioner at
+    N = 1024^2, kappa = pi sqrt(N) / 16 (Tab. t:h2, tests/golden/tab_h2_gmres20.json):
+    the same matrix (eqs. e:b1, e:b2) reaches 1e-12 within 5% of it (b is
+    another uniform random draw)."""
+    import json
+    import math
+    import os
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    with open(os.path.join(os.path.dirname(__file__), "golden", "tab_h2_gmres20.json")) as f:
+        row = json.load(f)["rows"][0]
+    n = int(round(math.sqrt(row["N"])))
+    kappa = 2 * math.pi * row["kappa_over_2pi"]
+    assert abs(kappa - math.pi * n / 16) < 1e-9
+    k = W.paper_helmholtz(n, kappa)
+    op = rss.GridOperator(k, n)
+    Bd = _dev(torch, W.uniform_rhs(n * n, 1, 0))
+    st = rss.krylov(None, op, Bd, method="gmres", tol=1e-12, maxit=3000, restart=20)
+    print(f"N={n}^2 GMRES(20): {st['iters']} iterations (paper {row['n_it_unpreconditioned']}), "
+          f"relres {st['relres']:.2e}", flush=True)
+    assert st["relres"] <= 1.5e-12
+    assert abs(st["iters"] - row["n_it_unpreconditioned"]) <= 0.05 * row["n_it_unpreconditioned"]
+    op.close()

@@ -149,3 +149,65 @@ def test_relres_follows_tolerance_like_the_paper():
         assert 0.1 * eps <= rr[eps] <= 1000 * eps, (eps, rr[eps])
     assert rr[1e-9] < 1e-2 * rr[1e-6]
     assert its[1e-9] <= its[1e-6] <= 6
+
+
+def test_restarted_gmres_matches_scipy():
+    # GMRES(20) without a preconditioner (Tab. t:h2's last column) on the
+    # LS Helmholtz matrix: the oracle's cycle count of steps and its solution
+    # equal SciPy's restarted GMRES (inner steps counted by its callback)
+    import scipy.sparse.linalg as sla
+    n = 24
+    P = W.grid_points(n)
+    k = W.paper_helmholtz(n, 50.0)
+    A = kernels.dense_matrix(k, P)
+    b = W.uniform_rhs(n * n, 1, 0)[:, 0]
+    x, it, hist = krylov.gmres(lambda v: A @ v, lambda v: v, b, tol=1e-10, maxit=2000, restart=20)
+    cnt = [0]
+
+    def cb(_):
+        cnt[0] += 1
+    xs, info = sla.gmres(A, b, rtol=1e-10, atol=0, restart=20, maxiter=100, callback=cb,
+                         callback_type="pr_norm")
+    assert info == 0 and it > 40  # several cycles
+    assert abs(it - cnt[0]) <= 1, (it, cnt[0])
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    # restart >= steps needed: the same iterate as GMRES without restart
+    x1, it1, _ = krylov.gmres(lambda v: A @ v, lambda v: v, b, tol=1e-10, maxit=2000, restart=0)
+    x2, it2, _ = krylov.gmres(lambda v: A @ v, lambda v: v, b, tol=1e-10, maxit=2000, restart=it1 + 5)
+    assert it1 == it2 and np.allclose(x1, x2, rtol=0, atol=1e-14 * np.abs(x1).max())
+
+
+def test_tolerance_sweep_like_tab_cpp():
+    # Tab. t:cpp (LS Helmholtz, kappa = 25): the relres of one application
+    # follows eps down to 1e-9, the preconditioned GMRES count to 1e-12 does
+    # not grow as eps decreases, and ranks grow as eps decreases (Def. 1)
+    n, leaf = 48, 36
+    P = W.grid_points(n)
+    k = W.paper_helmholtz(n, 25.0)
+    b = W.uniform_rhs(n * n, 1, 0)[:, 0]
+    mv = lambda v: matvec.fft_matvec(k, n, v)  # noqa: E731
+    its, rr, rk = {}, {}, {}
+    for eps in (1e-3, 1e-6, 1e-9, 1e-12):
+        F = rss.factor(P, k, eps, leaf)
+        rr[eps] = matvec.relres(mv(rss.solve(F, b)), b)
+        _, its[eps], _ = krylov.gmres(mv, lambda v: rss.solve(F, v), b, tol=1e-12, maxit=40)
+        rk[eps] = np.mean([len(s) for (d, _), s in F.skeletons.items() if d == F.tree.D])
+    for eps in (1e-3, 1e-6, 1e-9):
+        assert 1e-3 * eps <= rr[eps] <= 10 * eps, (eps, rr[eps])
+    assert rr[1e-12] <= 1e-10
+    assert its[1e-3] >= its[1e-6] >= its[1e-9] >= its[1e-12] >= 1, its
+    assert rk[1e-3] < rk[1e-6] < rk[1e-9] < rk[1e-12], rk
+
+
+def test_helmholtz_ranks_grow_with_kappa():
+    # Fig. f:ranks / Sec. 5.2: the numerical rank of the Helmholtz kernel grows
+    # with kappa at fixed geometry (O(kappa D)): mean skeleton counts of the
+    # top compressed depth (boxes of side 1/4) rise with kappa
+    n, leaf = 64, 64
+    P = W.grid_points(n)
+    top = []
+    for kappa in (5.0, 40.0, 120.0):
+        F = rss.factor(P, W.paper_helmholtz(n, kappa), 1e-6, leaf)
+        top.append(np.mean([len(s) for (d, _), s in F.skeletons.items() if d == 2]))
+    assert top[0] < top[1] < top[2], top

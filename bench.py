@@ -169,7 +169,7 @@ def tolerance_and_frequency(torch, rss, W):
     return {"tolerance_sweep_ls_k25_n512": sweep, "rising_frequency_eps1e-6": freq}
 
 
-def batched_sweep(torch, rss, W, reps=2):
+def batched_sweep(torch, rss, W, reps=4):
     """256 independent problems (n uniform over {32,48,64,96,128}, Laplace or
     Helmholtz kappa ~ U[5,40], leaf 64, tol 1e-6, FP64, one RHS each, seed 3),
     factored in one batched sweep and solved in one batched apply."""
@@ -194,9 +194,15 @@ def batched_sweep(torch, rss, W, reps=2):
         if r > 0:
             tf.append(t1 - t0)
             ta.append(t3 - t2)
+    tab = [e for e in rss.factor_tuning() if e["precision_bytes"] == 8]
     return {"problems": len(probs), "unknowns": tot,
             "factor_ms": float(np.median(tf) * 1e3), "factor_unknowns_per_s": tot / float(np.median(tf)),
-            "apply_ms": float(np.median(ta) * 1e3), "apply_unknowns_per_s": tot / float(np.median(ta))}
+            "factor_ms_min": float(np.min(tf) * 1e3),
+            "apply_ms": float(np.median(ta) * 1e3), "apply_unknowns_per_s": tot / float(np.median(ta)),
+            "reps": reps,
+            "factor_tuning": {"buckets": len(tab),
+                              "targets": sorted({e["target_workgroups"] for e in tab}),
+                              "table": tab}}
 
 
 def serving(torch, rss, W, count=300, sides=(128, 256, 512), max_nrhs=256, load=0.7, budget=32e9):

@@ -369,6 +369,34 @@ int rss_set_graphs(int enable);
  */
 int rss_set_autotune(int enable);
 
+/*
+ * Factor-side tuning (same switch, enable = 1 only): the ID's Gram kernel
+ * splits each box's rows into chunks, one workgroup each; per bucket of
+ * (precision, largest box in steps of 16 points, log2 of the boxes in the
+ * launch, log2 of the rows of a box) the first phase of a factorization that
+ * meets the bucket times the chunkings that aim at 512, 1024, 2048, 4096 and
+ * 8192 workgroups on its own data and keeps the fastest for the process
+ * (later phases and factorizations reuse it; the solve server's threads
+ * never time).  Off: 2048.  The choice changes only the order in which
+ * partial Gram matrices are summed (double-double, Def. 1's decisions are
+ * taken on it).
+ *
+ * rss_factor_tuning -- copy up to cap entries of the table into out and set
+ * *count to the number of entries; out may be NULL with cap 0.
+ * rss_factor_tuning_clear -- empty the table (the next factorizations tune again).
+ */
+typedef struct {
+  int precision_bytes;    /* 4: complex64 factors, 8: complex128 */
+  int box_points_hi;      /* the bucket holds boxes of up to this many points */
+  int boxes_log2;         /* ... launches of up to 2^boxes_log2 boxes */
+  int rows_log2;          /* ... boxes of up to 2^rows_log2 rows */
+  int target_workgroups;  /* the chosen target */
+  int chunks;             /* the row chunks per box it gave */
+  float us;               /* its measured time per launch */
+} rss_tune_entry;
+int rss_factor_tuning(rss_tune_entry* out, int cap, int* count);
+int rss_factor_tuning_clear(void);
+
 /* ------------------------------------------------------------------------- */
 /* Solve server: factorizations stay resident in device memory; factor and   */
 /* solve requests are served with continuous batching (a factor worker and a */

@@ -740,6 +740,60 @@ int gram_nmax() {
   return v;
 }
 
+std::atomic<bool> g_autotune{true};
+std::atomic<int> g_autotune_mode{1};
+}  // namespace
+namespace rss {
+extern thread_local bool g_server_thread;
+}
+namespace {
+
+// Factor-tile autotuner.  The Gram kernel of the ID splits each box's rows of
+// Y = [A_MB; K(proxy, B)] into chunks, one workgroup each (partial Gram
+// matrices summed in chunk order); how many pays depends on the number of
+// boxes in the launch, their size and their row count.  Per bucket of those
+// (precision, box size in steps of 16, log2 of boxes per launch, log2 of rows)
+// the first phase that meets it times the candidates (a target of 512 ... 8192
+// workgroups per launch) and keeps the fastest for the process; later phases
+// of the bucket reuse it.  The kernel is a pure function of the level, so the
+// candidates run on the real data and the chosen one runs last.  Off (or in
+// the solve server's threads): 2048.
+struct GramTuneKey {
+  int prec, nb, sb, rb;
+  bool operator<(const GramTuneKey& o) const {
+    return std::tie(prec, nb, sb, rb) < std::tie(o.prec, o.nb, o.sb, o.rb);
+  }
+};
+struct GramTuneVal {
+  int target;   // workgroups per launch aimed at
+  int chunks;   // row chunks per box that gave
+  float us;     // its time per launch
+};
+std::mutex g_gram_tune_mu;
+std::map<GramTuneKey, GramTuneVal> g_gram_tune;
+constexpr int GRAM_TUNE_DEFAULT = 2048;
+constexpr int GRAM_TUNE_TARGETS[] = {512, 1024, 2048, 4096, 8192};
+
+int ceil_log2(int v) {
+  int b = 0;
+  while ((1 << b) < v) ++b;
+  return b;
+}
+GramTuneKey gram_tune_key(int prec_bytes, int nmax, int nslot, int rows_ub) {
+  return {prec_bytes, (nmax + 15) / 16, ceil_log2(std::max(1, nslot)), ceil_log2(std::max(1, rows_ub))};
+}
+// row chunks per box for a target workgroup count: at least 32 rows of Y per
+// chunk, chunk rows a multiple of 16
+void gram_chunking(int target, int nslot, int nmax, int rows_ub, int& chunks, int& chunk_rows) {
+  const int tgroups = gram_tile_groups(std::max(1, nmax));
+  const int want = std::max(1, (target + nslot * tgroups - 1) / (nslot * tgroups));
+  const int most = std::max(1, (rows_ub + 31) / 32);
+  const int ch = std::min(want, most);
+  chunk_rows = ((rows_ub + ch - 1) / ch + 15) / 16 * 16;
+  chunks = std::max(1, (rows_ub + chunk_rows - 1) / chunk_rows);
+}
+bool gram_tuning_on() { return g_autotune.load() && g_autotune_mode.load() == 1 && !rss::g_server_thread; }
+
 // Bounded wait of the multi-workgroup QR's per-box barriers (spins of about
 // 0.1 us); the environment variable RSS_MG_SPIN_LIMIT (read once) sets another
 // value (tests force timeouts with a tiny one).
@@ -1018,6 +1072,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       int rows_ub = 0;                   // most rows of Y = [A_MB; K(proxy, B)] of a slot
       int chunks = 1, chunk_rows = 1;
       int nmax = 0;                      // largest box of the phase
+      bool tune = false;                 // time the Gram chunkings (workspace for the largest)
+      GramTuneKey key{};
     } M[9];
     // the ID through the double-double Gram matrix for boxes of up to
     // GRAM_NMAX points, else column-pivoted Householder QR on C
@@ -1062,15 +1118,22 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       G.tot = C + X + Z;
       G.itot = I;
       if (use_gram && !G.box.empty()) {
-        // row chunks per box: enough workgroups to fill the chip (~2048), at
-        // least 32 rows of Y per chunk
+        // row chunks per box: the tuned choice of this bucket, else ~2048
+        // workgroups; a bucket not tuned yet gets workspace for the most chunks
         const int nslot = (int)G.box.size();
-        const int tgroups = gram_tile_groups(std::max(1, G.nmax));
-        const int want = std::max(1, (2048 + nslot * tgroups - 1) / (nslot * tgroups));
-        const int most = std::max(1, (G.rows_ub + 31) / 32);
-        const int ch = std::min(want, most);
-        G.chunk_rows = ((G.rows_ub + ch - 1) / ch + 15) / 16 * 16;
-        G.chunks = std::max(1, (G.rows_ub + G.chunk_rows - 1) / G.chunk_rows);
+        G.key = gram_tune_key((int)sizeof(R), G.nmax, nslot, G.rows_ub);
+        int target = GRAM_TUNE_DEFAULT;
+        bool cached = false;
+        {
+          std::lock_guard<std::mutex> lk(g_gram_tune_mu);
+          auto it = g_gram_tune.find(G.key);
+          if (it != g_gram_tune.end()) {
+            target = it->second.target;
+            cached = true;
+          }
+        }
+        G.tune = !cached && gram_tuning_on();
+        gram_chunking(G.tune ? GRAM_TUNE_TARGETS[4] : target, nslot, G.nmax, G.rows_ub, G.chunks, G.chunk_rows);
         int64_t o = 0;
         for (size_t i = 0; i < G.box.size(); ++i) {
           const int n = W[act[G.prob[i]]].cur.n0[G.box[i]];
@@ -1137,9 +1200,49 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       }
     }
     pk.flush(scr, s);
+    // the Gram chunking of a bucket met for the first time: each candidate
+    // once to warm up and twice timed, then the fastest is kept (and set in gw)
+    auto tune_gram = [&](const Phase<R>& ph, GramWs& gw, Merged& G) {
+      {
+        std::lock_guard<std::mutex> lk(g_gram_tune_mu);
+        auto it = g_gram_tune.find(G.key);
+        if (it != g_gram_tune.end()) {  // tuned by an earlier phase of this height
+          gram_chunking(it->second.target, ph.nbox, G.nmax, G.rows_ub, gw.chunks, gw.chunk_rows);
+          return;
+        }
+      }
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      GramTuneVal best{GRAM_TUNE_DEFAULT, 0, 0.0f};
+      int last_chunks = -1;
+      for (int target : GRAM_TUNE_TARGETS) {
+        int ch = 0, cr = 0;
+        gram_chunking(target, ph.nbox, G.nmax, G.rows_ub, ch, cr);
+        if (ch == last_chunks) continue;  // the same launch as the previous target
+        last_chunks = ch;
+        gw.chunks = ch;
+        gw.chunk_rows = cr;
+        launch_gram<R>(d_probs, ph, gw, G.nmax, s);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 2; ++rep) launch_gram<R>(d_probs, ph, gw, G.nmax, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 500.0f;
+        if (best.chunks == 0 || us < best.us) best = {target, ch, us};
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      gram_chunking(best.target, ph.nbox, G.nmax, G.rows_ub, gw.chunks, gw.chunk_rows);
+      std::lock_guard<std::mutex> lk(g_gram_tune_mu);
+      g_gram_tune.emplace(G.key, best);
+    };
     for (int c = 0; c < 9; ++c) {
       if (M[c].box.empty()) continue;
       const Phase<R>& ph = phs[c];
+      if (use_gram && M[c].tune) tune_gram(ph, gws[c], M[c]);
       if (use_gram) {
         prof.run(RSS_K_ID, s, [&] {
           launch_gram<R>(d_probs, ph, gws[c], M[c].nmax, s);
@@ -1802,8 +1905,6 @@ struct ApplyGraph : ApplyGraphBase {
 };
 
 std::atomic<bool> g_use_graphs{true};
-std::atomic<bool> g_autotune{true};
-std::atomic<int> g_autotune_mode{1};
 }  // namespace
 namespace rss {
 thread_local bool g_server_thread = false;
@@ -2825,6 +2926,29 @@ int rss_set_autotune(int enable) {
   }
   g_autotune.exchange(enable == 1);
   return g_autotune_mode.exchange(enable);
+}
+
+int rss_factor_tuning(rss_tune_entry* out, int cap, int* count) {
+  if (!count || cap < 0 || (cap > 0 && !out)) {
+    g_err = "bad arguments";
+    return RSS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_gram_tune_mu);
+  int i = 0;
+  for (const auto& kv : g_gram_tune) {
+    if (i < cap)
+      out[i] = {kv.first.prec, kv.first.nb * 16, kv.first.sb, kv.first.rb, kv.second.target, kv.second.chunks,
+                kv.second.us};
+    ++i;
+  }
+  *count = i;
+  return RSS_OK;
+}
+
+int rss_factor_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_gram_tune_mu);
+  g_gram_tune.clear();
+  return RSS_OK;
 }
 
 const char* rss_last_error(void) { return g_err.c_str(); }

@@ -52,10 +52,17 @@ class rss_stats(ctypes.Structure):
 EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_solve_batch", "rss_apply",
            "rss_apply_batch", "rss_free", "rss_info", "rss_skeletons", "rss_kernel_block", "rss_residual",
            "rss_residual_static", "rss_gridop_create", "rss_gridop_apply", "rss_gridop_residual",
-           "rss_gridop_free", "rss_set_residual_op", "rss_krylov", "rss_krylov_ex",
+           "rss_gridop_free", "rss_set_residual_op", "rss_krylov", "rss_krylov_ex", "rss_factor_tuning",
+           "rss_factor_tuning_clear",
            "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
+
+
+class rss_tune_entry(ctypes.Structure):
+    _fields_ = [("precision_bytes", ctypes.c_int), ("box_points_hi", ctypes.c_int), ("boxes_log2", ctypes.c_int),
+                ("rows_log2", ctypes.c_int), ("target_workgroups", ctypes.c_int), ("chunks", ctypes.c_int),
+                ("us", ctypes.c_float)]
 
 
 class rss_krylov_stats(ctypes.Structure):
@@ -134,6 +141,8 @@ def load():
     lib.rss_set_residual_op.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.rss_krylov.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                ctypes.c_double, ctypes.c_int, P(rss_krylov_stats)]
+    lib.rss_factor_tuning.argtypes = [P(rss_tune_entry), ctypes.c_int, P(ctypes.c_int)]
+    lib.rss_factor_tuning_clear.argtypes = []
     lib.rss_krylov_ex.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   P(rss_krylov_stats)]
@@ -441,6 +450,20 @@ def krylov(fact, op, B, method: str = "cg", tol: float = 1e-12, maxit: int = 100
                                 nrhs, 0 if method == "cg" else 1, float(tol), int(maxit), int(restart),
                                 _stream_ptr(stream), ctypes.byref(st)))
     return {"iters": st.iters, "relres": st.relres, "t_ms": st.t_ms}
+
+
+def factor_tuning() -> list:
+    """rss_factor_tuning: the factor-side tuner's table (one dict per bucket)."""
+    lib = load()
+    cnt = ctypes.c_int()
+    _check(lib.rss_factor_tuning(None, 0, ctypes.byref(cnt)))
+    buf = (rss_tune_entry * max(1, cnt.value))()
+    _check(lib.rss_factor_tuning(buf, cnt.value, ctypes.byref(cnt)))
+    return [{f: getattr(buf[i], f) for f, _ in rss_tune_entry._fields_} for i in range(cnt.value)]
+
+
+def factor_tuning_clear():
+    _check(load().rss_factor_tuning_clear())
 
 
 def solve_batch(facts, Bs):

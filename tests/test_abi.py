@@ -62,7 +62,8 @@ def _struct_fields(name):
                                       ("rss_server_options", rss.rss_server_options),
                                       ("rss_completion", rss.rss_completion),
                                       ("rss_server_stats", rss.rss_server_stats),
-                                      ("rss_krylov_stats", rss.rss_krylov_stats)])
+                                      ("rss_krylov_stats", rss.rss_krylov_stats),
+                                      ("rss_tune_entry", rss.rss_tune_entry)])
 def test_struct_mirrors(cname, py):
     assert _struct_fields(cname) == [f for f, _ in py._fields_]
 

@@ -170,3 +170,46 @@ def test_fused_tiles_agree_with_default(torch_cuda, kappa, n, leaf):
     finally:
         rss.set_autotune(prev_t)
         rss.set_graphs(prev_g)
+
+
+def test_factor_tuner_buckets_and_agreement(torch_cuda):
+    """The factor-side tuner (rss_factor_tuning): a factorization with tuning
+    on fills the table with one entry per bucket it meets, each a candidate
+    target; the chunking changes only the summation order of the Gram partial
+    matrices, so the skeleton sets equal an untuned factorization's and the
+    applies agree to 1e-12; the next factorization reuses the table."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n = 128
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, 40.0)
+    B0 = W.rhs(n * n, 3, 32)
+    rss.factor_tuning_clear()
+    prev = rss.set_autotune(False)
+    try:
+        f0 = rss.Factorization(P, k, 1e-6, 64, precision="fp64")
+        assert rss.factor_tuning() == []
+        X0 = _dev(torch, B0)
+        f0.apply(X0)
+        rss.set_autotune(True)
+        f1 = rss.Factorization(P, k, 1e-6, 64, precision="fp64")
+        tab = rss.factor_tuning()
+        print(tab, flush=True)
+        assert len(tab) >= 2  # several depths, several buckets
+        for e in tab:
+            assert e["target_workgroups"] in (512, 1024, 2048, 4096, 8192)
+            assert e["chunks"] >= 1 and e["us"] > 0 and e["precision_bytes"] == 8
+        D = f1.info()["depth"]
+        for d in range(D, 1, -1):
+            a, b = f0.skeletons(d), f1.skeletons(d)
+            assert all(np.array_equal(x, y) for x, y in zip(a, b)), d
+        X1 = _dev(torch, B0)
+        f1.apply(X1)
+        x0, x1 = X0.cpu().numpy(), X1.cpu().numpy()
+        assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-12
+        f2 = rss.Factorization(P, k, 1e-6, 64, precision="fp64")
+        assert rss.factor_tuning() == tab
+        for f in (f0, f1, f2):
+            f.close()
+    finally:
+        rss.set_autotune(prev)

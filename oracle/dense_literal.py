@@ -53,7 +53,9 @@ class LiteralFactorization:
     skeletons: dict
 
 
-def factor_literal(P, kern, tol, leaf, n_proxy=0, proxy_radius=1.25, min_depth=2, root=None):
+def factor_literal(P, kern, tol, leaf, n_proxy=0, proxy_radius=1.25, min_depth=2, root=None, colours=9):
+    """colours = 4: the four-colour schedule; every ID of a colour is taken
+    from the matrix as it stands before the colour's first elimination."""
     P = np.asarray(P, dtype=np.float64)
     tree = Tree(P, leaf, root)
     N = tree.N
@@ -66,21 +68,32 @@ def factor_literal(P, kern, tol, leaf, n_proxy=0, proxy_radius=1.25, min_depth=2
     d = tree.D
     while True:
         snaps[d] = ([a.copy() for a in active], A.copy())
-        for b in tree.order(d):
+
+        def ident(b):
             I = active[b]
-            n = I.size
-            if n == 0:
-                continue
             Mb = tree.dist2(d, b)
-            Nb = tree.nbrs(d, b)
             Midx = np.concatenate([active[m] for m in Mb]) if Mb else np.zeros(0, np.int64)
-            Nidx = np.concatenate([active[x] for x in Nb]) if Nb else np.zeros(0, np.int64)
             G = tree.proxy_points(d, b, npx, proxy_radius)
             C = np.vstack([A[np.ix_(Midx, I)], A[np.ix_(I, Midx)].conj().T,
                            kernels.proxy_entries(kern, G, P, I),
                            kernels.proxy_entries_t(kern, G, P, I)])
             Sl, Rl, T = cpqr.interpolative_decomposition(C, tol, I)
-            nu0 = np.sqrt(np.sum(np.abs(C) ** 2, axis=0)).max()
+            return Sl, Rl, T, np.sqrt(np.sum(np.abs(C) ** 2, axis=0)).max()
+
+        order = tree.order(d, colours)
+        snap_ids = {}
+        for pos, b in enumerate(order):
+            I = active[b]
+            n = I.size
+            if n == 0:
+                continue
+            if colours == 4 and (pos == 0 or tree.colour(d, order[pos - 1], 4) != tree.colour(d, b, 4)):
+                # first box of a colour: the IDs of the whole colour, from this matrix
+                c = tree.colour(d, b, 4)
+                snap_ids = {x: ident(x) for x in order if tree.colour(d, x, 4) == c and active[x].size}
+            Nb = tree.nbrs(d, b)
+            Nidx = np.concatenate([active[x] for x in Nb]) if Nb else np.zeros(0, np.int64)
+            Sl, Rl, T, nu0 = snap_ids[b] if colours == 4 else ident(b)
             skel[(d, b)] = I[Sl].copy()
             if Rl.size == 0:
                 continue

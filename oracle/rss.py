@@ -25,6 +25,19 @@ Factorization (Alg. a:fact):
   indices are factored densely (the root; Sec. 2.5 footnote: the top level has
   no far field).
 
+Four-colour schedule (Options.colours = 4; Sec. 3's coloured variant, where
+only neighbours must differ in colour): the boxes of one colour are at
+distance 2, so a box B' of the colour lies in M(B).  Reading: the colour is
+one concurrent step taken from a snapshot -- every ID of the colour is
+computed from the blocks as they stand before any of its eliminations (B's
+compression matrix still holds all of B''s indices, a superset of the rows
+a sequential order would give), then every box is sparsified, eliminated and
+compacted.  Those steps commute exactly: B's sparsification reads only
+blocks with B as an index, which no other box of the colour writes (Rem.
+r:nn: B is not a neighbour of B'), and the Schur updates of two boxes meet
+only additively on blocks between common neighbours.  The result is a valid
+RS-S factorization in another order than the nine-colour one.
+
 Storage: a dense block A[b, b'] for every ordered pair of boxes at distance
 <= 2 at the current depth ("explicitly store the modified interactions for
 every box", Sec. 3.3).  Each box's active index set is kept sorted by global
@@ -52,6 +65,9 @@ class Options:
     n_proxy: int = 0            # 0 -> 64 for Laplace, 128 otherwise
     proxy_radius: float = 1.25  # proxy circle radius in box-side units
     min_depth: int = 2          # compress depths D .. min_depth
+    colours: int = 9            # 9: colour (bx mod 3) + 3 (by mod 3); 4: (bx mod 2) + 2 (by mod 2)
+    reverse_within_colour: bool = False  # four colours: eliminate a colour's boxes in descending id
+                                         # order (tests of the snapshot reading: no effect but rounding)
 
 
 @dataclasses.dataclass
@@ -151,16 +167,29 @@ def _compression_matrix(st: _State, kern, P, b, npx, c_r, counter):
     return np.vstack(rows) if rows else np.zeros((0, I.size), complex)
 
 
-def _skel(st: _State, kern, P, b, tol, opts, records, ledger, skeletons, counter):
+def _skel_id(st: _State, kern, P, b, tol, opts, counter):
+    """The ID of box b from the current blocks (Def. 1, eqs. e:con, e:proxy):
+    (Sl, Rl, T, m), or None for an empty box."""
+    I = st.active[b]
+    if I.size == 0:
+        return None
+    npx = _default_npx(kern, opts.n_proxy)
+    C = _compression_matrix(st, kern, P, b, npx, opts.proxy_radius, counter)
+    Sl, Rl, T = cpqr.interpolative_decomposition(C, tol, I)
+    return Sl, Rl, T, C.shape[0]
+
+
+def _skel(st: _State, kern, P, b, tol, opts, records, ledger, skeletons, counter, ident=None):
+    """Strong skeletonization of box b; ident: its ID when already taken
+    (the four-colour schedule's snapshot), else computed here."""
     tree, d = st.tree, st.d
     I = st.active[b]
     n = I.size
     if n == 0:
         return
-    npx = _default_npx(kern, opts.n_proxy)
-    C = _compression_matrix(st, kern, P, b, npx, opts.proxy_radius, counter)
-    m = C.shape[0]
-    Sl, Rl, T = cpqr.interpolative_decomposition(C, tol, I)
+    if ident is None:
+        ident = _skel_id(st, kern, P, b, tol, opts, counter)
+    Sl, Rl, T, m = ident
     k, r = Sl.size, Rl.size
     Nb = tree.nbrs(d, b)
     nN = sum(st.active[x].size for x in Nb)
@@ -269,8 +298,16 @@ def factor(P: np.ndarray, kern, tol: float, leaf: int, opts: Options | None = No
         st = _leaf_state(tree, kern, P, counter)
         d = tree.D
         while True:
-            for b in tree.order(d):
-                _skel(st, kern, P, b, tol, opts, records, ledger, skeletons, counter)
+            if opts.colours == 4:
+                order = tree.order(d, 4)
+                for c in range(4):
+                    boxes = [b for b in order if tree.colour(d, b, 4) == c]
+                    ids = {b: _skel_id(st, kern, P, b, tol, opts, counter) for b in boxes}
+                    for b in (boxes[::-1] if opts.reverse_within_colour else boxes):
+                        _skel(st, kern, P, b, tol, opts, records, ledger, skeletons, counter, ids[b])
+            else:
+                for b in tree.order(d):
+                    _skel(st, kern, P, b, tol, opts, records, ledger, skeletons, counter)
             if d == opts.min_depth:
                 break
             st = _transition(st, kern, P, counter)

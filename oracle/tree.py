@@ -13,6 +13,10 @@
   so by Rem. r:t and Rem. r:nn they read and write disjoint blocks.  Within a
   depth the oracle visits colours 0..8 and, inside a colour, boxes in id
   order -- one admissible instance of "a given ordering" in Alg. a:fact.
+* The four-colour schedule (colour (bx mod 2) + 2 (by mod 2)) of Sec. 3's
+  coloured variant only keeps neighbours apart: boxes of one colour are at
+  distance 2, share neighbours and see each other in their compression
+  matrices (rss.factor's snapshot reading).
 """
 from __future__ import annotations
 
@@ -105,15 +109,17 @@ class Tree:
         return self.ring(d, b, 2)
 
     @staticmethod
-    def colour(d: int, b: int) -> int:
+    def colour(d: int, b: int, ncol: int = 9) -> int:
         nb = 1 << d
+        if ncol == 4:
+            return (b % nb) % 2 + 2 * ((b // nb) % 2)
         return (b % nb) % 3 + 3 * ((b // nb) % 3)
 
-    def order(self, d: int) -> list:
+    def order(self, d: int, ncol: int = 9) -> list:
         """Elimination order at depth d: colour-major, id order inside a colour."""
         nb = 1 << d
         boxes = range(nb * nb)
-        return [b for c in range(9) for b in boxes if self.colour(d, b) == c]
+        return [b for c in range(ncol) for b in boxes if self.colour(d, b, ncol) == c]
 
     @staticmethod
     def children(d: int, p: int) -> list:

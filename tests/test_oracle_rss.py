@@ -238,3 +238,52 @@ def test_shallow_tree_is_dense_lu():
     assert F.tree.D == 0 and not F.records
     b = W.rhs(64, 1, 0)
     assert _rel(rss.solve(F, b), _dense_solve(k, P, b)) < 1e-13
+
+
+# --- four-colour schedule (Sec. 3's coloured variant; snapshot reading) ---
+
+@pytest.mark.parametrize("kind,kappa,n,leaf", [("laplace", 0, 16, 4), ("helmholtz", 40, 24, 9),
+                                               ("helmholtz", 25, 32, 16)])
+def test_four_colour_dense_literal_agrees(kind, kappa, n, leaf):
+    # the block-store oracle and the literal full-matrix one, both taking a
+    # colour's IDs from the matrix before its first elimination
+    P = W.grid_points(n)
+    k = W.grid_kernel(kind, n, kappa)
+    F = rss.factor(P, k, 1e-6, leaf, rss.Options(colours=4))
+    LF = dense_literal.factor_literal(P, k, 1e-6, leaf, colours=4)
+    assert F.skeletons.keys() == LF.skeletons.keys()
+    for key in F.skeletons:
+        assert np.array_equal(F.skeletons[key], LF.skeletons[key])
+    b = W.rhs(n * n, 1, 2)[:, 0]
+    assert _rel(rss.solve(F, b), dense_literal.solve_literal(LF, b)) < 1e-12
+    assert max(r.far_ratio for r in LF.records) <= 100.0
+
+
+@pytest.mark.parametrize("kind,kappa", [("laplace", 0.0), ("helmholtz", 25.0), ("helmholtz", 50.0)])
+def test_four_colour_relres_below_tol(kind, kappa):
+    n, leaf, tol = 32, 16, 1e-6
+    P = W.grid_points(n)
+    k = W.grid_kernel(kind, n, kappa)
+    F = rss.factor(P, k, tol, leaf, rss.Options(colours=4))
+    b = W.rhs(n * n, 3, 11)
+    x = rss.solve(F, b)
+    A = kernels.dense_matrix(k, P)
+    assert matvec.relres(A @ x, b) < tol
+    assert _rel(x, scipy.linalg.solve(A, b)) < tol
+
+
+def test_four_colour_order_inside_a_colour_is_immaterial():
+    # a colour is one concurrent step: eliminating its boxes in the reverse
+    # order gives the same skeletons and, to rounding, the same factorization
+    n, leaf = 32, 16
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, 40.0)
+    F1 = rss.factor(P, k, 1e-6, leaf, rss.Options(colours=4))
+    F2 = rss.factor(P, k, 1e-6, leaf, rss.Options(colours=4, reverse_within_colour=True))
+    for key in F1.skeletons:
+        assert np.array_equal(F1.skeletons[key], F2.skeletons[key])
+    b = W.rhs(n * n, 2, 4)
+    assert _rel(rss.solve(F2, b), rss.solve(F1, b)) < 1e-12
+    # and the schedule is another elimination order than the nine-colour one
+    F9 = rss.factor(P, k, 1e-6, leaf)
+    assert any(not np.array_equal(F1.skeletons[key], F9.skeletons[key]) for key in F1.skeletons)

@@ -254,6 +254,54 @@ def serving(torch, rss, W, count=300, sides=(128, 256, 512), max_nrhs=256, load=
     return res
 
 
+def four_colour_schedule(torch, rss, W, w, P, B, gop, reps=2):
+    """The four-colour schedule (rss_options.colours = 4; Sec. 3's coloured
+    variant) beside the default nine colours on the headline workload: FP32
+    and FP64 factor times, one application, and the time to relres <= 1e-10
+    with the FFT residual (FP32: refinement; FP64: one application and its
+    check), medians of ``reps`` after a warm-up factorization of each."""
+    out = {}
+    for col in (9, 4):
+        res = {}
+        for prec in ("fp32", "fp64"):
+            F = rss.Factorization(P, w.kernel, w.tol, w.leaf, precision=prec, n_proxy=w.n_proxy, colours=col)
+            F.close()
+            tf, ta, ts, steps, rr = [], [], [], 0, 0.0
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F = rss.Factorization(P, w.kernel, w.tol, w.leaf, precision=prec, n_proxy=w.n_proxy,
+                                      colours=col, max_refine=10, refine_tol=1e-10)
+                torch.cuda.synchronize()
+                tf.append(time.perf_counter() - t0)
+                X = B.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F.apply(X)
+                torch.cuda.synchronize()
+                ta.append(time.perf_counter() - t0)
+                rss.set_residual_op(F, gop)
+                X = B.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F.solve(X)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                info = F.info()
+                steps, rr = info["last_iters"], info["last_relres"]
+                rss.set_residual_op(F, None)
+                F.close()
+            tfm, tsm = float(np.median(tf)), float(np.median(ts))
+            res[prec] = {"t_factor_ms": tfm * 1e3, "factor_unknowns_per_s": w.N / tfm,
+                         "apply_ms": float(np.median(ta)) * 1e3, "t_solve_to_1e-10_ms": tsm * 1e3,
+                         "time_to_solution_unknowns_per_s": w.N / (tfm + tsm), "refine_steps": steps,
+                         "relres": rr}
+        res["fp32_over_fp64_time_to_solution"] = (res["fp32"]["time_to_solution_unknowns_per_s"]
+                                                  / res["fp64"]["time_to_solution_unknowns_per_s"])
+        out[f"colours_{col}"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +404,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
+    schedules = four_colour_schedule(torch, rss, W, w, P, B, gop)
     gop.close()
     # relres of the last step's results by the oracle's exact FFT product (host)
     from oracle import matvec as omv
@@ -465,6 +514,7 @@ def main():
                              "relres": recs[-1]["i64f"]["last_relres"],
                              "refine_steps": recs[-1]["i64f"]["last_iters"]},
         },
+        "schedules_fft_residual": schedules,
         "ranks_fp32": [round(i32["rank_sum"][d] / max(1, i32["box_count"][d]), 2) for d in range(2, i32["depth"] + 1)],
         "ranks_fp64": [round(i64["rank_sum"][d] / max(1, i64["box_count"][d]), 2) for d in range(2, i64["depth"] + 1)],
         "ledger_fp32": {k: i32[k] for k in ("flops_id", "flops_lu", "flops_y", "flops_schur",

@@ -87,6 +87,16 @@ typedef struct {
   void* stream;           /* hipStream_t for all work; NULL -> a stream owned by the handle */
   int profile;            /* nonzero: time every kernel class with HIP events on the stream
                              (rss_stats.t_class_ms); adds a little host overhead */
+  int colours;            /* elimination schedule within a depth; 0 or 9: nine colours
+                             (bx mod 3) + 3 (by mod 3), boxes of a colour 3 apart, the default;
+                             4: four colours (bx mod 2) + 2 (by mod 2) (Sec. 3's coloured
+                             variant: only neighbours differ): boxes of a colour are 2 apart,
+                             every ID of a colour is taken before its first elimination, their
+                             Schur updates meet additively (applied in four ordered passes, so
+                             the factorization is deterministic) and the forward solve adds
+                             their neighbour updates atomically (results not bitwise
+                             reproducible).  Fewer, wider phases: 4 instead of 9 per depth.
+                             All problems of one rss_factor_batch share the schedule. */
 } rss_options;
 
 /* kernel classes timed when rss_options.profile is set (index into t_class_ms) */

@@ -794,6 +794,20 @@ void gram_chunking(int target, int nslot, int nmax, int rows_ub, int& chunks, in
 }
 bool gram_tuning_on() { return g_autotune.load() && g_autotune_mode.load() == 1 && !rss::g_server_thread; }
 
+// Colour of box b (row-major id on an nb x nb grid) in the elimination
+// schedule: nine colours (bx mod 3) + 3 (by mod 3), boxes of a colour 3 apart;
+// four colours (bx mod 2) + 2 (by mod 2), boxes of a colour 2 apart.
+int box_colour(int b, int nb, int colours) {
+  const int bx = b % nb, by = b / nb;
+  return colours == 4 ? (bx & 1) + 2 * (by & 1) : bx % 3 + 3 * (by % 3);
+}
+// Four colours: the Schur updates of a colour go in four ordered passes,
+// boxes of a pass 4 apart, so no two updates of a pass meet on a block.
+int schur_pass(int b, int nb) {
+  const int bx = b % nb, by = b / nb;
+  return ((bx >> 1) & 1) + 2 * ((by >> 1) & 1);
+}
+
 // Bounded wait of the multi-workgroup QR's per-box barriers (spins of about
 // 0.1 us); the environment variable RSS_MG_SPIN_LIMIT (read once) sets another
 // value (tests force timeouts with a tiny one).
@@ -1019,11 +1033,15 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       dr.kmax = dr.rmax = cur.nmax;
       dr.d_F = h->arena.alloc((size_t)F * E);
       dr.d_G = (int*)h->arena.alloc((size_t)G * sizeof(int));
-      // per-problem phase lists (kept for the solve)
+      // per-problem phase lists (kept for the solve); four colours: a
+      // colour's boxes ordered by their pass of the Schur update
       for (int c = 0; c < 9; ++c) {
         PhaseHost& P = dr.ph[c];
-        for (int b = 0; b < nbox; ++b)
-          if ((b % nb) % 3 + 3 * ((b / nb) % 3) == c && cur.n0[b] > 0) P.boxes.push_back(b);
+        for (int q = 0; q < 4; ++q)
+          for (int b = 0; b < nbox; ++b)
+            if (box_colour(b, nb, h->opt.colours) == c && cur.n0[b] > 0 &&
+                (h->opt.colours == 9 ? q == 0 : schur_pass(b, nb) == q))
+              P.boxes.push_back(b);
       }
       h->recs.push_back(std::move(dr));
       {
@@ -1074,7 +1092,9 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       int nmax = 0;                      // largest box of the phase
       bool tune = false;                 // time the Gram chunkings (workspace for the largest)
       GramTuneKey key{};
+      int pass_lo[5] = {0, 0, 0, 0, 0};  // four colours: slots of Schur pass q are [pass_lo[q], pass_lo[q+1])
     } M[9];
+    const int colours = H[0]->opt.colours;
     // the ID through the double-double Gram matrix for boxes of up to
     // GRAM_NMAX points, else column-pivoted Householder QR on C
     const bool use_gram = nmax <= gram_nmax();
@@ -1084,11 +1104,23 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       Merged& G = M[c];
       int64_t C = 0, X = 0, Z = 0, I = 0;
       std::vector<int64_t> cx_, xx_, zx_;
-      for (size_t a = 0; a < act.size(); ++a) {
+      // slots problem by problem (nine colours), or pass by pass and then
+      // problem by problem (four colours)
+      std::vector<std::pair<int, int>> slots;  // (a, b)
+      for (int q = 0; q < (colours == 4 ? 4 : 1); ++q) {
+        G.pass_lo[q] = (int)slots.size();
+        for (size_t a = 0; a < act.size(); ++a)
+          for (int b : H[act[a]]->recs.back().ph[c].boxes)
+            if (colours != 4 || schur_pass(b, W[act[a]].cur.nb) == q) slots.push_back({(int)a, b});
+      }
+      for (int q = (colours == 4 ? 4 : 1); q < 5; ++q) G.pass_lo[q] = (int)slots.size();
+      for (const auto& sl : slots) {
+        const size_t a = (size_t)sl.first;
+        const int b = sl.second;
         const int p = act[a];
         const LevelHost& cur = W[p].cur;
         const int nb = cur.nb;
-        for (int b : H[p]->recs.back().ph[c].boxes) {
+        {
           const int n = cur.n0[b];
           int msum = 0, nN0 = 0;
           for (int x : ring(nb, b, 2)) msum += cur.n0[x];
@@ -1260,8 +1292,23 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(d_probs, ph, d_err, nmax, s); });
       launch_plan_y<R>(d_probs, ph, desc, s);
       prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, nmax, nmax + nNmax, s); });
-      prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(d_probs, ph, s); });
-      prof.run(RSS_K_SCHUR, s, [&] { launch_schur<R>(d_probs, ph, nmax + nNmax, s); });
+      prof.run(RSS_K_COMPACT, s, [&] { launch_compact<R>(d_probs, ph, colours, s); });
+      prof.run(RSS_K_SCHUR, s, [&] {
+        if (colours != 4) {
+          launch_schur<R>(d_probs, ph, nmax + nNmax, s);
+          return;
+        }
+        // four ordered passes: boxes of a pass are 4 apart (no common target block)
+        for (int q = 0; q < 4; ++q) {
+          const int lo = M[c].pass_lo[q], hi = M[c].pass_lo[q + 1];
+          if (hi <= lo) continue;
+          Phase<R> sub = ph;
+          sub.nbox = hi - lo;
+          sub.box += lo;
+          sub.prob += lo;
+          launch_schur<R>(d_probs, sub, nmax + nNmax, s);
+        }
+      });
     }
     std::vector<int> mrow_h((size_t)9 * std::max(1, maxph));
     HIPCHK(hipMemcpyAsync(mrow_h.data(), mrow, mrow_h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1670,6 +1717,8 @@ struct ApplyPlan {
             ph.prob = mem.up(prob, s);
           }
         }
+        for (int p = 0; p < np; ++p)
+          if (idxmap[p] >= 0 && H[p]->opt.colours == 4) ph.atomic_nbr = 1;
       }
     }
     // tiles: the tuned choice for the level's shape, else the defaults; the
@@ -2164,6 +2213,8 @@ rss_ctx* make_ctx(const double* points, int64_t n, const rss_kernel* k, double t
   if (h->opt.refine_tol == 0) h->opt.refine_tol = 1e-10;
   if (h->opt.precision != RSS_FP64 && h->opt.precision != RSS_FP32_REFINE)
     fail(RSS_EINVAL, "unknown precision");
+  if (h->opt.colours == 0) h->opt.colours = 9;
+  if (h->opt.colours != 9 && h->opt.colours != 4) fail(RSS_EINVAL, "colours must be 0, 4 or 9");
   // refinement steps after the first solve (-1: no refinement, plain apply)
   if (h->opt.precision == RSS_FP32_REFINE)
     h->refine_steps = h->opt.max_refine == 0 ? 10 : (h->opt.max_refine < 0 ? -1 : h->opt.max_refine);
@@ -2341,6 +2392,7 @@ int rss_apply_batch(int nh, rss_handle* hs, void* const* B, const int* nrhs) {
     for (int p = 0; p < nh; ++p) {
       if (!H[p] || !B[p] || nrhs[p] < 1) fail(RSS_EINVAL, "bad batch entry");
       if (H[p]->precision != H[0]->precision) fail(RSS_EINVAL, "mixed precisions in a batch");
+      if (H[p]->opt.colours != H[0]->opt.colours) fail(RSS_EINVAL, "mixed schedules in a batch");
     }
     hipStream_t s = H[0]->stream;
     for (int p = 1; p < nh; ++p)
@@ -2648,6 +2700,10 @@ int rss_krylov_ex(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, 
       const int m = restart > 0 ? std::min(restart, maxit) : maxit;
       const int64_t vstride = (int64_t)tot;
       cx<double>* V = (cx<double>*)scr.alloc((size_t)(m + 1) * vb);
+      // with a preconditioner, Z_j = M^{-1} V_j are kept, so that the
+      // correction sum_j y_j Z_j needs no further application (the flexible
+      // form; the same iterates for a fixed M, one application fewer)
+      cx<double>* Zs = h ? (cx<double>*)scr.alloc((size_t)m * vb) : nullptr;
       cx<double>* hcoef = (cx<double>*)scr.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
       using C = std::complex<double>;
       std::vector<char> act(nrhs, 1);
@@ -2675,8 +2731,9 @@ int rss_krylov_ex(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, 
         for (int k = 0; k < mc; ++k) {
           if (std::find(run_c.begin(), run_c.end(), 1) == run_c.end()) break;
           cx<double>* w = V + (size_t)(k + 1) * vstride;
-          precond(V + (size_t)k * vstride, z);
-          A->apply(z, nullptr, w, nrhs, 0, s);
+          cx<double>* zk = Zs ? Zs + (size_t)k * vstride : z;
+          precond(V + (size_t)k * vstride, zk);
+          A->apply(zk, nullptr, w, nrhs, 0, s);
           for (int pass = 0; pass < 2; ++pass) {
             std::vector<C> hv((size_t)(k + 1) * nrhs);
             for (int j = 0; j <= k; ++j) {
@@ -2733,12 +2790,16 @@ int rss_krylov_ex(rss_handle h, rss_gridop_t A, void* Bv, int nrhs, int method, 
           for (int i = 0; i < mm; ++i) ycoef[(size_t)i * nrhs + c] = -y[i];
         }
         if (kmax > 0) {
-          HIPCHK(hipMemsetAsync(q, 0, vb, s));
           HIPCHK(hipMemcpyAsync(hcoef, ycoef.data(), (size_t)kmax * nrhs * sizeof(cx<double>),
                                 hipMemcpyHostToDevice, s));
-          launch_lincomb_sub(V, vstride, kmax, hcoef, q, N, nrhs, s);
-          precond(q, z);
-          launch_add_c128(x, z, (int64_t)tot, s);
+          if (Zs) {
+            // x += sum_j y_j Z_j (hcoef holds -y)
+            launch_lincomb_sub(Zs, vstride, kmax, hcoef, x, N, nrhs, s);
+          } else {
+            HIPCHK(hipMemsetAsync(q, 0, vb, s));
+            launch_lincomb_sub(V, vstride, kmax, hcoef, q, N, nrhs, s);
+            launch_add_c128(x, q, (int64_t)tot, s);
+          }
         }
         // the next cycle's residual, and which columns still iterate
         A->apply(x, b, V, nrhs, 1, s);

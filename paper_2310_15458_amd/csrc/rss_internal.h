@@ -108,6 +108,9 @@ struct Phase {
   // r x r complex128 work for X_RR^{-1} when it does not fit in LDS
   const int64_t* oD;
   cx<double>* Wd;
+  // solve sweeps: boxes of the phase share neighbours (four-colour
+  // schedule), so the forward sweep's neighbour updates are atomic adds
+  int atomic_nbr = 0;
 };
 
 // Workspace of the interpolative decomposition through the Gram matrix of one
@@ -204,7 +207,7 @@ void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int 
 template <class R>
 void launch_plan_y(const Prob<R>* probs, const Phase<R>& ph, GemmDesc<R>* desc, hipStream_t s);
 template <class R>
-void launch_compact(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s);
+void launch_compact(const Prob<R>* probs, const Phase<R>& ph, int colours, hipStream_t s);
 template <class R>
 void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipStream_t s);
 // Schur update of every box of the phase as one (k + |N|)^2 product per box,

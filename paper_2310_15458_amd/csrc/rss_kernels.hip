@@ -1392,6 +1392,72 @@ void launch_gemm(const GemmDesc<R>* desc, int ndesc, int max_m, int max_n, hipSt
 // drop R: every stored block of B keeps only the skeleton rows / columns
 // (in ascending order), and B's active ids shrink to S.
 // ---------------------------------------------------------------------------
+constexpr int COMPACT_PER = 8;
+
+// rows of A (ld, ncols columns): row i <- row Sl[i] for i < k; columns independent
+template <class R>
+__device__ void compact_rows(cx<R>* A, int ld, const int* Sl, int k, int ncols) {
+  constexpr int PER = COMPACT_PER;
+  const int cw = max(1, (256 * PER) / max(k, 1));
+  for (int c0 = 0; c0 < ncols; c0 += cw) {
+    const int nc = min(cw, ncols - c0);
+    cx<R> tmp[PER];
+    int cnt = 0;
+    for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+      const int i = e % k, c = c0 + e / k;
+      tmp[cnt] = A[Sl[i] + (int64_t)c * ld];
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
+      const int i = e % k, c = c0 + e / k;
+      A[i + (int64_t)c * ld] = tmp[cnt];
+    }
+    __syncthreads();
+  }
+}
+
+// columns of A (ld, nrows rows): column j <- column Sl[j] for j < k; rows independent
+template <class R>
+__device__ void compact_cols(cx<R>* A, int ld, const int* Sl, int k, int nrows) {
+  constexpr int PER = COMPACT_PER;
+  const int rw = max(1, (256 * PER) / max(k, 1));
+  for (int i0 = 0; i0 < nrows; i0 += rw) {
+    const int nr = min(rw, nrows - i0);
+    cx<R> tmp[PER];
+    int cnt = 0;
+    for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+      const int i = i0 + e % nr, j = e / nr;
+      tmp[cnt] = A[i + (int64_t)Sl[j] * ld];
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
+      const int i = i0 + e % nr, j = e / nr;
+      A[i + (int64_t)j * ld] = tmp[cnt];
+    }
+    __syncthreads();
+  }
+}
+
+// B's active ids shrink to S and its size to k
+template <class R>
+__device__ void compact_ids(const Level<R>& L, int b, const int* Sl, int k) {
+  int* gid = L.idx + L.ioff[b];
+  for (int base = 0; base < k; base += 256) {
+    const int i = base + threadIdx.x;
+    const int v = i < k ? gid[Sl[i]] : 0;
+    __syncthreads();
+    if (i < k) gid[i] = v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) L.cur[b] = k;
+}
+
+// nine colours: workgroup (slot, s) handles the stencil pair s of the box,
+// rows of A[b, b2] and columns of A[b2, b] (the diagonal block: rows, then
+// columns, then the ids).  Boxes of one colour are 3 apart: no block is
+// touched by two of them.
 template <class R>
 __global__ __launch_bounds__(256) void k_compact(const Prob<R>* probs, Phase<R> ph) {
   const int slot = blockIdx.x, b = ph.box[slot];
@@ -1404,106 +1470,59 @@ __global__ __launch_bounds__(256) void k_compact(const Prob<R>* probs, Phase<R> 
   if (b2 < 0) return;
   const int n0b = L.n0[b];
   const int* Sl = ph.Wi + ph.oI[slot];
-  constexpr int PER = 8;
   if (b2 != b) {
     const int c2 = L.cur[b2];
-    // rows of A[b, b2]: row i <- row Sl[i]; columns independent
-    {
-      cx<R>* A = block_ptr(L, b, b2);
-      const int cw = max(1, (256 * PER) / max(k, 1));
-      for (int c0 = 0; c0 < c2; c0 += cw) {
-        const int nc = min(cw, c2 - c0);
-        cx<R> tmp[PER];
-        int cnt = 0;
-        for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
-          const int i = e % k, c = c0 + e / k;
-          tmp[cnt] = A[Sl[i] + (int64_t)c * n0b];
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
-          const int i = e % k, c = c0 + e / k;
-          A[i + (int64_t)c * n0b] = tmp[cnt];
-        }
-        __syncthreads();
-      }
-    }
-    // columns of A[b2, b]: column j <- column Sl[j]; rows independent
-    {
-      cx<R>* A = block_ptr(L, b2, b);
-      const int ld = L.n0[b2];
-      const int rw = max(1, (256 * PER) / max(k, 1));
-      for (int i0 = 0; i0 < c2; i0 += rw) {
-        const int nr = min(rw, c2 - i0);
-        cx<R> tmp[PER];
-        int cnt = 0;
-        for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
-          const int i = i0 + e % nr, j = e / nr;
-          tmp[cnt] = A[i + (int64_t)Sl[j] * ld];
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
-          const int i = i0 + e % nr, j = e / nr;
-          A[i + (int64_t)j * ld] = tmp[cnt];
-        }
-        __syncthreads();
-      }
-    }
+    compact_rows(block_ptr(L, b, b2), n0b, Sl, k, c2);
+    compact_cols(block_ptr(L, b2, b), L.n0[b2], Sl, k, c2);
   } else {
     cx<R>* A = block_ptr(L, b, b);
-    const int n = L.cur[b];
-    // rows first (all n columns), then columns (first k rows)
-    const int cw = max(1, (256 * PER) / max(k, 1));
-    for (int c0 = 0; c0 < n; c0 += cw) {
-      const int nc = min(cw, n - c0);
-      cx<R> tmp[PER];
-      int cnt = 0;
-      for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
-        const int i = e % k, c = c0 + e / k;
-        tmp[cnt] = A[Sl[i] + (int64_t)c * n0b];
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int e = threadIdx.x; e < k * nc && cnt < PER; e += 256, ++cnt) {
-        const int i = e % k, c = c0 + e / k;
-        A[i + (int64_t)c * n0b] = tmp[cnt];
-      }
-      __syncthreads();
-    }
-    const int rw = max(1, (256 * PER) / max(k, 1));
-    for (int i0 = 0; i0 < k; i0 += rw) {
-      const int nr = min(rw, k - i0);
-      cx<R> tmp[PER];
-      int cnt = 0;
-      for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
-        const int i = i0 + e % nr, j = e / nr;
-        tmp[cnt] = A[i + (int64_t)Sl[j] * n0b];
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int e = threadIdx.x; e < k * nr && cnt < PER; e += 256, ++cnt) {
-        const int i = i0 + e % nr, j = e / nr;
-        A[i + (int64_t)j * n0b] = tmp[cnt];
-      }
-      __syncthreads();
-    }
-    int* gid = L.idx + L.ioff[b];
-    for (int base = 0; base < k; base += 256) {
-      const int i = base + threadIdx.x;
-      const int v = i < k ? gid[Sl[i]] : 0;
-      __syncthreads();
-      if (i < k) gid[i] = v;
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) L.cur[b] = k;
+    compact_rows(A, n0b, Sl, k, L.cur[b]);
+    compact_cols(A, n0b, Sl, k, k);
+    compact_ids(L, b, Sl, k);
   }
 }
 
+// four colours: boxes of one colour are 2 apart, so A[b, b2] of two such
+// boxes has its rows dropped by one and its columns by the other.  Pass 0:
+// rows of every A[b, .]; pass 1: columns of every A[., b]; the sizes and ids
+// change only after both (k_compact_ids), so every pass reads the sizes the
+// colour started with (rows beyond a new size are stale and never read).
 template <class R>
-void launch_compact(const Prob<R>* probs, const Phase<R>& ph, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_compact_pass(const Prob<R>* probs, Phase<R> ph, int pass) {
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  const int k = rec.k[b], r = rec.r[b];
+  if (r == 0) return;
+  const int s = blockIdx.y;
+  const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
+  if (b2 < 0) return;
+  const int* Sl = ph.Wi + ph.oI[slot];
+  if (pass == 0)
+    compact_rows(block_ptr(L, b, b2), L.n0[b], Sl, k, L.cur[b2]);
+  else
+    compact_cols(block_ptr(L, b2, b), L.n0[b2], Sl, k, b2 == b ? k : L.cur[b2]);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_compact_ids(const Prob<R>* probs, Phase<R> ph) {
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const Level<R> L = probs[ph.prob[slot]].L;
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  if (rec.r[b] == 0) return;
+  compact_ids(L, b, ph.Wi + ph.oI[slot], rec.k[b]);
+}
+
+template <class R>
+void launch_compact(const Prob<R>* probs, const Phase<R>& ph, int colours, hipStream_t s) {
   if (ph.nbox == 0) return;
-  hipLaunchKernelGGL(k_compact<R>, dim3(ph.nbox, 25), dim3(256), 0, s, probs, ph);
+  if (colours != 4) {
+    hipLaunchKernelGGL(k_compact<R>, dim3(ph.nbox, 25), dim3(256), 0, s, probs, ph);
+    return;
+  }
+  hipLaunchKernelGGL(k_compact_pass<R>, dim3(ph.nbox, 25), dim3(256), 0, s, probs, ph, 0);
+  hipLaunchKernelGGL(k_compact_pass<R>, dim3(ph.nbox, 25), dim3(256), 0, s, probs, ph, 1);
+  hipLaunchKernelGGL(k_compact_ids<R>, dim3(ph.nbox), dim3(256), 0, s, probs, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -1929,6 +1948,21 @@ __device__ __forceinline__ void sub_row(cx<R>* z, int64_t ldz, int64_t g, int c0
     if (c < nc) p[c * ldz] = o[c] - v[c];
 }
 
+// z[g + (c0 + c) ldz] -= v[c] for c < nc by atomic adds (the four-colour
+// schedule's forward sweep: boxes of a phase share neighbours; hipMalloc
+// memory is coarse-grained, so the hardware float atomics apply)
+template <class R>
+__device__ __forceinline__ void sub_row_atomic(cx<R>* z, int64_t ldz, int64_t g, int c0, int nc,
+                                               const cx<R> (&v)[SNC]) {
+  R* p = reinterpret_cast<R*>(z + g + (int64_t)c0 * ldz);
+#pragma unroll
+  for (int c = 0; c < SNC; ++c)
+    if (c < nc) {
+      unsafeAtomicAdd(p + 2 * c * ldz, -v[c].x);
+      unsafeAtomicAdd(p + 2 * c * ldz + 1, -v[c].y);
+    }
+}
+
 // LDS panel P[i * sld + c] = z[g(i) + (c0 + c) ldz] for i < n, c < nc, eight
 // loads in flight per thread
 template <class R, class Idx>
@@ -2058,8 +2092,12 @@ __global__ __launch_bounds__(256) void k_solve_fwd_fused(const SolveProb<R>* sp,
     z[gR[a] + (int64_t)(c0 + c) * ldz] = zR[a * sld + c];
   }
   const int q = k + nN;
+  const bool at = ph.atomic_nbr != 0;
   blk_mm<R, false>(XS, q, q, 0, r, w, sld, nc, red, [&](int a, const cx<R>(&v)[SNC]) {
-    sub_row(z, ldz, a < k ? gS[a] : gN[a - k], c0, nc, v);
+    if (a >= k && at)
+      sub_row_atomic(z, ldz, gN[a - k], c0, nc, v);
+    else
+      sub_row(z, ldz, a < k ? gS[a] : gN[a - k], c0, nc, v);
   });
 }
 
@@ -2093,10 +2131,14 @@ __global__ __launch_bounds__(256) void k_solve_fwd_b(const SolveProb<R>* sp, Pha
     w[a * sld + c] = Wb[(int64_t)a * ldw + c];
   }
   __syncthreads();
+  const bool at = ph.atomic_nbr != 0;
   blk_mm<R, false>(XS + a_lo, q, a_hi - a_lo, 0, r, w, sld, nc, red,
                    [&](int a, const cx<R>(&v)[SNC]) {
                      const int row = a_lo + a;
-                     sub_row(z, ldz, row < k ? gS[row] : gN[row - k], c0, nc, v);
+                     if (row >= k && at)
+                       sub_row_atomic(z, ldz, gN[row - k], c0, nc, v);
+                     else
+                       sub_row(z, ldz, row < k ? gS[row] : gN[row - k], c0, nc, v);
                    });
 }
 
@@ -2466,7 +2508,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);             \
   template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t);        \
   template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);      \
-  template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t);                   \
+  template void launch_compact<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);                   \
   template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t);                    \
   template void launch_schur<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);                \
   template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int,         \

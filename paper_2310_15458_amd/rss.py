@@ -32,7 +32,7 @@ class rss_options(ctypes.Structure):
     _fields_ = [("n_proxy", ctypes.c_int), ("proxy_radius", ctypes.c_double),
                 ("precision", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int), ("root", ctypes.c_double * 3),
-                ("stream", ctypes.c_void_p), ("profile", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("profile", ctypes.c_int), ("colours", ctypes.c_int)]
 
 
 class rss_stats(ctypes.Structure):
@@ -198,7 +198,7 @@ def _stream_ptr(stream):
 
 
 def make_options(precision="fp64", n_proxy=0, proxy_radius=0.0, refine_tol=0.0, max_refine=0,
-                 root=None, stream=None, profile=False) -> rss_options:
+                 root=None, stream=None, profile=False, colours=0) -> rss_options:
     opt = rss_options()
     opt.n_proxy = int(n_proxy)
     opt.proxy_radius = float(proxy_radius)
@@ -209,6 +209,7 @@ def make_options(precision="fp64", n_proxy=0, proxy_radius=0.0, refine_tol=0.0, 
         opt.root[0], opt.root[1], opt.root[2] = (float(v) for v in root)
     opt.stream = _stream_ptr(stream).value
     opt.profile = 1 if profile else 0
+    opt.colours = int(colours)
     return opt
 
 
@@ -217,13 +218,14 @@ class Factorization:
 
     def __init__(self, points, kern, tol: float, leaf: int, precision: str = "fp64",
                  n_proxy: int = 0, proxy_radius: float = 0.0, refine_tol: float = 0.0,
-                 max_refine: int = 0, root=None, stream=None, profile: bool = False):
+                 max_refine: int = 0, root=None, stream=None, profile: bool = False, colours: int = 0):
         lib = load()
         P = np.ascontiguousarray(points, dtype=np.float64)
         self.N = P.shape[0]
         self.kernel = kern
         self._k = make_kernel(kern)
-        opt = make_options(precision, n_proxy, proxy_radius, refine_tol, max_refine, root, stream, profile)
+        opt = make_options(precision, n_proxy, proxy_radius, refine_tol, max_refine, root, stream, profile,
+                           colours)
         self._stream = opt.stream
         h = ctypes.c_void_p()
         _check(lib.rss_factor_ex(P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.N,

@@ -27,12 +27,14 @@ static std::vector<double> grid(int n) {
   } while (0)
 
 int main() {
-  // single problem, both precisions
-  for (int prec = 0; prec < 2; ++prec) {
+  // single problem, both precisions, both schedules
+  for (int run = 0; run < 4; ++run) {
+    const int prec = run & 1;
     auto P = grid(48);
     rss_kernel k{RSS_HELMHOLTZ2D, 30.0, 1.0 / (48 * 48), 1.0, 2};
     rss_options o{};
     o.precision = (rss_precision)prec;
+    o.colours = run < 2 ? 9 : 4;
     rss_handle h;
     CHECK(rss_factor_ex(P.data(), 48 * 48, &k, 1e-6, 36, &o, &h));
     std::vector<double> B(2 * 48 * 48 * 3);

@@ -15,7 +15,7 @@ template <class R> void launch_gram(const Prob<R>*, const Phase<R>&, const GramW
 template <class R> void launch_chol(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
 template <class R> void launch_inverse(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t) {}
 template <class R> void launch_plan_y(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t) {}
-template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, hipStream_t) {}
+template <class R> void launch_compact(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_gemm(const GemmDesc<R>*, int, int, int, hipStream_t) {}
 template <class R> void launch_schur(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_assemble_pairs(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t) {}
@@ -40,7 +40,7 @@ template bool solve_fused_fits<R>(int, int, int); \
 template bool launch_cpqr_mg<R>(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, unsigned, hipStream_t); \
 template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t); \
 template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t); \
-template void launch_compact<R>(const Prob<R>*, const Phase<R>&, hipStream_t); \
+template void launch_compact<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_gemm<R>(const GemmDesc<R>*, int, int, int, hipStream_t); \
 template void launch_schur<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_assemble_pairs<R>(const PairDesc*, int, const ListEntry*, int, int, const Prob<R>*, hipStream_t); \

@@ -23,6 +23,8 @@
 #include <cstring>
 #include <functional>
 #include <exception>
+#include <limits>
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -576,6 +578,64 @@ KParams to_kp(const rss_kernel& k) {
   return p;
 }
 
+// Equal points share a cell of a 2^15 x 2^15 grid over their bounding box.
+// The (cell key, index) pairs are sorted by key -- a linear scan when they
+// already are (points listed cell by cell, e.g. a grid in row order), else
+// three 10-bit radix passes -- and the points of each cell compared exactly.
+void check_distinct(const double* points, int64_t n) {
+  if (n < 2) return;
+  double x0 = points[0], x1 = points[0], y0 = points[1], y1 = points[1];
+  for (int64_t i = 1; i < n; ++i) {
+    x0 = std::min(x0, points[2 * i]);
+    x1 = std::max(x1, points[2 * i]);
+    y0 = std::min(y0, points[2 * i + 1]);
+    y1 = std::max(y1, points[2 * i + 1]);
+  }
+  constexpr int B = 15, NB = 1 << B;
+  const double sx = x1 > x0 ? (double)NB / (x1 - x0) : 0.0, sy = y1 > y0 ? (double)NB / (y1 - y0) : 0.0;
+  std::vector<uint64_t> a((size_t)n);
+  bool sorted = true;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t cx = (uint64_t)std::min<double>(NB - 1, std::floor((points[2 * i] - x0) * sx));
+    const uint64_t cy = (uint64_t)std::min<double>(NB - 1, std::floor((points[2 * i + 1] - y0) * sy));
+    a[(size_t)i] = (((cy << B) | cx) << 32) | (uint64_t)i;
+    if (i > 0 && (a[(size_t)i] >> 32) < (a[(size_t)i - 1] >> 32)) sorted = false;
+  }
+  if (!sorted) {
+    constexpr int RB = 10, NR = 1 << RB;
+    std::vector<uint64_t> b((size_t)n);
+    std::vector<uint32_t> cnt(NR + 1);
+    for (int pass = 0; pass < 3; ++pass) {
+      std::fill(cnt.begin(), cnt.end(), 0u);
+      const int sh = 32 + pass * RB;
+      for (int64_t i = 0; i < n; ++i) cnt[((a[(size_t)i] >> sh) & (NR - 1)) + 1]++;
+      for (int d = 0; d < NR; ++d) cnt[d + 1] += cnt[d];
+      for (int64_t i = 0; i < n; ++i) b[cnt[(a[(size_t)i] >> sh) & (NR - 1)]++] = a[(size_t)i];
+      a.swap(b);
+    }
+  }
+  for (int64_t lo = 0; lo < n;) {
+    int64_t hi = lo + 1;
+    while (hi < n && (a[(size_t)hi] >> 32) == (a[(size_t)lo] >> 32)) ++hi;
+    if (hi - lo > 1) {
+      std::vector<int64_t> run;
+      for (int64_t i = lo; i < hi; ++i) run.push_back((int64_t)(a[(size_t)i] & 0xffffffffu));
+      std::sort(run.begin(), run.end(), [points](int64_t u, int64_t v) {
+        if (points[2 * u] != points[2 * v]) return points[2 * u] < points[2 * v];
+        if (points[2 * u + 1] != points[2 * v + 1]) return points[2 * u + 1] < points[2 * v + 1];
+        return u < v;
+      });
+      for (size_t i = 1; i < run.size(); ++i) {
+        const int64_t u = run[i - 1], v = run[i];
+        if (points[2 * u] == points[2 * v] && points[2 * u + 1] == points[2 * v + 1])
+          fail(RSS_EINVAL, "duplicate points " + std::to_string(std::min(u, v)) + " and " +
+                               std::to_string(std::max(u, v)));
+      }
+    }
+    lo = hi;
+  }
+}
+
 void validate(const double* points, int64_t n, const rss_kernel* k, double tol, int leaf) {
   if (!points || !k) fail(RSS_EINVAL, "null pointer argument");
   if (n < 1) fail(RSS_EINVAL, "n must be >= 1");
@@ -594,21 +654,8 @@ void validate(const double* points, int64_t n, const rss_kernel* k, double tol, 
     fail(RSS_EINVAL, "bad scattering potential parameters");
   for (int64_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(points[i])) fail(RSS_EINVAL, "non-finite point coordinate");
-  // coincident points would put K(0) (log 0, H0(0)) into the matrix: sort the
-  // (x, y) pairs and reject any repeat
-  std::vector<int64_t> ord(n);
-  for (int64_t i = 0; i < n; ++i) ord[i] = i;
-  auto less = [points](int64_t a, int64_t b) {
-    if (points[2 * a] != points[2 * b]) return points[2 * a] < points[2 * b];
-    return points[2 * a + 1] < points[2 * b + 1];
-  };
-  std::sort(ord.begin(), ord.end(), less);
-  for (int64_t i = 1; i < n; ++i) {
-    const int64_t a = ord[i - 1], b = ord[i];
-    if (points[2 * a] == points[2 * b] && points[2 * a + 1] == points[2 * b + 1])
-      fail(RSS_EINVAL, "duplicate points " + std::to_string(std::min(a, b)) + " and " +
-                           std::to_string(std::max(a, b)));
-  }
+  // coincident points would put K(0) (log 0, H0(0)) into the matrix: reject any repeat
+  check_distinct(points, n);
 }
 
 // Box coordinates at depth MAX_DEPTH: floor((p - corner) / side) clamped to the
@@ -2141,9 +2188,15 @@ void refine_step_impl(const std::vector<RefineJob*>& live, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
   }
   for (auto* j : res) {
+    // the largest column relres; a NaN in any column makes it NaN (never converged)
     j->relres = 0.0;
-    for (int c = 0; c < j->nrhs; ++c)
-      j->relres = std::max(j->relres, j->bn[c] > 0 ? j->rn[c] / j->bn[c] : 0.0);
+    for (int c = 0; c < j->nrhs; ++c) {
+      const double q = j->bn[c] > 0 ? j->rn[c] / j->bn[c] : 0.0;
+      if (std::isnan(q) || std::isnan(j->relres))
+        j->relres = std::numeric_limits<double>::quiet_NaN();
+      else
+        j->relres = std::max(j->relres, q);
+    }
     if (j->relres <= j->h->opt.refine_tol || j->it >= j->h->refine_steps) j->done = true;
     // a NaN relres never counts as an improvement
     const bool better = j->relres < j->best;

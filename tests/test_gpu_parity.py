@@ -298,6 +298,24 @@ def test_fp64_refinement(torch_cuda):
     assert F.info()["last_iters"] >= 1
 
 
+def test_nan_right_hand_side_never_converges(torch_cuda):
+    """A NaN in one column makes the refinement's relres NaN: the solve runs
+    to max_refine and reports RSS_ENOCONV instead of convergence."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n, leaf = 32, 16
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, 20.0)
+    F = rss.Factorization(P, k, 1e-6, leaf, precision="fp32", max_refine=2)
+    B = W.rhs(n * n, 3, 4)
+    B[5, 1] = np.nan
+    Bd = _dev(torch, B)
+    assert F.solve(Bd) == rss.RSS_ENOCONV
+    info = F.info()
+    assert np.isnan(info["last_relres"]) and info["last_iters"] == 2
+    F.close()
+
+
 def test_invalid_arguments(torch_cuda):
     from paper_2310_15458_amd import rss
     P = W.grid_points(8)

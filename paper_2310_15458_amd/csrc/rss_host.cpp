@@ -1675,8 +1675,10 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   int err = 0;
   HIPCHK(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
+  // a barrier timeout first: the boxes behind it were not factored, so a zero
+  // pivot found after it proves nothing (the factorization is redone)
   if (err & ERRF_TIMEOUT) throw MgTimeout{};
+  if (err & ERRF_SINGULAR) fail(RSS_ESINGULAR, "zero pivot in a redundant-block or root inverse");
   for (int p = 0; p < np; ++p) {
     rss_ctx* h = H[p];
     Work& w = W[p];
@@ -2191,7 +2193,9 @@ void refine_step_impl(const std::vector<RefineJob*>& live, hipStream_t s) {
     // the largest column relres; a NaN in any column makes it NaN (never converged)
     j->relres = 0.0;
     for (int c = 0; c < j->nrhs; ++c) {
-      const double q = j->bn[c] > 0 ? j->rn[c] / j->bn[c] : 0.0;
+      const double bnc = j->bn[c], rnc = j->rn[c];
+      const double q = (std::isnan(bnc) || std::isnan(rnc)) ? std::numeric_limits<double>::quiet_NaN()
+                                                             : (bnc > 0 ? rnc / bnc : 0.0);
       if (std::isnan(q) || std::isnan(j->relres))
         j->relres = std::numeric_limits<double>::quiet_NaN();
       else

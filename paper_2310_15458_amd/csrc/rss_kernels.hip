@@ -1311,13 +1311,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc<R>* desc, int tiles
   }
 }
 
-// Schur update of one box (eq. e:step) as one product:
+// Schur update of one box (eq. e:step) as one product (three waves per SIMD:
+// the tiles are latency-bound chains, and a third resident workgroup per CU
+// covers more of them than the registers it takes cost; four spill):
 //   [A_SS A_SN; A_NS A_NN] -= [X_SR; X_NR] Y,   Y = X_RR^{-1} [X_RS X_RN],
 // rows and columns ordered [S; N_1 .. N_8] (Q = k + |N|).  Workgroup (slot, tile)
 // computes a 64 x 64 tile of the Q x Q product and subtracts each element from
 // the stencil block of its row box and column box.
 template <class R>
-__global__ __launch_bounds__(256) void k_schur(const Prob<R>* probs, Phase<R> ph, int tiles_q) {
+__global__ __launch_bounds__(256, 3) void k_schur(const Prob<R>* probs, Phase<R> ph, int tiles_q) {
   __shared__ cx<R>* bp[9][9];
   __shared__ int ldr[9];
   __shared__ unsigned char rbk[64], cbk[64];

@@ -916,6 +916,11 @@ void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStre
   hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(RSS_SPARSIFY_NT), shm, s, probs, ph, nmax, tcap);
 }
 
+// v - c s in complex FP64, four FMAs
+__device__ __forceinline__ cx<double> sub_mul(cx<double> v, cx<double> c, cx<double> s) {
+  return {fma(-c.x, s.x, fma(c.y, s.y, v.x)), fma(-c.x, s.y, fma(-c.y, s.x, v.y))};
+}
+
 // ---------------------------------------------------------------------------
 // X_RR^{-1} by Gauss-Jordan elimination with partial pivoting (the LU of
 // eq. e:step, kept as an explicit inverse), in FP64 in both forms: X_RR is as
@@ -926,7 +931,7 @@ void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStre
 // ---------------------------------------------------------------------------
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> ph, int* errflag,
-                                                size_t lds_off, size_t lds_cap) {
+                                                size_t lds_off, size_t lds_cap, int rmin) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NW = NT / 64;
   __shared__ double rv[NW];
@@ -934,7 +939,7 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
   const int slot = blockIdx.x, b = ph.box[slot];
   const Records<R> rec = probs[ph.prob[slot]].rec;
   const int r = rec.r[b];
-  if (r == 0) return;
+  if (r <= rmin) return;  // empty, or inverted by k_inverse_reg
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // LDS: pivot column, scaled pivot row, pivot rows, column map; then the block if it fits
   cx<double>* colk = reinterpret_cast<cx<double>*>(smem_raw);
@@ -1018,7 +1023,7 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
       cx<double> v;
       if (i == kk) v = rowk[j];
       else if (j == kk) v = czero<double>() - colk[i] * pinv;
-      else v = A[e] - colk[i] * rowk[j];
+      else v = sub_mul(A[e], colk[i], rowk[j]);
       A[e] = v;
       if (j == kk + 1 && i > kk) {
         const double a2 = abs2d(v);
@@ -1054,10 +1059,240 @@ __global__ __launch_bounds__(NT) void k_inverse(const Prob<R>* probs, Phase<R> p
   }
 }
 
+// lane moves within rows of 16 lanes (DPP controls): exchange with lane ^ 1,
+// with lane ^ 2, lane i with 7 - i of its half-row, lane i with 15 - i
+enum { DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141 };
+template <int CTL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTL, 0xF, 0xF, false);
+}
+template <int CTL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = dpp_i<CTL>((int)(unsigned)u), hi = dpp_i<CTL>((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>)
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// The same elimination for blocks held in registers: a TI x TJ grid of
+// threads, thread (ti, tj) owning the entries (ti + TI a, tj + TJ c),
+// a < RA, c < RC, for blocks of up to min(TI RA, TJ RC) rows.  Rows are not
+// interchanged: the pivot row of step kk stays where it is and two tables
+// (the position of each row in the row-interchanging form above, and the row
+// at each position) record the interchanges, so the pivot choices and their
+// tie rule are those of k_inverse.  Entry (i, j) of the eliminated block is
+// entry (position of i, row at position j) of the inverse.
+// A step has two barriers: after the pivot row (scaled) is posted to LDS, and
+// after the next pivot is chosen.  The TI threads holding column kk + 1 (a
+// wave's lanes) update that column first, post it for the next step and
+// choose its pivot with its reciprocal while the other waves update the
+// rest; every entry is updated as v - c s, and the pivot row and column are
+// then rewritten by the few threads holding them.  The steps are unrolled by
+// column block, so that the blocks of columns kk and kk + 1 are known at
+// compile time.
+template <class R, int TI, int TJ, int RA, int RC>
+__global__ __launch_bounds__(TI * TJ) void k_inverse_reg(const Prob<R>* probs, Phase<R> ph, int* errflag) {
+  static_assert(TI == 16 || TI == 32, "a column's holders are one or two rows of lanes of a wave");
+  constexpr int RM = TI * RA < TJ * RC ? TI * RA : TJ * RC;
+  constexpr int NT = TI * TJ;
+  __shared__ cx<double> colk[2][TI * RA], rowk[TJ * RC];
+  __shared__ int pos[TI * RA], rowat[TI * RA];
+  __shared__ double selv[2];
+  __shared__ int selr[2];
+  __shared__ cx<double> selinv[2];  // 1 / the chosen pivot
+  const int slot = blockIdx.x, b = ph.box[slot];
+  const Records<R> rec = probs[ph.prob[slot]].rec;
+  const int r = rec.r[b];
+  if (r == 0 || r > RM) return;  // larger blocks: k_inverse
+  const int ti = (int)threadIdx.x % TI, tj = (int)threadIdx.x / TI;
+  const cx<R>* X = ph.W + ph.oX[slot];
+  cx<double> v[RA][RC];
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      const int i = ti + TI * a, j = tj + TJ * c;
+      v[a][c] = (i < r && j < r) ? to_d(X[i + (int64_t)j * r]) : czero<double>();
+    }
+  for (int i = threadIdx.x; i < TI * RA; i += NT) {
+    pos[i] = i;
+    rowat[i] = i;
+  }
+  // by the TI threads holding column c (block C of their entries): post the
+  // column to colk[c & 1] and choose its pivot among the rows at positions
+  // >= c (largest |.|^2, the smallest position on ties) into slot c & 1 with
+  // its reciprocal, then interchange positions c and that of the pivot row.
+  // The choice is a reduction over the TI lanes: lane moves within rows of
+  // 16 lanes (quad exchanges, then the half-row and row mirrors), and a
+  // shuffle between the two rows of a 32-lane group.
+  auto post_and_search = [&](auto Cc, int c) __attribute__((always_inline)) {
+    constexpr int C = decltype(Cc)::value;
+    const int q = rowat[c];
+    double best = -1.0, dx = 0.0, dy = 0.0;
+    int key = 0;  // position * 256 + row
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const int i = ti + TI * a;
+      colk[c & 1][i] = v[a][C];
+      if (i >= r) continue;
+      const int pi = pos[i];
+      const double a2 = abs2d(v[a][C]);
+      const int k2 = pi * 256 + i;
+      if (pi >= c && (a2 > best || (a2 == best && k2 < key))) {
+        best = a2;
+        key = k2;
+        dx = v[a][C].x;
+        dy = v[a][C].y;
+      }
+    }
+    auto take = [&](double b2, int k2, double x2, double y2) __attribute__((always_inline)) {
+      if (b2 > best || (b2 == best && k2 < key)) {
+        best = b2;
+        key = k2;
+        dx = x2;
+        dy = y2;
+      }
+    };
+    auto dpp_round = [&](auto Ctl) __attribute__((always_inline)) {
+      constexpr int CTL = decltype(Ctl)::value;
+      take(dpp_d<CTL>(best), dpp_i<CTL>(key), dpp_d<CTL>(dx), dpp_d<CTL>(dy));
+    };
+    dpp_round(std::integral_constant<int, DPP_QUAD_XOR1>{});
+    dpp_round(std::integral_constant<int, DPP_QUAD_XOR2>{});
+    dpp_round(std::integral_constant<int, DPP_ROW_HALF_MIRROR>{});
+    dpp_round(std::integral_constant<int, DPP_ROW_MIRROR>{});
+    if constexpr (TI == 32)
+      take(__shfl_xor(best, 16, 64), __shfl_xor(key, 16, 64), __shfl_xor(dx, 16, 64), __shfl_xor(dy, 16, 64));
+    if (ti == 0) {
+      const int pr = key & 255, pp = key >> 8;
+      const double inv = 1.0 / best;
+      selv[c & 1] = best;
+      selr[c & 1] = pr;
+      selinv[c & 1] = cx<double>{dx * inv, -dy * inv};
+      if (best > 0.0) {
+        rowat[c] = pr;
+        rowat[pp] = q;
+        pos[pr] = c;
+        pos[q] = pp;
+      }
+    }
+  };
+  // step kk, its column in block KB and column kk + 1 in block C1; false if
+  // the block is singular
+  auto step = [&](auto KBc, auto C1c, int kk) __attribute__((always_inline)) -> bool {
+    constexpr int KB = decltype(KBc)::value, C1 = decltype(C1c)::value;
+    const int buf = kk & 1;
+    __syncthreads();
+    const double best = selv[buf];
+    const int p = selr[buf];
+    if (!(best > 0.0)) return false;  // uniform: every thread read the same pivot
+    const cx<double> pinv = selinv[buf];
+    const bool prow = ti == p % TI, pcol = tj == kk % TJ;
+    const int ap = p / TI;
+    // The row of v at the runtime block ap is reached by one branch per
+    // block; the empty asm with the block number keeps the compiler from
+    // merging the branches into an access through a selected pointer, which
+    // would move v out of registers.
+    if (prow) {  // the pivot row, scaled: row p of the result
+      static_for<0, RA>([&](auto Ac) __attribute__((always_inline)) {
+        constexpr int A = decltype(Ac)::value;
+        if (A == ap) {
+#pragma unroll
+          for (int c = 0; c < RC; ++c) rowk[tj + TJ * c] = (c == KB && pcol) ? pinv : v[A][c] * pinv;
+          __asm__ volatile("; row block %0" ::"i"(A));
+        }
+      });
+    }
+    __syncthreads();
+    cx<double> rs[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) rs[c] = rowk[tj + TJ * c];
+    const cx<double>* col = colk[buf] + ti;  // column kk at rows ti + TI a
+    // column kk + 1 first, by its holders (its final values: row p included)
+    const bool first = kk + 1 < r && tj == (kk + 1) % TJ;
+    if (first) {
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
+        v[a][C1] = ti + TI * a == p ? rs[C1] : sub_mul(v[a][C1], col[TI * a], rs[C1]);
+      post_and_search(C1c, kk + 1);
+    }
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      const cx<double> ca = col[TI * a];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c != C1) v[a][c] = sub_mul(v[a][c], ca, rs[c]);
+      if (!first) v[a][C1] = sub_mul(v[a][C1], ca, rs[C1]);
+    }
+    if (pcol) {
+#pragma unroll
+      for (int a = 0; a < RA; ++a) v[a][KB] = czero<double>() - col[TI * a] * pinv;
+    }
+    if (prow) {
+      static_for<0, RA>([&](auto Ac) __attribute__((always_inline)) {
+        constexpr int A = decltype(Ac)::value;
+        if (A == ap) {
+#pragma unroll
+          for (int c = 0; c < RC; ++c) v[A][c] = rs[c];
+          __asm__ volatile("; row block %0" ::"i"(A));
+        }
+      });
+    }
+    return true;
+  };
+  __syncthreads();
+  if (tj == 0) post_and_search(std::integral_constant<int, 0>{}, 0);
+  bool ok = true;
+  static_for<0, RC>([&](auto KBc) __attribute__((always_inline)) {
+    constexpr int KB = decltype(KBc)::value;
+    constexpr int NB = KB + 1 < RC ? KB + 1 : KB;  // block of the column after this block
+    for (int kr = 0; ok && kr < TJ - 1 && KB * TJ + kr < r; ++kr) ok = step(KBc, KBc, KB * TJ + kr);
+    if (ok && KB * TJ + TJ - 1 < r) ok = step(KBc, std::integral_constant<int, NB>{}, KB * TJ + TJ - 1);
+  });
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(errflag, ERRF_SINGULAR);
+    return;
+  }
+  __syncthreads();
+  cx<R>* Aout = rec.F + rec.oXi[b];
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      const int i = ti + TI * a, j = tj + TJ * c;
+      if (i < r && j < r) Aout[pos[i] + (int64_t)rowat[j] * r] = from_cd<R>(v[a][c]);
+    }
+}
+
 template <class R>
 void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s) {
   if (ph.nbox == 0) return;
+  // blocks of up to 128 rows in registers: 1024 threads (2 x 2, 3 x 3 or
+  // 4 x 4 entries each), 512 (2 x 4) where many boxes share the CUs
+  int rreg;
+  if (nmax <= 64 && ph.nbox >= 256) {
+    hipLaunchKernelGGL((k_inverse_reg<R, 32, 16, 2, 4>), dim3(ph.nbox), dim3(512), 0, s, probs, ph, errflag);
+    rreg = 64;
+  } else if (nmax <= 64) {
+    hipLaunchKernelGGL((k_inverse_reg<R, 32, 32, 2, 2>), dim3(ph.nbox), dim3(1024), 0, s, probs, ph, errflag);
+    rreg = 64;
+  } else if (nmax <= 96) {
+    hipLaunchKernelGGL((k_inverse_reg<R, 32, 32, 3, 3>), dim3(ph.nbox), dim3(1024), 0, s, probs, ph, errflag);
+    rreg = 96;
+  } else {
+    hipLaunchKernelGGL((k_inverse_reg<R, 32, 32, 4, 4>), dim3(ph.nbox), dim3(1024), 0, s, probs, ph, errflag);
+    rreg = 128;
+  }
+  if (nmax <= rreg) return;
   const size_t E = sizeof(cx<double>);
   const size_t head = ((size_t)nmax * (2 * E + 2 * sizeof(int)) + 15) & ~(size_t)15;
   // the block itself in LDS up to 96 KiB (r <= 78) where many boxes share the
@@ -1067,8 +1302,7 @@ void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int 
   const size_t cap = std::min({(size_t)nmax * nmax, ph.nbox <= 512 ? room / E : (size_t)(96 * 1024) / E, room / E});
   const size_t shm = head + cap * E;
   hipLaunchKernelGGL((k_inverse<R, RSS_INVERSE_NT>), dim3(ph.nbox), dim3(RSS_INVERSE_NT), shm, s, probs, ph,
-                     errflag, head,
-                     cap);
+                     errflag, head, cap, rreg);
 }
 
 // ---------------------------------------------------------------------------

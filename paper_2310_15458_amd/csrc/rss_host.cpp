@@ -1220,7 +1220,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
           G.oG.push_back(o);
           o += 2 * nn;
           G.oR.push_back(o);
-          o += nn;
+          o += 2 * nn;  // rows of R: high and low parts
           G.oP.push_back(o);
           if (G.chunks > 1) o += (int64_t)G.chunks * 2 * nn;
         }

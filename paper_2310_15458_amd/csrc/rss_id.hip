@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rss_internal.h"
 
@@ -283,28 +284,69 @@ void launch_gram(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int
                        0, s, probs, ph, gw);
 }
 
-// ---------------------------------------------------------------------------
-// pivoted Cholesky factorization of G in double-double, one workgroup per box.
-// The upper triangle of G (hi and lo parts) is worked on in LDS, packed by
-// columns (boxes of up to GRAM_NLDS points), else in place in the workspace.
-// Per pivot step: one wave takes the pivot (largest trailing norm
-// sqrt(G_cc) among the remaining columns, smallest global id within TIE of
-// it) and the truncation test against tol * nu0; one thread per column forms
-// R(j, c) = G(p, c) / sqrt(G(p, p)); the waves subtract R(j, i) R(j, c) from
-// the remaining entries, a column per wave at a time.  Rows of R (FP64) go to
-// the workspace; T = R11^{-1} R12 by back substitution, one thread per
-// redundant column.
-// ---------------------------------------------------------------------------
-constexpr int GRAM_NLDS = 128;
+// max / min over the 64 lanes of a wave, in every lane: lane moves within
+// rows of 16 lanes (exchange with lane ^ 1, lane ^ 2, then the half-row and
+// row mirrors), then shuffles across rows
+template <int CTL>
+__device__ __forceinline__ int dpp_mov(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTL, 0xF, 0xF, false);
+}
+template <int CTL>
+__device__ __forceinline__ unsigned long long dpp_mov64(unsigned long long x) {
+  const int lo = dpp_mov<CTL>((int)(unsigned)x), hi = dpp_mov<CTL>((int)(x >> 32));
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  auto mv = [](T x, auto ctl) {
+    unsigned long long u;
+    __builtin_memcpy(&u, &x, 8);
+    u = dpp_mov64<decltype(ctl)::value>(u);
+    T y;
+    __builtin_memcpy(&y, &u, 8);
+    return y;
+  };
+  v = op(v, mv(v, std::integral_constant<int, 0xB1>{}));   // lane ^ 1
+  v = op(v, mv(v, std::integral_constant<int, 0x4E>{}));   // lane ^ 2
+  v = op(v, mv(v, std::integral_constant<int, 0x141>{}));  // 7 - lane in half-rows
+  v = op(v, mv(v, std::integral_constant<int, 0x140>{}));  // 15 - lane in rows
+  v = op(v, __shfl_xor(v, 16, 64));
+  v = op(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
+}
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
+  return wave_reduce(v, [](unsigned long long a, unsigned long long b) { return b < a ? b : a; });
+}
 
-template <class R, int NT, bool SHARED>
-__global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, GramWs gw) {
-  constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) double csm[];
-  __shared__ double qh[GRAM_NMAX], ql[GRAM_NMAX];
+// ---------------------------------------------------------------------------
+// pivoted Cholesky factorization of G in double-double, one workgroup per box,
+// one thread per column, in left-looking form: a pivot step forms only the
+// pivot's row of the trailing matrix, from G and the earlier rows of R, and
+// updates the trailing diagonal in place.  Per pivot step:
+//   * one wave takes the pivot (largest trailing norm sqrt(G_cc) among the
+//     remaining columns, smallest global id within TIE of it) and the
+//     truncation test against tol * nu0, and forms R(j, p) = sqrt(G(p, p));
+//   * the thread of each remaining column c forms
+//       G(p, c) - sum_{q < j} R(q, p) R(q, c),  q in increasing order,
+//     then R(j, c) = that / R(j, p) and G(c, c) -= R(j, c)^2.
+// Each entry takes exactly the double-double operations, in the same order,
+// that a right-looking elimination (subtracting R(j, i) R(j, c) from every
+// remaining entry after each pivot step) applies to it, so the factorization
+// is that one, at O(k^2 n) instead of O(k n^2) work and without writing the
+// trailing matrix.  Rows of R (FP64 high and low parts) go to the workspace;
+// T = R11^{-1} R12 by back substitution, one thread per redundant column.
+// ---------------------------------------------------------------------------
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, GramWs gw, int kl) {
+  extern __shared__ double2 Rs[];  // rows q < kl of R, (high, low) at q n + c
+  __shared__ double dh[GRAM_NMAX], dl[GRAM_NMAX];  // trailing diagonal
+  __shared__ double nrm[GRAM_NMAX];                // sqrt(max(dh, 0))
   __shared__ int rem[GRAM_NMAX], piv[GRAM_NMAX], rank[GRAM_NMAX], gidv[GRAM_NMAX];
   __shared__ int sh_p;
-  __shared__ double sh_nu0;
+  __shared__ double sh_nu0, sh_rh, sh_rl;
   const int slot = blockIdx.x, b = ph.box[slot];
   const Prob<R>& pr = probs[ph.prob[slot]];
   const Level<R> L = pr.L;
@@ -314,25 +356,17 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
   if (n == 0) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nn = (int64_t)n * n;
-  double* Gg = gw.G + gw.oG[slot];
-  double* Rw = gw.Rw + gw.oR[slot];
+  const double* Gg = gw.G + gw.oG[slot];  // upper triangle: G(i, j) at i + j n, i <= j
+  double* Rw = gw.Rw + gw.oR[slot];       // row q of R at Rw + q n (high parts)
+  double* Rl = Rw + nn;                   // low parts
   const int* gid = L.idx + L.ioff[b];
-  const int64_t ne = (int64_t)n * (n + 1) / 2;
-  double* gh = SHARED ? csm : Gg;
-  double* gl = SHARED ? csm + ne : Gg + nn;
-  auto at = [n](int i, int j) -> int64_t {
-    return SHARED ? (int64_t)j * (j + 1) / 2 + i : i + (int64_t)j * n;
-  };
-  if (SHARED) {
-    for (int j = wv; j < n; j += NW)
-      for (int i = lane; i <= j; i += 64) {
-        gh[at(i, j)] = Gg[i + (int64_t)j * n];
-        gl[at(i, j)] = Gg[nn + i + (int64_t)j * n];
-      }
-  }
-  for (int c = threadIdx.x; c < n; c += NT) {
+  const int c = threadIdx.x;  // this thread's column (NT >= n)
+  if (c < n) {
     rem[c] = 1;
     gidv[c] = gid[c];
+    dh[c] = Gg[c + (int64_t)c * n];
+    dl[c] = Gg[nn + c + (int64_t)c * n];
+    nrm[c] = sqrt(fmax(dh[c], 0.0));
   }
   __syncthreads();
   int k = 0;
@@ -340,26 +374,21 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
   for (int j = 0; j < jmax; ++j) {
     if (wv == 0) {
       double mx = 0.0;
-      for (int c = lane; c < n; c += 64)
-        if (rem[c]) mx = fmax(mx, sqrt(fmax(gh[at(c, c)], 0.0)));
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      for (int cc = lane; cc < n; cc += 64)
+        if (rem[cc]) mx = fmax(mx, nrm[cc]);
+      mx = wave_max(mx);
       if (j == 0 && lane == 0) sh_nu0 = mx;
       const double nu0 = j == 0 ? mx : sh_nu0;
       int best = -1;
       if (!(mx <= tol * nu0)) {
         const double thr = (1.0 - TIE) * mx;
         unsigned long long key = ~0ull;
-        for (int c = lane; c < n; c += 64)
-          if (rem[c] && sqrt(fmax(gh[at(c, c)], 0.0)) >= thr) {
-            const unsigned long long kc = ((unsigned long long)(unsigned)gidv[c] << 32) | (unsigned)c;
+        for (int cc = lane; cc < n; cc += 64)
+          if (rem[cc] && nrm[cc] >= thr) {
+            const unsigned long long kc = ((unsigned long long)(unsigned)gidv[cc] << 32) | (unsigned)cc;
             key = kc < key ? kc : key;
           }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const unsigned long long ko = __shfl_xor(key, o, 64);
-          key = ko < key ? ko : key;
-        }
+        key = wave_min(key);
         best = (int)(unsigned)(key & 0xffffffffu);
       }
       if (lane == 0) {
@@ -367,41 +396,71 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
         if (best >= 0) {
           rem[best] = 0;
           piv[j] = best;
+          dd_sqrt(dh[best], dl[best], sh_rh, sh_rl);
         }
       }
     }
     __syncthreads();
     const int p = sh_p;
     if (p < 0) break;
-    {
-      double rh, rl;
-      dd_sqrt(gh[at(p, p)], gl[at(p, p)], rh, rl);
-      for (int c = threadIdx.x; c < n; c += NT) {
-        if (c == p) {
-          Rw[(int64_t)j * n + p] = rh;
-        } else if (rem[c]) {
-          const int64_t e = c < p ? at(c, p) : at(p, c);
-          double a, a2;
-          dd_div(gh[e], gl[e], rh, rl, a, a2);
-          qh[c] = a;
-          ql[c] = a2;
-          Rw[(int64_t)j * n + c] = a;
+    if (c == p) {
+      Rw[(int64_t)j * n + p] = sh_rh;
+    } else if (c < n && rem[c]) {
+      const int i0 = min(c, p), i1 = max(c, p);
+      double gh = Gg[i0 + (int64_t)i1 * n], gl = Gg[nn + i0 + (int64_t)i1 * n];
+      // rows of R in groups of CH, all of a group's loads issued before its
+      // subtractions (which stay in row order): rows below kl from LDS, the
+      // rest from the workspace.  Past the last row a group subtracts zero,
+      // which leaves the double-double (normalized by the subtraction before
+      // it) exactly as it is; no branch, so the loads stay ahead of the
+      // arithmetic.
+      constexpr int CH = 8;
+      const int jl = min(j, kl);
+      for (int q0 = 0; q0 < jl; q0 += CH) {
+        double2 vc[CH], vp[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int q = min(q0 + u, jl - 1);
+          vc[u] = Rs[q * n + c];
+          vp[u] = Rs[q * n + p];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          double ph_, pl_;
+          dd_mul(vc[u].x, vc[u].y, vp[u].x, vp[u].y, ph_, pl_);
+          const bool in = q0 + u < jl;
+          dd_add(gh, gl, in ? -ph_ : -0.0, in ? -pl_ : -0.0, gh, gl);
         }
       }
-    }
-    __syncthreads();
-    for (int jj = wv; jj < n; jj += NW) {
-      if (!rem[jj]) continue;
-      const double qjh = qh[jj], qjl = ql[jj];
-      for (int i = lane; i <= jj; i += 64)
-        if (rem[i]) {
-          const int64_t e = at(i, jj);
-          double ph_, pl_, nh, nl;
-          dd_mul(qh[i], ql[i], qjh, qjl, ph_, pl_);
-          dd_add(gh[e], gl[e], -ph_, -pl_, nh, nl);
-          gh[e] = nh;
-          gl[e] = nl;
+      for (int q0 = jl; q0 < j; q0 += CH) {
+        double ach[CH], acl[CH], aph[CH], apl[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int64_t o = (int64_t)min(q0 + u, j - 1) * n;
+          ach[u] = Rw[o + c];
+          acl[u] = Rl[o + c];
+          aph[u] = Rw[o + p];
+          apl[u] = Rl[o + p];
         }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          double ph_, pl_;
+          dd_mul(ach[u], acl[u], aph[u], apl[u], ph_, pl_);
+          const bool in = q0 + u < j;
+          dd_add(gh, gl, in ? -ph_ : -0.0, in ? -pl_ : -0.0, gh, gl);
+        }
+      }
+      double a, a2;
+      dd_div(gh, gl, sh_rh, sh_rl, a, a2);
+      Rw[(int64_t)j * n + c] = a;
+      Rl[(int64_t)j * n + c] = a2;
+      if (j < kl) Rs[j * n + c] = double2{a, a2};
+      double ph_, pl_, nh, nl;
+      dd_mul(a, a2, a, a2, ph_, pl_);
+      dd_add(dh[c], dl[c], -ph_, -pl_, nh, nl);
+      dh[c] = nh;
+      dl[c] = nl;
+      nrm[c] = sqrt(fmax(nh, 0.0));
     }
     __syncthreads();
     k = j + 1;
@@ -419,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
   int* Rloc = Sloc + n0b;
   for (int a = threadIdx.x; a < n; a += NT) {
     int rk = 0;
-    for (int c = 0; c < a; ++c) rk += rem[c] == rem[a];
+    for (int cc = 0; cc < a; ++cc) rk += rem[cc] == rem[a];
     rank[a] = rk;
     if (rem[a]) Rloc[rk] = a;
     else Sloc[rk] = a;
@@ -428,14 +487,14 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
   if (k == 0 || r == 0) return;
   // T = R11^{-1} R12 in place of R12: column c, rows in pivot order
   cx<R>* Tout = rec.F + rec.oT[b];
-  for (int c = threadIdx.x; c < n; c += NT) {
-    if (!rem[c]) continue;
+  for (int cc = threadIdx.x; cc < n; cc += NT) {
+    if (!rem[cc]) continue;
     for (int i = k - 1; i >= 0; --i) {
-      double sacc = Rw[(int64_t)i * n + c];
-      for (int q = i + 1; q < k; ++q) sacc = fma(-Rw[(int64_t)i * n + piv[q]], Rw[(int64_t)q * n + c], sacc);
+      double sacc = Rw[(int64_t)i * n + cc];
+      for (int q = i + 1; q < k; ++q) sacc = fma(-Rw[(int64_t)i * n + piv[q]], Rw[(int64_t)q * n + cc], sacc);
       const double x = sacc / Rw[(int64_t)i * n + piv[i]];
-      Rw[(int64_t)i * n + c] = x;
-      Tout[rank[piv[i]] + (int64_t)k * rank[c]] = from_d<R>(x, 0.0);
+      Rw[(int64_t)i * n + cc] = x;
+      Tout[rank[piv[i]] + (int64_t)k * rank[cc]] = from_d<R>(x, 0.0);
     }
   }
 }
@@ -443,13 +502,19 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
 template <class R>
 void launch_chol(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  const size_t shm = (size_t)nmax * (nmax + 1) * sizeof(double);  // hi and lo triangles
+  static_assert(GRAM_NMAX <= 192, "one thread per column, at most three waves");
+  // leading rows of R in LDS: up to 64 KiB per box where many boxes share the
+  // CUs, else up to 148 KiB
+  const size_t row = (size_t)std::max(1, nmax) * sizeof(double2);
+  const size_t budget = ph.nbox >= 256 ? (size_t)64 * 1024 : (size_t)148 * 1024;
+  const int kl = (int)std::min<size_t>((size_t)nmax, budget / row);
+  const size_t shm = (size_t)kl * row;
   if (nmax <= 64)
-    hipLaunchKernelGGL((k_chol<R, 256, true>), dim3(ph.nbox), dim3(256), shm, s, probs, ph, gw);
-  else if (nmax <= GRAM_NLDS)
-    hipLaunchKernelGGL((k_chol<R, 512, true>), dim3(ph.nbox), dim3(512), shm, s, probs, ph, gw);
+    hipLaunchKernelGGL((k_chol<R, 64>), dim3(ph.nbox), dim3(64), shm, s, probs, ph, gw, kl);
+  else if (nmax <= 128)
+    hipLaunchKernelGGL((k_chol<R, 128>), dim3(ph.nbox), dim3(128), shm, s, probs, ph, gw, kl);
   else
-    hipLaunchKernelGGL((k_chol<R, 1024, false>), dim3(ph.nbox), dim3(1024), 0, s, probs, ph, gw);
+    hipLaunchKernelGGL((k_chol<R, 192>), dim3(ph.nbox), dim3(192), shm, s, probs, ph, gw, kl);
 }
 
 template void launch_gram<double>(const Prob<double>*, const Phase<double>&, const GramWs&, int, hipStream_t);

@@ -118,7 +118,8 @@ struct Phase {
 //  part : per slot, `chunks` partial Gram matrices, each hi (n x n) then lo
 //  G    : per slot, the summed Gram matrix, hi then lo (aliases part when
 //         chunks == 1)
-//  Rw   : per slot, n x n: the rows of the pivoted Cholesky factor, then T
+//  Rw   : per slot, 2 (n x n): the rows of the pivoted Cholesky factor (high
+//         parts, then T in their place), then their low parts
 struct GramWs {
   double* part;
   const int64_t* oP;

@@ -36,10 +36,7 @@ namespace rss {
 #ifndef RSS_CPQR_CB
 #define RSS_CPQR_CB 2
 #endif
-// threads per workgroup of the sparsification and of the redundant-block inverse
-#ifndef RSS_SPARSIFY_NT
-#define RSS_SPARSIFY_NT 1024
-#endif
+// threads per workgroup of the redundant-block inverse for blocks past 128 rows
 #ifndef RSS_INVERSE_NT
 #define RSS_INVERSE_NT 512
 #endif
@@ -787,23 +784,72 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 // part 0: the box's own block; part 1 + j: neighbour j (ascending id).
 // ---------------------------------------------------------------------------
 // sum over s < k of term(s), two accumulators (independent loads in flight)
-template <class F>
-__device__ __forceinline__ cx<double> dot2(int k, F&& term) {
-  cx<double> u0{0.0, 0.0}, u1{0.0, 0.0};
-  int s = 0;
-#pragma unroll 4
-  for (; s + 1 < k; s += 2) {
-    u0 = u0 + term(s);
-    u1 = u1 + term(s + 1);
+// out(i, c) = base(i, c) - sum_s G(s, i) t(s, c), i < M, c < r, for the
+// products of the sparsification: G(s, i) = g(i, s) (a gathered block of A)
+// staged in LDS IC rows i at a time ([s][i], the loads ordered i-fast or
+// s-fast as the source is laid out), t = T (real, k x r) in LDS ([c][s]);
+// each thread a 2 x 4 tile of outputs, sums in FP64.
+template <class R, int NT, bool SFAST, class Gf, class Base, class Dst>
+__device__ __forceinline__ void sp_gemm(int M, int k, int r, const double* Tl, cx<R>* Gs, int IC, Gf g,
+                                        Base base, Dst dst) {
+  for (int i0 = 0; i0 < M; i0 += IC) {
+    const int mi = min(IC, M - i0);
+    __syncthreads();  // the previous chunk's readers are done
+    if (SFAST) {
+      for (int e = threadIdx.x; e < k * mi; e += NT) {
+        const int ss = e % k, i = e / k;
+        Gs[ss * IC + i] = g(i0 + i, ss);
+      }
+    } else {
+      for (int e = threadIdx.x; e < k * mi; e += NT) {
+        const int i = e % mi, ss = e / mi;
+        Gs[ss * IC + i] = g(i0 + i, ss);
+      }
+    }
+    __syncthreads();
+    const int np = (mi + 1) / 2, nq = (r + 3) / 4;
+    for (int t = threadIdx.x; t < np * nq; t += NT) {
+      const int i = 2 * (t % np), c = 4 * (t / np);
+      const int i1 = min(i + 1, mi - 1);
+      int cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cc[u] = min(c + u, r - 1) * k;
+      cx<double> acc[2][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[0][u] = acc[1][u] = czero<double>();
+      for (int ss = 0; ss < k; ++ss) {
+        const cx<double> g0 = to_d(Gs[ss * IC + i]), g1 = to_d(Gs[ss * IC + i1]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double tv = Tl[cc[u] + ss];
+          acc[0][u].x = fma(g0.x, tv, acc[0][u].x);
+          acc[0][u].y = fma(g0.y, tv, acc[0][u].y);
+          acc[1][u].x = fma(g1.x, tv, acc[1][u].x);
+          acc[1][u].y = fma(g1.y, tv, acc[1][u].y);
+        }
+      }
+#pragma unroll
+      for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + a2 < mi && c + u < r) dst(i0 + i + a2, c + u, base(i0 + i + a2, c + u) - acc[a2][u]);
+    }
   }
-  if (s < k) u0 = u0 + term(s);
-  return u0 + u1;
 }
 
-// LDS: the S and R index lists, then T (k x r) when k r <= tcap
-template <class R>
-__global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph, int nmax,
-                                                             int tcap) {
+// Sparsification of box b (eqs. e:con / e:step): with T (k x r, real: the ID
+// of a real Gram matrix) and the index lists S, R of the ID,
+//   part 0 (the box itself, A = A_bb):
+//     X_SR = A_SR - A_SS T           -> rows 0..k-1 of the record's X_{S+N,R}
+//     X_RR = A_RR - A_RS T - T^T X_SR (X_SR as stored)
+//   part j = 1..8 (neighbour n_j, cn points):
+//     X_{n_j R} = A_{n_j R} - A_{n_j S} T, Z_{R n_j} = A_{R n_j} - T^T A_{S n_j}
+//   part 9: Z_RS = A_RS - T^T A_SS   -> columns 0..k-1 of Z (r x (k + nN)).
+// Every product runs through sp_gemm; T^T X_SR is formed first (FP64, in the
+// phase's FP64 workspace, transposed) and folded into the base of X_RR.
+// LDS: the S and R lists, T, then the staging rows.
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph, int nmax, int ic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int slot = blockIdx.x, b = ph.box[slot];
   const Level<R> L = probs[ph.prob[slot]].L;
@@ -828,92 +874,101 @@ __global__ __launch_bounds__(RSS_SPARSIFY_NT) void k_sparsify(const Prob<R>* pro
     }
     nN += ncur[j];
   }
-  if (part > 0 && nbj < 0) return;
+  if (part > 0 && part < 9 && nbj < 0) return;
   const int n0b = L.n0[b];
+  const size_t ib = ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15;
+  const size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
   int* Sl = reinterpret_cast<int*>(smem_raw);
   int* Rl = Sl + k;
-  cx<R>* Ts = reinterpret_cast<cx<R>*>(smem_raw + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
+  double* Tl = reinterpret_cast<double*>(smem_raw + ib);
+  cx<R>* Gs = reinterpret_cast<cx<R>*>(smem_raw + ib + tb);
   {
     const int* Sg = ph.Wi + ph.oI[slot];
-    for (int a = threadIdx.x; a < k; a += blockDim.x) Sl[a] = Sg[a];
-    for (int c = threadIdx.x; c < r; c += blockDim.x) Rl[c] = Sg[n0b + c];
+    for (int a = threadIdx.x; a < k; a += NT) Sl[a] = Sg[a];
+    for (int c = threadIdx.x; c < r; c += NT) Rl[c] = Sg[n0b + c];
+    const cx<R>* Tg = rec.F + rec.oT[b];
+    for (int e = threadIdx.x; e < k * r; e += NT) Tl[e] = (double)Tg[e].x;
   }
-  const cx<R>* Tg = rec.F + rec.oT[b];
-  const bool tl = k * r <= tcap;
-  if (tl)
-    for (int e = threadIdx.x; e < k * r; e += blockDim.x) Ts[e] = Tg[e];
   __syncthreads();
-  const cx<R>* T = tl ? Ts : Tg;
   cx<R>* XSNR = rec.F + rec.oXSNR[b];
   const int ldx = k + nN;
   cx<R>* Z = ph.W + ph.oZ[slot];
   const int* gid = L.idx + L.ioff[b];
-  if (part == 0) {
+  if (part == 9) {
+    // Z_RS (row a of A_SS read along its columns)
     const cx<R>* A = block_ptr(L, b, b);
     const int ld = n0b;
-    for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
-      const int a = e % k, c = e / k;
-      const cx<R>* Ar = A + Sl[a];
-      const cx<R>* Tc = T + (int64_t)c * k;
-      const cx<double> u = dot2(k, [&](int s) { return to_d(Ar[(int64_t)Sl[s] * ld]) * to_d(Tc[s]); });
-      XSNR[a + (int64_t)c * ldx] = from_cd<R>(to_d(Ar[(int64_t)Rl[c] * ld]) - u);
-    }
-    for (int e = threadIdx.x; e < r * k; e += blockDim.x) {
-      const int c = e % r, a = e / r;
-      const cx<R>* Aa = A + (int64_t)Sl[a] * ld;
-      const cx<R>* Tc = T + (int64_t)c * k;
-      const cx<double> u = dot2(k, [&](int s) { return cmulc(to_d(Tc[s]), to_d(Aa[Sl[s]])); });
-      Z[c + (int64_t)a * r] = from_cd<R>(to_d(Aa[Rl[c]]) - u);
-    }
-    __syncthreads();
+    sp_gemm<R, NT, true>(
+        k, k, r, Tl, Gs, ic, [&](int a, int s_) { return A[Sl[s_] + (int64_t)Sl[a] * ld]; },
+        [&](int a, int c) { return to_d(A[Rl[c] + (int64_t)Sl[a] * ld]); },
+        [&](int a, int c, cx<double> v) { Z[c + (int64_t)a * r] = from_cd<R>(v); });
+  } else if (part == 0) {
+    const cx<R>* A = block_ptr(L, b, b);
+    const int ld = n0b;
+    // X_SR
+    sp_gemm<R, NT, false>(
+        k, k, r, Tl, Gs, ic, [&](int a, int s_) { return A[Sl[a] + (int64_t)Sl[s_] * ld]; },
+        [&](int a, int c) { return to_d(A[Sl[a] + (int64_t)Rl[c] * ld]); },
+        [&](int a, int c, cx<double> v) { XSNR[a + (int64_t)c * ldx] = from_cd<R>(v); });
+    // -(T^T X_SR)^T into the FP64 workspace: W(c2, c1) = -sum_s X_SR(s, c2) T(s, c1)
+    cx<double>* Wt = ph.Wd + ph.oD[slot];
+    __syncthreads();  // X_SR stored
+    sp_gemm<R, NT, true>(
+        r, k, r, Tl, Gs, ic, [&](int c2, int s_) { return XSNR[s_ + (int64_t)c2 * ldx]; },
+        [&](int, int) { return czero<double>(); },
+        [&](int c2, int c1, cx<double> v) { Wt[c2 + (int64_t)c1 * r] = v; });
+    __syncthreads();  // W stored
+    // X_RR = A_RR - T^T X_SR - A_RS T
     cx<R>* X = ph.W + ph.oX[slot];
-    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
-      const int c1 = e % r, c2 = e / r;
-      const cx<R>* Ar = A + Rl[c1];
-      const cx<R>* T1 = T + (int64_t)c1 * k;
-      const cx<R>* T2 = T + (int64_t)c2 * k;
-      const cx<R>* X2 = XSNR + (int64_t)c2 * ldx;
-      const cx<double> u1 = dot2(k, [&](int s) { return to_d(Ar[(int64_t)Sl[s] * ld]) * to_d(T2[s]); });
-      const cx<double> u2 = dot2(k, [&](int s) { return cmulc(to_d(T1[s]), to_d(X2[s])); });
-      X[c1 + (int64_t)c2 * r] = from_cd<R>(to_d(Ar[(int64_t)Rl[c2] * ld]) - u1 - u2);
-    }
+    sp_gemm<R, NT, false>(
+        r, k, r, Tl, Gs, ic, [&](int c1, int s_) { return A[Rl[c1] + (int64_t)Sl[s_] * ld]; },
+        [&](int c1, int c2) { return to_d(A[Rl[c1] + (int64_t)Rl[c2] * ld]) + Wt[c2 + (int64_t)c1 * r]; },
+        [&](int c1, int c2, cx<double> v) { X[c1 + (int64_t)c2 * r] = from_cd<R>(v); });
     int* gS = rec.G + rec.oS[b];
     int* gR = rec.G + rec.oR[b];
-    for (int a = threadIdx.x; a < k; a += blockDim.x) gS[a] = gid[Sl[a]];
-    for (int c = threadIdx.x; c < r; c += blockDim.x) gR[c] = gid[Rl[c]];
+    for (int a = threadIdx.x; a < k; a += NT) gS[a] = gid[Sl[a]];
+    for (int c = threadIdx.x; c < r; c += NT) gR[c] = gid[Rl[c]];
     if (threadIdx.x == 0) rec.nN[b] = nN;
   } else {
     const int cn = L.cur[nbj];
     const cx<R>* A1 = block_ptr(L, nbj, b);  // cn x n, ld n0[nbj]
     const int ld1 = L.n0[nbj];
-    for (int e = threadIdx.x; e < cn * r; e += blockDim.x) {
-      const int i = e % cn, c = e / cn;
-      const cx<R>* Ai = A1 + i;
-      const cx<R>* Tc = T + (int64_t)c * k;
-      const cx<double> u = dot2(k, [&](int s) { return to_d(Ai[(int64_t)Sl[s] * ld1]) * to_d(Tc[s]); });
-      XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(to_d(Ai[(int64_t)Rl[c] * ld1]) - u);
-    }
+    sp_gemm<R, NT, false>(
+        cn, k, r, Tl, Gs, ic, [&](int i, int s_) { return A1[i + (int64_t)Sl[s_] * ld1]; },
+        [&](int i, int c) { return to_d(A1[i + (int64_t)Rl[c] * ld1]); },
+        [&](int i, int c, cx<double> v) { XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(v); });
     const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
-    for (int e = threadIdx.x; e < r * cn; e += blockDim.x) {
-      const int c = e % r, i = e / r;
-      const cx<R>* Ai = A2 + (int64_t)i * n0b;
-      const cx<R>* Tc = T + (int64_t)c * k;
-      const cx<double> u = dot2(k, [&](int s) { return cmulc(to_d(Tc[s]), to_d(Ai[Sl[s]])); });
-      Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(to_d(Ai[Rl[c]]) - u);
-    }
+    sp_gemm<R, NT, true>(
+        cn, k, r, Tl, Gs, ic, [&](int i, int s_) { return A2[Sl[s_] + (int64_t)i * n0b]; },
+        [&](int i, int c) { return to_d(A2[Rl[c] + (int64_t)i * n0b]); },
+        [&](int i, int c, cx<double> v) { Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(v); });
     int* gN = rec.G + rec.oN[b];
     const int* gid2 = L.idx + L.ioff[nbj];
-    for (int i = threadIdx.x; i < cn; i += blockDim.x) gN[offj + i] = gid2[i];
+    for (int i = threadIdx.x; i < cn; i += NT) gN[offj + i] = gid2[i];
   }
 }
 
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  // T in LDS up to 64 KiB
-  const int tcap = (int)std::min<size_t>((size_t)nmax * nmax, (64 * 1024) / sizeof(cx<R>));
-  const size_t shm = (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15) + (size_t)tcap * sizeof(cx<R>);
-  hipLaunchKernelGGL(k_sparsify<R>, dim3(ph.nbox, 9), dim3(RSS_SPARSIFY_NT), shm, s, probs, ph, nmax, tcap);
+  // LDS: the index lists, T (k r <= floor(n/2) ceil(n/2) reals), then as many
+  // staging rows (k <= nmax entries each) as the budget leaves: a budget that
+  // lets several workgroups share a CU when there are many (the staging loads'
+  // latency is hidden by the other workgroups), up to 150 KiB when few
+  const size_t ib = ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15;
+  const size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
+  const int64_t nwg = (int64_t)ph.nbox * 10;
+  const size_t budget = nwg >= 2048 ? (size_t)32 * 1024 : nwg >= 512 ? (size_t)56 * 1024 : (size_t)150 * 1024;
+  const size_t rowb = (size_t)std::max(1, nmax) * sizeof(cx<R>);
+  const size_t room = budget > ib + tb ? budget - ib - tb : 0;
+  int ic = (int)std::min<size_t>((size_t)std::max(2, nmax), std::max<size_t>(16, room / rowb));
+  ic = std::max(2, ic & ~1);
+  const size_t shm = ib + tb + (size_t)ic * rowb;
+  // 256 threads per workgroup where there are many, else 1024
+  if (nwg >= 512)
+    hipLaunchKernelGGL((k_sparsify<R, 256>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
+  else
+    hipLaunchKernelGGL((k_sparsify<R, 1024>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
 }
 
 // v - c s in complex FP64, four FMAs

@@ -1142,6 +1142,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       int pass_lo[5] = {0, 0, 0, 0, 0};  // four colours: slots of Schur pass q are [pass_lo[q], pass_lo[q+1])
     } M[9];
     const int colours = H[0]->opt.colours;
+    if (sparsify_min_lds(nmax) > SPARSIFY_LDS_CAP)
+      fail(RSS_EUNSUPPORTED, "boxes of " + std::to_string(nmax) + " active points exceed the sparsification's LDS");
     // the ID through the double-double Gram matrix for boxes of up to
     // GRAM_NMAX points, else column-pivoted Householder QR on C
     const bool use_gram = nmax <= gram_nmax();

@@ -202,6 +202,10 @@ template <class R>
 void launch_chol(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s);
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s);
+// LDS the sparsification needs at least (its S and R index lists) and the
+// most it takes per workgroup
+constexpr size_t SPARSIFY_LDS_CAP = (size_t)150 * 1024;
+inline size_t sparsify_min_lds(int nmax) { return ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15; }
 template <class R>
 void launch_inverse(const Prob<R>* probs, const Phase<R>& ph, int* errflag, int nmax,
                     hipStream_t s);

@@ -787,15 +787,19 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 // out(i, c) = base(i, c) - sum_s G(s, i) t(s, c), i < M, c < r, for the
 // products of the sparsification: G(s, i) = g(i, s) (a gathered block of A)
 // staged in LDS IC rows i at a time ([s][i], the loads ordered i-fast or
-// s-fast as the source is laid out), t = T (real, k x r) in LDS ([c][s]);
+// s-fast as the source is laid out), t = T (real, k x r, [c][s]) read through
+// tval (LDS, or the record when it does not fit; G too is read in place
+// when not even two rows fit);
 // each thread a 2 x 4 tile of outputs, sums in FP64.
-template <class R, int NT, bool SFAST, class Gf, class Base, class Dst>
-__device__ __forceinline__ void sp_gemm(int M, int k, int r, const double* Tl, cx<R>* Gs, int IC, Gf g,
-                                        Base base, Dst dst) {
+template <class R, int NT, bool SFAST, bool GS, class Tf, class Gf, class Base, class Dst>
+__device__ __forceinline__ void sp_gemm(int M, int k, int r, Tf tval, cx<R>* Gs, int IC, Gf g, Base base,
+                                        Dst dst) {
+  if (!GS) IC = M;  // G read in place (boxes too large to stage two rows)
   for (int i0 = 0; i0 < M; i0 += IC) {
     const int mi = min(IC, M - i0);
     __syncthreads();  // the previous chunk's readers are done
-    if (SFAST) {
+    if (!GS) {
+    } else if (SFAST) {
       for (int e = threadIdx.x; e < k * mi; e += NT) {
         const int ss = e % k, i = e / k;
         Gs[ss * IC + i] = g(i0 + i, ss);
@@ -818,10 +822,11 @@ __device__ __forceinline__ void sp_gemm(int M, int k, int r, const double* Tl, c
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[0][u] = acc[1][u] = czero<double>();
       for (int ss = 0; ss < k; ++ss) {
-        const cx<double> g0 = to_d(Gs[ss * IC + i]), g1 = to_d(Gs[ss * IC + i1]);
+        const cx<double> g0 = to_d(GS ? Gs[ss * IC + i] : g(i0 + i, ss));
+        const cx<double> g1 = to_d(GS ? Gs[ss * IC + i1] : g(i0 + i1, ss));
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const double tv = Tl[cc[u] + ss];
+          const double tv = tval(cc[u] + ss);
           acc[0][u].x = fma(g0.x, tv, acc[0][u].x);
           acc[0][u].y = fma(g0.y, tv, acc[0][u].y);
           acc[1][u].x = fma(g1.x, tv, acc[1][u].x);
@@ -848,7 +853,7 @@ __device__ __forceinline__ void sp_gemm(int M, int k, int r, const double* Tl, c
 // Every product runs through sp_gemm; T^T X_SR is formed first (FP64, in the
 // phase's FP64 workspace, transposed) and folded into the base of X_RR.
 // LDS: the S and R lists, T, then the staging rows.
-template <class R, int NT>
+template <class R, int NT, bool TL, bool GS>
 __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph, int nmax, int ic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int slot = blockIdx.x, b = ph.box[slot];
@@ -877,19 +882,24 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
   if (part > 0 && part < 9 && nbj < 0) return;
   const int n0b = L.n0[b];
   const size_t ib = ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15;
-  const size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
+  const size_t tb = TL ? (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15 : 0;
   int* Sl = reinterpret_cast<int*>(smem_raw);
   int* Rl = Sl + k;
   double* Tl = reinterpret_cast<double*>(smem_raw + ib);
   cx<R>* Gs = reinterpret_cast<cx<R>*>(smem_raw + ib + tb);
+  const cx<R>* Tg = rec.F + rec.oT[b];
   {
     const int* Sg = ph.Wi + ph.oI[slot];
     for (int a = threadIdx.x; a < k; a += NT) Sl[a] = Sg[a];
     for (int c = threadIdx.x; c < r; c += NT) Rl[c] = Sg[n0b + c];
-    const cx<R>* Tg = rec.F + rec.oT[b];
-    for (int e = threadIdx.x; e < k * r; e += NT) Tl[e] = (double)Tg[e].x;
+    if (TL)
+      for (int e = threadIdx.x; e < k * r; e += NT) Tl[e] = (double)Tg[e].x;
   }
   __syncthreads();
+  auto tval = [&](int e) -> double {
+    if constexpr (TL) return Tl[e];
+    else return (double)Tg[e].x;
+  };
   cx<R>* XSNR = rec.F + rec.oXSNR[b];
   const int ldx = k + nN;
   cx<R>* Z = ph.W + ph.oZ[slot];
@@ -898,30 +908,30 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
     // Z_RS (row a of A_SS read along its columns)
     const cx<R>* A = block_ptr(L, b, b);
     const int ld = n0b;
-    sp_gemm<R, NT, true>(
-        k, k, r, Tl, Gs, ic, [&](int a, int s_) { return A[Sl[s_] + (int64_t)Sl[a] * ld]; },
+    sp_gemm<R, NT, true, GS>(
+        k, k, r, tval, Gs, ic, [&](int a, int s_) { return A[Sl[s_] + (int64_t)Sl[a] * ld]; },
         [&](int a, int c) { return to_d(A[Rl[c] + (int64_t)Sl[a] * ld]); },
         [&](int a, int c, cx<double> v) { Z[c + (int64_t)a * r] = from_cd<R>(v); });
   } else if (part == 0) {
     const cx<R>* A = block_ptr(L, b, b);
     const int ld = n0b;
     // X_SR
-    sp_gemm<R, NT, false>(
-        k, k, r, Tl, Gs, ic, [&](int a, int s_) { return A[Sl[a] + (int64_t)Sl[s_] * ld]; },
+    sp_gemm<R, NT, false, GS>(
+        k, k, r, tval, Gs, ic, [&](int a, int s_) { return A[Sl[a] + (int64_t)Sl[s_] * ld]; },
         [&](int a, int c) { return to_d(A[Sl[a] + (int64_t)Rl[c] * ld]); },
         [&](int a, int c, cx<double> v) { XSNR[a + (int64_t)c * ldx] = from_cd<R>(v); });
     // -(T^T X_SR)^T into the FP64 workspace: W(c2, c1) = -sum_s X_SR(s, c2) T(s, c1)
     cx<double>* Wt = ph.Wd + ph.oD[slot];
     __syncthreads();  // X_SR stored
-    sp_gemm<R, NT, true>(
-        r, k, r, Tl, Gs, ic, [&](int c2, int s_) { return XSNR[s_ + (int64_t)c2 * ldx]; },
+    sp_gemm<R, NT, true, GS>(
+        r, k, r, tval, Gs, ic, [&](int c2, int s_) { return XSNR[s_ + (int64_t)c2 * ldx]; },
         [&](int, int) { return czero<double>(); },
         [&](int c2, int c1, cx<double> v) { Wt[c2 + (int64_t)c1 * r] = v; });
     __syncthreads();  // W stored
     // X_RR = A_RR - T^T X_SR - A_RS T
     cx<R>* X = ph.W + ph.oX[slot];
-    sp_gemm<R, NT, false>(
-        r, k, r, Tl, Gs, ic, [&](int c1, int s_) { return A[Rl[c1] + (int64_t)Sl[s_] * ld]; },
+    sp_gemm<R, NT, false, GS>(
+        r, k, r, tval, Gs, ic, [&](int c1, int s_) { return A[Rl[c1] + (int64_t)Sl[s_] * ld]; },
         [&](int c1, int c2) { return to_d(A[Rl[c1] + (int64_t)Rl[c2] * ld]) + Wt[c2 + (int64_t)c1 * r]; },
         [&](int c1, int c2, cx<double> v) { X[c1 + (int64_t)c2 * r] = from_cd<R>(v); });
     int* gS = rec.G + rec.oS[b];
@@ -933,13 +943,13 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
     const int cn = L.cur[nbj];
     const cx<R>* A1 = block_ptr(L, nbj, b);  // cn x n, ld n0[nbj]
     const int ld1 = L.n0[nbj];
-    sp_gemm<R, NT, false>(
-        cn, k, r, Tl, Gs, ic, [&](int i, int s_) { return A1[i + (int64_t)Sl[s_] * ld1]; },
+    sp_gemm<R, NT, false, GS>(
+        cn, k, r, tval, Gs, ic, [&](int i, int s_) { return A1[i + (int64_t)Sl[s_] * ld1]; },
         [&](int i, int c) { return to_d(A1[i + (int64_t)Rl[c] * ld1]); },
         [&](int i, int c, cx<double> v) { XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(v); });
     const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
-    sp_gemm<R, NT, true>(
-        cn, k, r, Tl, Gs, ic, [&](int i, int s_) { return A2[Sl[s_] + (int64_t)i * n0b]; },
+    sp_gemm<R, NT, true, GS>(
+        cn, k, r, tval, Gs, ic, [&](int i, int s_) { return A2[Sl[s_] + (int64_t)i * n0b]; },
         [&](int i, int c) { return to_d(A2[Rl[c] + (int64_t)i * n0b]); },
         [&](int i, int c, cx<double> v) { Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(v); });
     int* gN = rec.G + rec.oN[b];
@@ -951,24 +961,38 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
 template <class R>
 void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s) {
   if (ph.nbox == 0) return;
-  // LDS: the index lists, T (k r <= floor(n/2) ceil(n/2) reals), then as many
-  // staging rows (k <= nmax entries each) as the budget leaves: a budget that
-  // lets several workgroups share a CU when there are many (the staging loads'
-  // latency is hidden by the other workgroups), up to 150 KiB when few
-  const size_t ib = ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15;
-  const size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
-  const int64_t nwg = (int64_t)ph.nbox * 10;
-  const size_t budget = nwg >= 2048 ? (size_t)32 * 1024 : nwg >= 512 ? (size_t)56 * 1024 : (size_t)150 * 1024;
+  // LDS: the index lists, T (k r <= floor(n/2) ceil(n/2) reals) unless that
+  // leaves fewer than 16 staging rows in 150 KiB (then T is read from the
+  // record), then as many staging rows (k <= nmax entries each) as the budget
+  // leaves: a budget that lets several workgroups share a CU when there are
+  // many (the staging loads' latency is hidden by the other workgroups), up
+  // to 150 KiB when few.  Boxes too large for two rows read G in place.
+  const size_t cap = SPARSIFY_LDS_CAP;
+  const size_t ib = sparsify_min_lds(nmax);
   const size_t rowb = (size_t)std::max(1, nmax) * sizeof(cx<R>);
+  size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
+  const bool tl = ib + tb + 16 * rowb <= cap;
+  if (!tl) tb = 0;
+  const bool gs = ib + 2 * rowb <= cap;
+  const int64_t nwg = (int64_t)ph.nbox * 10;
+  if (!gs) {
+    hipLaunchKernelGGL((k_sparsify<R, 256, false, false>), dim3(ph.nbox, 10), dim3(256), ib, s, probs, ph, nmax, 2);
+    return;
+  }
+  const size_t budget = nwg >= 2048 ? (size_t)32 * 1024 : nwg >= 512 ? (size_t)56 * 1024 : cap;
   const size_t room = budget > ib + tb ? budget - ib - tb : 0;
-  int ic = (int)std::min<size_t>((size_t)std::max(2, nmax), std::max<size_t>(16, room / rowb));
+  const size_t most = cap - ib - tb;  // at least 16 rows with T in LDS, 2 without
+  int ic = (int)std::min<size_t>({(size_t)std::max(2, nmax), std::max<size_t>(16, room / rowb), most / rowb});
   ic = std::max(2, ic & ~1);
   const size_t shm = ib + tb + (size_t)ic * rowb;
   // 256 threads per workgroup where there are many, else 1024
-  if (nwg >= 512)
-    hipLaunchKernelGGL((k_sparsify<R, 256>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
-  else
-    hipLaunchKernelGGL((k_sparsify<R, 1024>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
+  if (nwg >= 512) {
+    if (tl) hipLaunchKernelGGL((k_sparsify<R, 256, true, true>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
+    else hipLaunchKernelGGL((k_sparsify<R, 256, false, true>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
+  } else {
+    if (tl) hipLaunchKernelGGL((k_sparsify<R, 1024, true, true>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
+    else hipLaunchKernelGGL((k_sparsify<R, 1024, false, true>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
+  }
 }
 
 // v - c s in complex FP64, four FMAs

@@ -1337,7 +1337,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
             launch_cpqr<R>(d_probs, ph, nmax, mmax, s);
         });
       }
-      prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(d_probs, ph, nmax, s); });
+      prof.run(RSS_K_SPARSIFY, s, [&] { launch_sparsify<R>(d_probs, ph, nmax, use_gram, s); });
       prof.run(RSS_K_INVERSE, s, [&] { launch_inverse<R>(d_probs, ph, d_err, nmax, s); });
       launch_plan_y<R>(d_probs, ph, desc, s);
       prof.run(RSS_K_GEMM_Y, s, [&] { launch_gemm<R>(desc, ph.nbox, nmax, nmax + nNmax, s); });

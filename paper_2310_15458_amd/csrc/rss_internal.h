@@ -201,7 +201,8 @@ void launch_gram(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int
 template <class R>
 void launch_chol(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s);
 template <class R>
-void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s);
+// treal: every T of the phase is real (IDs through the Gram matrix)
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, bool treal, hipStream_t s);
 // LDS the sparsification needs at least (its S and R index lists) and the
 // most it takes per workgroup
 constexpr size_t SPARSIFY_LDS_CAP = (size_t)150 * 1024;

@@ -787,11 +787,11 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 // out(i, c) = base(i, c) - sum_s G(s, i) t(s, c), i < M, c < r, for the
 // products of the sparsification: G(s, i) = g(i, s) (a gathered block of A)
 // staged in LDS IC rows i at a time ([s][i], the loads ordered i-fast or
-// s-fast as the source is laid out), t = T (real, k x r, [c][s]) read through
-// tval (LDS, or the record when it does not fit; G too is read in place
-// when not even two rows fit);
+// s-fast as the source is laid out), t = T (k x r, [c][s]) read through tval
+// (LDS, or the record when it does not fit; G too is read in place when not
+// even two rows fit): a real t, or a complex one, conjugated if CONJ;
 // each thread a 2 x 4 tile of outputs, sums in FP64.
-template <class R, int NT, bool SFAST, bool GS, class Tf, class Gf, class Base, class Dst>
+template <class R, int NT, bool SFAST, bool GS, bool CONJ, class Tf, class Gf, class Base, class Dst>
 __device__ __forceinline__ void sp_gemm(int M, int k, int r, Tf tval, cx<R>* Gs, int IC, Gf g, Base base,
                                         Dst dst) {
   if (!GS) IC = M;  // G read in place (boxes too large to stage two rows)
@@ -826,11 +826,19 @@ __device__ __forceinline__ void sp_gemm(int M, int k, int r, Tf tval, cx<R>* Gs,
         const cx<double> g1 = to_d(GS ? Gs[ss * IC + i1] : g(i0 + i1, ss));
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const double tv = tval(cc[u] + ss);
-          acc[0][u].x = fma(g0.x, tv, acc[0][u].x);
-          acc[0][u].y = fma(g0.y, tv, acc[0][u].y);
-          acc[1][u].x = fma(g1.x, tv, acc[1][u].x);
-          acc[1][u].y = fma(g1.y, tv, acc[1][u].y);
+          const auto tv = tval(cc[u] + ss);
+          if constexpr (std::is_same<decltype(tv), const double>::value) {
+            acc[0][u].x = fma(g0.x, tv, acc[0][u].x);
+            acc[0][u].y = fma(g0.y, tv, acc[0][u].y);
+            acc[1][u].x = fma(g1.x, tv, acc[1][u].x);
+            acc[1][u].y = fma(g1.y, tv, acc[1][u].y);
+          } else if constexpr (CONJ) {  // conj(t) g
+            fmac_(acc[0][u], tv, g0);
+            fmac_(acc[1][u], tv, g1);
+          } else {
+            fma_(acc[0][u], g0, tv);
+            fma_(acc[1][u], g1, tv);
+          }
         }
       }
 #pragma unroll
@@ -842,18 +850,21 @@ __device__ __forceinline__ void sp_gemm(int M, int k, int r, Tf tval, cx<R>* Gs,
   }
 }
 
-// Sparsification of box b (eqs. e:con / e:step): with T (k x r, real: the ID
-// of a real Gram matrix) and the index lists S, R of the ID,
+// Sparsification of box b (eqs. e:con / e:step): with T (k x r) and the
+// index lists S, R of the ID,
 //   part 0 (the box itself, A = A_bb):
 //     X_SR = A_SR - A_SS T           -> rows 0..k-1 of the record's X_{S+N,R}
-//     X_RR = A_RR - A_RS T - T^T X_SR (X_SR as stored)
+//     X_RR = A_RR - A_RS T - T^* X_SR (X_SR as stored)
 //   part j = 1..8 (neighbour n_j, cn points):
-//     X_{n_j R} = A_{n_j R} - A_{n_j S} T, Z_{R n_j} = A_{R n_j} - T^T A_{S n_j}
-//   part 9: Z_RS = A_RS - T^T A_SS   -> columns 0..k-1 of Z (r x (k + nN)).
-// Every product runs through sp_gemm; T^T X_SR is formed first (FP64, in the
+//     X_{n_j R} = A_{n_j R} - A_{n_j S} T, Z_{R n_j} = A_{R n_j} - T^* A_{S n_j}
+//   part 9: Z_RS = A_RS - T^* A_SS   -> columns 0..k-1 of Z (r x (k + nN)).
+// T is real when the ID came from the Gram matrix (TC false: half the
+// arithmetic), complex from the Householder QR (rounding leaves imaginary
+// parts there, and the solve uses T as stored, so they are kept).
+// Every product runs through sp_gemm; T^* X_SR is formed first (FP64, in the
 // phase's FP64 workspace, transposed) and folded into the base of X_RR.
 // LDS: the S and R lists, T, then the staging rows.
-template <class R, int NT, bool TL, bool GS>
+template <class R, int NT, bool TL, bool GS, bool TC>
 __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> ph, int nmax, int ic) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int slot = blockIdx.x, b = ph.box[slot];
@@ -881,24 +892,29 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
   }
   if (part > 0 && part < 9 && nbj < 0) return;
   const int n0b = L.n0[b];
+  using TT = typename std::conditional<TC, cx<double>, double>::type;
   const size_t ib = ((size_t)2 * nmax * sizeof(int) + 15) & ~(size_t)15;
-  const size_t tb = TL ? (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15 : 0;
+  const size_t tb = TL ? (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(TT) + 15) & ~(size_t)15 : 0;
   int* Sl = reinterpret_cast<int*>(smem_raw);
   int* Rl = Sl + k;
-  double* Tl = reinterpret_cast<double*>(smem_raw + ib);
+  TT* Tl = reinterpret_cast<TT*>(smem_raw + ib);
   cx<R>* Gs = reinterpret_cast<cx<R>*>(smem_raw + ib + tb);
   const cx<R>* Tg = rec.F + rec.oT[b];
+  auto tget = [&](int e) -> TT {
+    if constexpr (TC) return to_d(Tg[e]);
+    else return (double)Tg[e].x;
+  };
   {
     const int* Sg = ph.Wi + ph.oI[slot];
     for (int a = threadIdx.x; a < k; a += NT) Sl[a] = Sg[a];
     for (int c = threadIdx.x; c < r; c += NT) Rl[c] = Sg[n0b + c];
     if (TL)
-      for (int e = threadIdx.x; e < k * r; e += NT) Tl[e] = (double)Tg[e].x;
+      for (int e = threadIdx.x; e < k * r; e += NT) Tl[e] = tget(e);
   }
   __syncthreads();
-  auto tval = [&](int e) -> double {
+  auto tval = [&](int e) -> TT {
     if constexpr (TL) return Tl[e];
-    else return (double)Tg[e].x;
+    else return tget(e);
   };
   cx<R>* XSNR = rec.F + rec.oXSNR[b];
   const int ldx = k + nN;
@@ -908,7 +924,7 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
     // Z_RS (row a of A_SS read along its columns)
     const cx<R>* A = block_ptr(L, b, b);
     const int ld = n0b;
-    sp_gemm<R, NT, true, GS>(
+    sp_gemm<R, NT, true, GS, true>(
         k, k, r, tval, Gs, ic, [&](int a, int s_) { return A[Sl[s_] + (int64_t)Sl[a] * ld]; },
         [&](int a, int c) { return to_d(A[Rl[c] + (int64_t)Sl[a] * ld]); },
         [&](int a, int c, cx<double> v) { Z[c + (int64_t)a * r] = from_cd<R>(v); });
@@ -916,21 +932,21 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
     const cx<R>* A = block_ptr(L, b, b);
     const int ld = n0b;
     // X_SR
-    sp_gemm<R, NT, false, GS>(
+    sp_gemm<R, NT, false, GS, false>(
         k, k, r, tval, Gs, ic, [&](int a, int s_) { return A[Sl[a] + (int64_t)Sl[s_] * ld]; },
         [&](int a, int c) { return to_d(A[Sl[a] + (int64_t)Rl[c] * ld]); },
         [&](int a, int c, cx<double> v) { XSNR[a + (int64_t)c * ldx] = from_cd<R>(v); });
-    // -(T^T X_SR)^T into the FP64 workspace: W(c2, c1) = -sum_s X_SR(s, c2) T(s, c1)
+    // -(T^* X_SR)^T into the FP64 workspace: W(c2, c1) = -sum_s X_SR(s, c2) conj(T(s, c1))
     cx<double>* Wt = ph.Wd + ph.oD[slot];
     __syncthreads();  // X_SR stored
-    sp_gemm<R, NT, true, GS>(
+    sp_gemm<R, NT, true, GS, true>(
         r, k, r, tval, Gs, ic, [&](int c2, int s_) { return XSNR[s_ + (int64_t)c2 * ldx]; },
         [&](int, int) { return czero<double>(); },
         [&](int c2, int c1, cx<double> v) { Wt[c2 + (int64_t)c1 * r] = v; });
     __syncthreads();  // W stored
-    // X_RR = A_RR - T^T X_SR - A_RS T
+    // X_RR = A_RR - T^* X_SR - A_RS T
     cx<R>* X = ph.W + ph.oX[slot];
-    sp_gemm<R, NT, false, GS>(
+    sp_gemm<R, NT, false, GS, false>(
         r, k, r, tval, Gs, ic, [&](int c1, int s_) { return A[Rl[c1] + (int64_t)Sl[s_] * ld]; },
         [&](int c1, int c2) { return to_d(A[Rl[c1] + (int64_t)Rl[c2] * ld]) + Wt[c2 + (int64_t)c1 * r]; },
         [&](int c1, int c2, cx<double> v) { X[c1 + (int64_t)c2 * r] = from_cd<R>(v); });
@@ -943,12 +959,12 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
     const int cn = L.cur[nbj];
     const cx<R>* A1 = block_ptr(L, nbj, b);  // cn x n, ld n0[nbj]
     const int ld1 = L.n0[nbj];
-    sp_gemm<R, NT, false, GS>(
+    sp_gemm<R, NT, false, GS, false>(
         cn, k, r, tval, Gs, ic, [&](int i, int s_) { return A1[i + (int64_t)Sl[s_] * ld1]; },
         [&](int i, int c) { return to_d(A1[i + (int64_t)Rl[c] * ld1]); },
         [&](int i, int c, cx<double> v) { XSNR[(k + offj + i) + (int64_t)c * ldx] = from_cd<R>(v); });
     const cx<R>* A2 = block_ptr(L, b, nbj);  // n x cn, ld n0[b]
-    sp_gemm<R, NT, true, GS>(
+    sp_gemm<R, NT, true, GS, true>(
         cn, k, r, tval, Gs, ic, [&](int i, int s_) { return A2[Sl[s_] + (int64_t)i * n0b]; },
         [&](int i, int c) { return to_d(A2[Rl[c] + (int64_t)i * n0b]); },
         [&](int i, int c, cx<double> v) { Z[c + (int64_t)(k + offj + i) * r] = from_cd<R>(v); });
@@ -958,25 +974,26 @@ __global__ __launch_bounds__(NT) void k_sparsify(const Prob<R>* probs, Phase<R> 
   }
 }
 
-template <class R>
-void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s) {
-  if (ph.nbox == 0) return;
-  // LDS: the index lists, T (k r <= floor(n/2) ceil(n/2) reals) unless that
-  // leaves fewer than 16 staging rows in 150 KiB (then T is read from the
+template <class R, bool TC>
+static void launch_sparsify_t(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStream_t s) {
+  // LDS: the index lists, T (k r <= floor(n/2) ceil(n/2) entries) unless that
+  // leaves fewer than 16 staging rows in the cap (then T is read from the
   // record), then as many staging rows (k <= nmax entries each) as the budget
   // leaves: a budget that lets several workgroups share a CU when there are
   // many (the staging loads' latency is hidden by the other workgroups), up
-  // to 150 KiB when few.  Boxes too large for two rows read G in place.
+  // to the cap when few.  Boxes too large for two rows read G in place.
   const size_t cap = SPARSIFY_LDS_CAP;
   const size_t ib = sparsify_min_lds(nmax);
   const size_t rowb = (size_t)std::max(1, nmax) * sizeof(cx<R>);
-  size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * sizeof(double) + 15) & ~(size_t)15;
+  const size_t te = TC ? sizeof(cx<double>) : sizeof(double);
+  size_t tb = (((size_t)(nmax / 2) * ((nmax + 1) / 2)) * te + 15) & ~(size_t)15;
   const bool tl = ib + tb + 16 * rowb <= cap;
   if (!tl) tb = 0;
   const bool gs = ib + 2 * rowb <= cap;
   const int64_t nwg = (int64_t)ph.nbox * 10;
+  const dim3 grid(ph.nbox, 10);
   if (!gs) {
-    hipLaunchKernelGGL((k_sparsify<R, 256, false, false>), dim3(ph.nbox, 10), dim3(256), ib, s, probs, ph, nmax, 2);
+    hipLaunchKernelGGL((k_sparsify<R, 256, false, false, TC>), grid, dim3(256), ib, s, probs, ph, nmax, 2);
     return;
   }
   const size_t budget = nwg >= 2048 ? (size_t)32 * 1024 : nwg >= 512 ? (size_t)56 * 1024 : cap;
@@ -987,12 +1004,19 @@ void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, hipStre
   const size_t shm = ib + tb + (size_t)ic * rowb;
   // 256 threads per workgroup where there are many, else 1024
   if (nwg >= 512) {
-    if (tl) hipLaunchKernelGGL((k_sparsify<R, 256, true, true>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
-    else hipLaunchKernelGGL((k_sparsify<R, 256, false, true>), dim3(ph.nbox, 10), dim3(256), shm, s, probs, ph, nmax, ic);
+    if (tl) hipLaunchKernelGGL((k_sparsify<R, 256, true, true, TC>), grid, dim3(256), shm, s, probs, ph, nmax, ic);
+    else hipLaunchKernelGGL((k_sparsify<R, 256, false, true, TC>), grid, dim3(256), shm, s, probs, ph, nmax, ic);
   } else {
-    if (tl) hipLaunchKernelGGL((k_sparsify<R, 1024, true, true>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
-    else hipLaunchKernelGGL((k_sparsify<R, 1024, false, true>), dim3(ph.nbox, 10), dim3(1024), shm, s, probs, ph, nmax, ic);
+    if (tl) hipLaunchKernelGGL((k_sparsify<R, 1024, true, true, TC>), grid, dim3(1024), shm, s, probs, ph, nmax, ic);
+    else hipLaunchKernelGGL((k_sparsify<R, 1024, false, true, TC>), grid, dim3(1024), shm, s, probs, ph, nmax, ic);
   }
+}
+
+template <class R>
+void launch_sparsify(const Prob<R>* probs, const Phase<R>& ph, int nmax, bool treal, hipStream_t s) {
+  if (ph.nbox == 0) return;
+  if (treal) launch_sparsify_t<R, false>(probs, ph, nmax, s);
+  else launch_sparsify_t<R, true>(probs, ph, nmax, s);
 }
 
 // v - c s in complex FP64, four FMAs
@@ -2820,7 +2844,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
   template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t);                    \
   template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);              \
   template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t);            \
-  template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);             \
+  template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, bool, hipStream_t);             \
   template void launch_inverse<R>(const Prob<R>*, const Phase<R>&, int*, int, hipStream_t);        \
   template void launch_plan_y<R>(const Prob<R>*, const Phase<R>&, GemmDesc<R>*, hipStream_t);      \
   template void launch_compact<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);                   \

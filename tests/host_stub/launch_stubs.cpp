@@ -9,7 +9,7 @@ template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, h
 template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
 template <class R> int solve_group(int, int, int nrhs) { return nrhs < 16 ? nrhs : 16; }
 template <class R> bool launch_cpqr_mg(const Prob<R>*, const Phase<R>&, int, int, int, double*, double*, unsigned*, int*, unsigned, hipStream_t) { return true; }
-template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
+template <class R> void launch_sparsify(const Prob<R>*, const Phase<R>&, int, bool, hipStream_t) {}
 int gram_tile_groups(int nmax) { return nmax > 64 ? 3 : 1; }
 template <class R> void launch_gram(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
 template <class R> void launch_chol(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t) {}
@@ -31,7 +31,7 @@ template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, Ge
 template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
 template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
-template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
+template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, bool, hipStream_t); \
 template void launch_gram<R>(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t); \
 template void launch_chol<R>(const Prob<R>*, const Phase<R>&, const GramWs&, int, hipStream_t); \
 template int cpqr_mg_groups<R>(int, int, int); \

@@ -211,6 +211,35 @@ def test_scattered_points_empty_boxes(torch_cuda):
     assert _rel(_host(Bd), orss.solve(Fo, B)) < 1e-10
 
 
+def test_large_boxes_tight_tolerance(torch_cuda):
+    """Boxes of more than 255 active points (Helmholtz kappa=25 at tol 1e-12):
+    the sparsification then reads T from the factor record rather than LDS.
+    One application of the FP64 factors leaves relres near the tolerance."""
+    torch = torch_cuda
+    from paper_2310_15458_amd import rss
+    n, kappa, tol = 256, 25.0, 1e-12
+    P = W.grid_points(n)
+    k = W.grid_kernel("helmholtz", n, kappa)
+    print(f"case helmholtz kappa={kappa} n={n} tol={tol}", flush=True)
+    F = rss.Factorization(P, k, tol, 64, precision="fp64")
+    depth = F.info()["depth"]
+    # active points of a box at depth d - 1: its four children's skeletons
+    nbig = 0
+    for d in range(depth, 2, -1):
+        nb = 2 ** d
+        act = {}
+        for b, s in F.skeletons(d).items():
+            par = (b // nb // 2) * (nb // 2) + (b % nb) // 2
+            act[par] = act.get(par, 0) + len(s)
+        nbig = max([nbig] + list(act.values()))
+    print(f"largest box: {nbig} active points", flush=True)
+    assert nbig > 255
+    B = W.rhs(n * n, 2, 5)
+    Bd = _dev(torch, B)
+    F.apply(Bd)
+    assert omv.relres(omv.fft_matvec(k, n, _host(Bd)), B) < 1e-9
+
+
 def test_multi_rhs_columns(torch_cuda):
     torch = torch_cuda
     from paper_2310_15458_amd import rss

@@ -357,6 +357,19 @@ int rss_set_stream(rss_handle h, void* stream);
 int rss_set_graphs(int enable);
 
 /*
+ * rss_trim_cache -- return the current device's cached device memory to the
+ * driver.  Freed factor records and workspaces stay with the library, per
+ * size class, and serve later allocations (repeated and batched
+ * factorizations then allocate nothing from the driver); the cache keeps at
+ * most half of the device's memory, and is emptied by itself when one of the
+ * library's own allocations fails, but not when other code in the process
+ * (torch's allocator, for one) runs short: such a caller trims first.
+ * Blocks in use by live handles or servers are not touched.  released (may be
+ * NULL): the bytes returned.  RSS_OK, or RSS_EHIP if no device is current.
+ */
+int rss_trim_cache(int64_t* released);
+
+/*
  * rss_set_autotune -- process-wide switch (default on) for the solve's tile
  * autotuner.  Each level of a solve (one tree height of one or more handles)
  * runs its sweeps with a tile: the right-hand sides per workgroup and the

@@ -73,8 +73,11 @@ constexpr size_t SLAB = (size_t)2 << 20, SMALL = (size_t)64 << 10;
 // only memory that no queued work uses any more (every free follows a
 // synchronization of the stream that used it; when an error unwinds an
 // operation, the device is synchronized before its blocks are cached).  At
-// most a quarter of the device's memory is kept cached; the rest goes back to
-// the driver, and so does the whole cache when an allocation fails.
+// most half of the device's memory is kept cached (a batched factorization of
+// a few hundred problems reuses its ~100 GB of blocks instead of handing tens
+// of GB back to the driver and mapping them again on every call); the rest
+// goes back to the driver, and so does the whole cache when an allocation
+// fails or rss_trim_cache asks for it.
 class DevPool {
  public:
   void* alloc(size_t n) {
@@ -139,21 +142,29 @@ class DevPool {
     if (it != cap_.end()) return it->second;
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
-    return cap_[dev] = tot / 4;
+    return cap_[dev] = tot / 2;
   }
-  void trim(int dev) {
+
+ public:
+  // return device dev's cached blocks to the driver; the bytes released
+  size_t trim(int dev) {
     std::vector<void*> out;
+    size_t bytes = 0;
     {
       std::lock_guard<std::mutex> g(mu_);
       for (auto& kv : free_)
         if (kv.first.first == dev) {
           out.insert(out.end(), kv.second.begin(), kv.second.end());
+          bytes += kv.first.second * kv.second.size();
           kv.second.clear();
         }
       cached_[dev] = 0;
     }
     for (void* q : out) (void)hipFree(q);
+    return bytes;
   }
+
+ private:
   std::mutex mu_;
   std::map<std::pair<int, size_t>, std::vector<void*>> free_;
   std::unordered_map<void*, std::pair<int, size_t>> live_;
@@ -3038,6 +3049,18 @@ int rss_set_stream(rss_handle h, void* stream) {
 }
 
 int rss_set_graphs(int enable) { return g_use_graphs.exchange(enable != 0) ? 1 : 0; }
+
+int rss_trim_cache(int64_t* released) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    g_err = "hipGetDevice failed";
+    return RSS_EHIP;
+  }
+  const size_t b = pool().trim(dev);
+  if (released) *released = (int64_t)b;
+  return RSS_OK;
+}
 
 int rss_set_autotune(int enable) {
   if (enable < 0 || enable > 2) {

@@ -54,7 +54,7 @@ EXPORTS = ["rss_factor", "rss_factor_ex", "rss_factor_batch", "rss_solve", "rss_
            "rss_residual_static", "rss_gridop_create", "rss_gridop_apply", "rss_gridop_residual",
            "rss_gridop_free", "rss_set_residual_op", "rss_krylov", "rss_krylov_ex", "rss_factor_tuning",
            "rss_factor_tuning_clear",
-           "rss_set_stream", "rss_set_graphs", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
+           "rss_set_stream", "rss_set_graphs", "rss_trim_cache", "rss_set_autotune", "rss_server_create", "rss_server_factor", "rss_server_solve",
            "rss_server_poll", "rss_server_stats_get", "rss_server_destroy", "rss_last_error",
            "rss_error_string"]
 
@@ -152,6 +152,7 @@ def load():
     lib.rss_solve_batch.argtypes = [ctypes.c_int, P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int)]
     lib.rss_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.rss_set_graphs.argtypes = [ctypes.c_int]
+    lib.rss_trim_cache.argtypes = [P(ctypes.c_int64)]
     lib.rss_set_autotune.argtypes = [ctypes.c_int]
     lib.rss_server_create.argtypes = [P(rss_server_options), P(ctypes.c_void_p)]
     lib.rss_server_factor.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, P(rss_kernel),
@@ -335,6 +336,15 @@ def set_graphs(enable: bool) -> bool:
     """rss_set_graphs: replay captured HIP graphs for single-handle applies
     (default) or launch every apply directly.  Returns the previous setting."""
     return bool(load().rss_set_graphs(1 if enable else 0))
+
+
+def trim_cache() -> int:
+    """rss_trim_cache: return the library's cached device memory (freed
+    records and workspaces kept for reuse) on the current device to the
+    driver.  Returns the bytes released."""
+    out = ctypes.c_int64()
+    _check(load().rss_trim_cache(ctypes.byref(out)))
+    return int(out.value)
 
 
 def set_autotune(mode) -> int:

@@ -1035,7 +1035,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
   // leaf stencils of every problem: one launch
   {
     std::vector<Prob<R>> probs;
-    int maxb = 0;
+    int maxb = 0, lnmax = 0;
     for (int p = 0; p < np; ++p)
       if (W[p].active) {
         Prob<R> pr{};
@@ -1044,10 +1044,11 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         pr.P = H[p]->d_P;
         probs.push_back(pr);
         maxb = std::max(maxb, W[p].cur.nb * W[p].cur.nb);
+        lnmax = std::max(lnmax, W[p].cur.nmax);
       }
     if (!probs.empty()) {
       Prob<R>* d = scr.up(probs, s);
-      prof.run(RSS_K_ASSEMBLE, s, [&] { launch_leaf_assemble<R>(d, (int)probs.size(), maxb, s); });
+      prof.run(RSS_K_ASSEMBLE, s, [&] { launch_leaf_assemble<R>(d, (int)probs.size(), maxb, lnmax, s); });
     }
   }
   for (int t = 0; t <= tmax; ++t) {

@@ -405,6 +405,7 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
     if (p < 0) break;
     if (c == p) {
       Rw[(int64_t)j * n + p] = sh_rh;
+      if (j < kl) Rs[j * n + p] = double2{sh_rh, sh_rl};  // for the back substitution
     } else if (c < n && rem[c]) {
       const int i0 = min(c, p), i1 = max(c, p);
       double gh = Gg[i0 + (int64_t)i1 * n], gl = Gg[nn + i0 + (int64_t)i1 * n];
@@ -485,15 +486,19 @@ __global__ __launch_bounds__(NT) void k_chol(const Prob<R>* probs, Phase<R> ph, 
   }
   __syncthreads();
   if (k == 0 || r == 0) return;
-  // T = R11^{-1} R12 in place of R12: column c, rows in pivot order
+  // T = R11^{-1} R12 in place of R12: column c, rows in pivot order; rows of
+  // R below kl (high parts) read and overwritten in LDS, the rest in the
+  // workspace
+  auto rget = [&](int i, int col) { return i < kl ? Rs[i * n + col].x : Rw[(int64_t)i * n + col]; };
   cx<R>* Tout = rec.F + rec.oT[b];
   for (int cc = threadIdx.x; cc < n; cc += NT) {
     if (!rem[cc]) continue;
     for (int i = k - 1; i >= 0; --i) {
-      double sacc = Rw[(int64_t)i * n + cc];
-      for (int q = i + 1; q < k; ++q) sacc = fma(-Rw[(int64_t)i * n + piv[q]], Rw[(int64_t)q * n + cc], sacc);
-      const double x = sacc / Rw[(int64_t)i * n + piv[i]];
-      Rw[(int64_t)i * n + cc] = x;
+      double sacc = rget(i, cc);
+      for (int q = i + 1; q < k; ++q) sacc = fma(-rget(i, piv[q]), rget(q, cc), sacc);
+      const double x = sacc / rget(i, piv[i]);
+      if (i < kl) Rs[i * n + cc].x = x;
+      else Rw[(int64_t)i * n + cc] = x;
       Tout[rank[piv[i]] + (int64_t)k * rank[cc]] = from_d<R>(x, 0.0);
     }
   }

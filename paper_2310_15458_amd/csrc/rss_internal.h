@@ -174,7 +174,7 @@ enum { ERRF_SINGULAR = 1, ERRF_TIMEOUT = 2 };
 // launchers (rss_kernels.hip); all enqueue on `s`
 // ---------------------------------------------------------------------------
 template <class R>
-void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStream_t s);
+void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, int nmax, hipStream_t s);
 template <class R>
 void launch_build_C(const Prob<R>* probs, const Phase<R>& ph, int chunks, hipStream_t s);
 template <class R>

@@ -61,8 +61,72 @@ __device__ __forceinline__ int nb_dy(int j) {
 // ---------------------------------------------------------------------------
 // leaf stencil: A[b, b2] = a(I_b, I_b2) for every pair at distance <= 2
 // ---------------------------------------------------------------------------
+// One workgroup per (box, problem) for the box's 25 blocks: the polynomial
+// table of H0 (15 KiB) is copied to LDS once, and the points of the box and
+// of each neighbour in turn (coordinates and scales) are staged there, so an
+// entry reads LDS only.  Same arithmetic as entry().
+constexpr int RSS_BESSEL_TAB = RSS_BESSEL_NSEG * 2 * (RSS_BESSEL_DEG + 1);
+
+size_t leaf_assemble_lds(int nmax) { return ((size_t)RSS_BESSEL_TAB + (size_t)6 * nmax) * sizeof(double); }
+
 template <class R>
-__global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs) {
+__global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs, int nmax) {
+  extern __shared__ double lsm[];
+  double* stab = lsm;
+  double* pb = stab + RSS_BESSEL_TAB;  // box b: x, y, scale (nmax each)
+  double* pc = pb + 3 * nmax;          // the neighbour in turn
+  const Level<R> L = probs[blockIdx.y].L;
+  const KParams kp = probs[blockIdx.y].kp;
+  const double* P = probs[blockIdx.y].P;
+  const int b = blockIdx.x;
+  if (b >= L.nb * L.nb) return;
+  const int m = L.n0[b];
+  if (m == 0) return;
+  for (int e = threadIdx.x; e < RSS_BESSEL_TAB; e += 256) stab[e] = rss_poly_jy[e];
+  {
+    const int* I = L.idx + L.ioff[b];
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const double x = P[2 * I[i]], y = P[2 * I[i] + 1];
+      pb[i] = x;
+      pb[nmax + i] = y;
+      pb[2 * nmax + i] = point_scale(kp, x, y);
+    }
+  }
+  for (int s = 0; s < 25; ++s) {
+    const int64_t off = L.boff[(int64_t)b * 25 + s];
+    if (off < 0) continue;
+    const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
+    const int n = L.n0[b2];
+    __syncthreads();  // the previous neighbour's readers are done
+    const int* J = L.idx + L.ioff[b2];
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const double x = P[2 * J[j]], y = P[2 * J[j] + 1];
+      pc[j] = x;
+      pc[nmax + j] = y;
+      pc[2 * nmax + j] = point_scale(kp, x, y);
+    }
+    __syncthreads();
+    cx<R>* out = L.A + off;
+    const bool self = s == 12;
+    for (int e = threadIdx.x; e < m * n; e += 256) {
+      const int i = e % m, j = e / m;
+      cx<double> v;
+      if (self && i == j) {
+        v = diag_entry(kp, pb[2 * nmax + i]);
+      } else {
+        const cx<double> k = kernel_raw(kp, pb[i], pb[nmax + i], pc[j], pc[nmax + j], stab);
+        double w = kp.weight;
+        if (kp.bump) w *= pb[2 * nmax + i] * pc[2 * nmax + j];
+        v = {w * k.x, w * k.y};
+      }
+      out[i + (int64_t)j * m] = from_d<R>(v.x, v.y);
+    }
+  }
+}
+
+// the same with every point read from P (boxes too large for the LDS staging)
+template <class R>
+__global__ __launch_bounds__(256) void k_leaf_assemble_g(const Prob<R>* probs) {
   const Level<R> L = probs[blockIdx.y].L;
   const KParams kp = probs[blockIdx.y].kp;
   const double* P = probs[blockIdx.y].P;
@@ -83,9 +147,13 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs) {
 }
 
 template <class R>
-void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, hipStream_t s) {
+void launch_leaf_assemble(const Prob<R>* probs, int nprob, int max_boxes, int nmax, hipStream_t s) {
   if (nprob == 0) return;
-  hipLaunchKernelGGL(k_leaf_assemble<R>, dim3(max_boxes * 25, nprob), dim3(256), 0, s, probs);
+  const size_t shm = leaf_assemble_lds(nmax);
+  if (shm <= (size_t)150 * 1024)
+    hipLaunchKernelGGL(k_leaf_assemble<R>, dim3(max_boxes, nprob), dim3(256), shm, s, probs, nmax);
+  else
+    hipLaunchKernelGGL(k_leaf_assemble_g<R>, dim3(max_boxes * 25, nprob), dim3(256), 0, s, probs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2841,7 +2909,7 @@ void launch_add_c128(cx<double>* x, const cx<double>* d, int64_t tot, hipStream_
 // explicit instantiations
 // ---------------------------------------------------------------------------
 #define RSS_INST(R)                                                                                \
-  template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t);                    \
+  template void launch_leaf_assemble<R>(const Prob<R>*, int, int, int, hipStream_t);                    \
   template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t);              \
   template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t);            \
   template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, bool, hipStream_t);             \

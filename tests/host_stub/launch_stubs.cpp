@@ -3,7 +3,7 @@
 #include "rss_internal.h"
 struct dim3s threadIdx, blockIdx, blockDim;
 namespace rss {
-template <class R> void launch_leaf_assemble(const Prob<R>*, int, int, hipStream_t) {}
+template <class R> void launch_leaf_assemble(const Prob<R>*, int, int, int, hipStream_t) {}
 template <class R> void launch_build_C(const Prob<R>*, const Phase<R>&, int, hipStream_t) {}
 template <class R> void launch_cpqr(const Prob<R>*, const Phase<R>&, int, int, hipStream_t) {}
 template <class R> int cpqr_mg_groups(int nbox, int, int) { return nbox < 8 ? 4 : 1; }
@@ -28,7 +28,7 @@ int solve_slices(int nbox, int) { return nbox < 64 ? 4 : 1; }
 template <class R> bool solve_fused_fits(int, int rmax, int) { return rmax < 64; }
 template <class R> void launch_root_apply(const RootApply<R>*, int, int, int, GemmDesc<R>*, hipStream_t) {}
 #define I(R) \
-template void launch_leaf_assemble<R>(const Prob<R>*, int, int, hipStream_t); \
+template void launch_leaf_assemble<R>(const Prob<R>*, int, int, int, hipStream_t); \
 template void launch_build_C<R>(const Prob<R>*, const Phase<R>&, int, hipStream_t); \
 template void launch_cpqr<R>(const Prob<R>*, const Phase<R>&, int, int, hipStream_t); \
 template void launch_sparsify<R>(const Prob<R>*, const Phase<R>&, int, bool, hipStream_t); \

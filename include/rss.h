@@ -361,9 +361,13 @@ int rss_set_graphs(int enable);
  * driver.  Freed factor records and workspaces stay with the library, per
  * size class, and serve later allocations (repeated and batched
  * factorizations then allocate nothing from the driver); the cache keeps at
- * most half of the device's memory, and is emptied by itself when one of the
- * library's own allocations fails, but not when other code in the process
- * (torch's allocator, for one) runs short: such a caller trims first.
+ * most three quarters of the device's memory, and gives blocks back by itself
+ * when one of the library's own allocations fails, but not when other code in
+ * the process (torch's allocator, for one) runs short: such a caller trims
+ * first.  A program that moves on to a different workload (other problem
+ * sizes or counts) trims too: once the cache is full of the old workload's
+ * blocks, frees past the cap go back with hipFree, which synchronizes the
+ * device and, inside a factorization, stalls its launches.
  * Blocks in use by live handles or servers are not touched.  released (may be
  * NULL): the bytes returned.  RSS_OK, or RSS_EHIP if no device is current.
  */

@@ -72,12 +72,16 @@ constexpr size_t SLAB = (size_t)2 << 20, SMALL = (size_t)64 << 10;
 // pay a hipMalloc and a device-synchronizing hipFree per block.  Callers free
 // only memory that no queued work uses any more (every free follows a
 // synchronization of the stream that used it; when an error unwinds an
-// operation, the device is synchronized before its blocks are cached).  At
-// most half of the device's memory is kept cached (a batched factorization of
-// a few hundred problems reuses its ~100 GB of blocks instead of handing tens
-// of GB back to the driver and mapping them again on every call); the rest
-// goes back to the driver, and so does the whole cache when an allocation
-// fails or rss_trim_cache asks for it.
+// operation, the device is synchronized before its blocks are cached).  Up to
+// three quarters of the device's memory is kept cached (a batched
+// factorization of a few hundred problems reuses its ~100 GB of blocks instead
+// of mapping them again on every call); a block freed past that goes back to
+// the driver.  hipFree synchronizes the device, so a cache filled with another
+// workload's blocks slows the next large factorization (its frees past the
+// cap stall the host's pipelined launches): a caller switching to a different
+// workload calls rss_trim_cache first.  When an allocation fails, the largest
+// cached blocks go back until the request's size (and half again) is
+// released, then the whole cache if that was not enough.
 class DevPool {
  public:
   void* alloc(size_t n) {
@@ -97,11 +101,17 @@ class DevPool {
     }
     void* p = nullptr;
     if (hipMalloc(&p, c) != hipSuccess) {
+      // give back the largest cached blocks, about what the request needs
+      // (unmapping the whole cache can take seconds), then all of them
       (void)hipGetLastError();
-      trim(dev);
+      trim(dev, c + c / 2);
       if (hipMalloc(&p, c) != hipSuccess) {
         (void)hipGetLastError();
-        return nullptr;
+        trim(dev);
+        if (hipMalloc(&p, c) != hipSuccess) {
+          (void)hipGetLastError();
+          return nullptr;
+        }
       }
     }
     std::lock_guard<std::mutex> g(mu_);
@@ -142,23 +152,28 @@ class DevPool {
     if (it != cap_.end()) return it->second;
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
-    return cap_[dev] = tot / 2;
+    return cap_[dev] = tot / 4 * 3;
   }
 
  public:
-  // return device dev's cached blocks to the driver; the bytes released
-  size_t trim(int dev) {
+  // return device dev's cached blocks to the driver, largest first, until at
+  // least `want` bytes are released (all of them by default); the bytes
+  // released
+  size_t trim(int dev, size_t want = ~(size_t)0) {
     std::vector<void*> out;
     size_t bytes = 0;
     {
       std::lock_guard<std::mutex> g(mu_);
-      for (auto& kv : free_)
-        if (kv.first.first == dev) {
-          out.insert(out.end(), kv.second.begin(), kv.second.end());
-          bytes += kv.first.second * kv.second.size();
-          kv.second.clear();
+      for (auto it = free_.rbegin(); it != free_.rend() && bytes < want; ++it) {
+        if (it->first.first != dev) continue;
+        auto& fl = it->second;
+        while (!fl.empty() && bytes < want) {
+          out.push_back(fl.back());
+          fl.pop_back();
+          bytes += it->first.second;
         }
-      cached_[dev] = 0;
+      }
+      cached_[dev] -= bytes;
     }
     for (void* q : out) (void)hipFree(q);
     return bytes;

@@ -444,3 +444,19 @@ def test_householder_id_and_forced_barrier_timeout(torch_cuda, spin):
     print(out, flush=True)
     assert out["bad"] == 0 and out["err"] < 1e-10
     assert out["retries"] == (1 if spin else 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_matrix_is_singular(torch_cuda, precision):
+    """A zero matrix (weight 0, diagonal 0): the ID keeps no skeletons, every
+    redundant block X_RR is exactly zero, and the inverse's pivot search
+    reports it: the factorization fails with RSS_ESINGULAR instead of
+    returning factors."""
+    from paper_2310_15458_amd import rss
+    n = 32
+    P = W.grid_points(n)
+    k = W.Kernel("helmholtz", kappa=10.0, weight=0.0, diag=0.0)
+    print(f"case zero matrix n={n} {precision}", flush=True)
+    with pytest.raises(rss.RSSError) as e:
+        rss.Factorization(P, k, 1e-6, 16, precision=precision)
+    assert e.value.code == rss.RSS_ESINGULAR

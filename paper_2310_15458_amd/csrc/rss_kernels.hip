@@ -1940,6 +1940,11 @@ void launch_compact(const Prob<R>* probs, const Phase<R>& ph, int colours, hipSt
 template <class R>
 __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, const ListEntry* lists,
                                                         int tiles_r, const Prob<R>* probs) {
+  // the tile's 64 rows and 64 columns (list entry, coordinates, point scale)
+  // and, for the Helmholtz kernel, the H0 table, staged in LDS
+  __shared__ __align__(16) double stab[RSS_BESSEL_TAB];
+  __shared__ double px[128], py[128], ps[128];
+  __shared__ int pbox[128], ploc[128], pgid[128];
   const PairDesc d = pd[blockIdx.x];
   const int tr = blockIdx.y % tiles_r, tc = blockIdx.y / tiles_r;
   const int i0 = tr * 64, j0 = tc * 64;
@@ -1947,26 +1952,54 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
   const Level<R> child = probs[d.prob].L;
   const KParams kp = probs[d.prob].kp;
   const double* P = probs[d.prob].P;
-  const ListEntry* rows = lists + d.roff;
-  const ListEntry* cols = lists + d.coff;
+  if (kp.kind == 1)
+    for (int e = threadIdx.x; e < RSS_BESSEL_TAB; e += 256) stab[e] = rss_poly_jy[e];
+  if (threadIdx.x < 128) {
+    const int t = threadIdx.x & 63;
+    const bool isrow = threadIdx.x < 64;
+    const int k = (isrow ? i0 : j0) + t, kn = isrow ? d.nr : d.nc;
+    if (k < kn) {
+      const ListEntry le = (isrow ? lists + d.roff : lists + d.coff)[k];
+      const double x = P[2 * le.gid], y = P[2 * le.gid + 1];
+      pbox[threadIdx.x] = le.box;
+      ploc[threadIdx.x] = le.local;
+      pgid[threadIdx.x] = le.gid;
+      px[threadIdx.x] = x;
+      py[threadIdx.x] = y;
+      ps[threadIdx.x] = point_scale(kp, x, y);
+    }
+  }
+  __syncthreads();
+  const double* tab = kp.kind == 1 ? (const double*)stab : rss_poly_jy;
   cx<R>* out = (cx<R>*)d.dst;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    const int li = e & 63, lj = e >> 6;
+    const int i = i0 + li, j = j0 + lj;
     if (i >= d.nr || j >= d.nc) continue;
-    const ListEntry ri = rows[i], cj = cols[j];
+    const int cj = 64 + lj;
     cx<R> v;
     bool stored = false;
     if (d.have_child) {
-      const int dx = cj.box % child.nb - ri.box % child.nb;
-      const int dy = cj.box / child.nb - ri.box / child.nb;
+      const int rb = pbox[li], cb = pbox[cj];
+      const int dx = cb % child.nb - rb % child.nb;
+      const int dy = cb / child.nb - rb / child.nb;
       if (abs(dx) <= 2 && abs(dy) <= 2) {
-        const cx<R>* blk = child.A + child.boff[(int64_t)ri.box * 25 + slot_of(dx, dy)];
-        v = blk[ri.local + (int64_t)cj.local * child.n0[ri.box]];
+        const cx<R>* blk = child.A + child.boff[(int64_t)rb * 25 + slot_of(dx, dy)];
+        v = blk[ploc[li] + (int64_t)ploc[cj] * child.n0[rb]];
         stored = true;
       }
     }
     if (!stored) {
-      const cx<double> a = entry(kp, P, ri.gid, cj.gid);
+      // the matrix entry of eq. e:aij, as entry() forms it, from the staged points
+      cx<double> a;
+      if (pgid[li] == pgid[cj]) {
+        a = diag_entry(kp, ps[li]);
+      } else {
+        const cx<double> k = kernel_raw(kp, px[li], py[li], px[cj], py[cj], tab);
+        double w = kp.weight;
+        if (kp.bump) w *= ps[li] * ps[cj];
+        a = cx<double>{w * k.x, w * k.y};
+      }
       v = from_d<R>(a.x, a.y);
     }
     out[i + (int64_t)j * d.ld] = v;
@@ -2090,10 +2123,14 @@ __global__ __launch_bounds__(1024) void k_root_panel(const RootDesc<R>* rd, int 
   if (threadIdx.x == 0) *d.gd = GemmDesc<R>{A, Wt, Xp, n, n, ROOT_NB, n, n, nbp, 1, 1};
 }
 
-// Few problems: unblocked Gauss-Jordan, one launch per pivot step for all of
-// them (ping-pong buffers, bound by launch latency); the next pivot is chosen
-// by the launch that produces its column (packed |a| / index keys in W,
-// atomicMax).  Pivot keys are zeroed and, for odd n, A is copied to tmp first.
+// Few problems: unblocked Gauss-Jordan, two pivot steps per launch for all of
+// them (ping-pong buffers, bound by launch latency); the first pivot of a
+// launch is chosen by the launch that produces its column (packed |a| / index
+// keys in W, atomicMax), the second by every workgroup of the launch itself.
+// Pivot keys are zeroed and, for an odd number of launches (n + 1) / 2, A is
+// copied to tmp first, so that the last launch writes A.
+__host__ __device__ inline int root_launches(int n) { return (n + 1) / 2; }
+
 template <class R>
 __global__ __launch_bounds__(256) void k_root_prep(const RootDesc<R>* rd) {
   const RootDesc<R> d = rd[blockIdx.y];
@@ -2101,7 +2138,7 @@ __global__ __launch_bounds__(256) void k_root_prep(const RootDesc<R>* rd) {
   unsigned long long* keys = reinterpret_cast<unsigned long long*>(d.W);
   const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
   for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * 256) keys[e] = 0ull;
-  if (n & 1)
+  if (root_launches(n) & 1)
     for (int64_t e = e0; e < (int64_t)n * n; e += (int64_t)gridDim.x * 256) d.tmp[e] = d.A[e];
 }
 
@@ -2129,56 +2166,151 @@ __global__ __launch_bounds__(256) void k_root_pivot0(const RootDesc<R>* rd) {
   if (threadIdx.x == 0) keys[0] = red[0];
 }
 
+// Pivot steps kk and kk + 1 (only kk when kk + 1 == n) on a 32 x 32 tile.
+// Step kk with pivot row p (its key from the previous launch) takes src to
+//   v1(r, j) = src(p, j) / a                        r = kk (j != kk; 1 / a at j = kk)
+//            = src(s, j) - src(s, kk) / a src(p, j)  r != kk, s = r with rows kk, p exchanged
+// (-src(s, kk) / a at j = kk), a = src(p, kk); step kk + 1 applies the same
+// rule to v1 with pivot p2 = the row r >= kk + 1 of largest |v1(r, kk + 1)|
+// (smallest r on ties), which every workgroup forms from src for itself.  The
+// workgroups holding column kk + 2 publish its pivot key for the next launch.
 template <class R>
 __global__ __launch_bounds__(256) void k_root_gj(const RootDesc<R>* rd, int kk, int* errflag) {
+  __shared__ unsigned long long wred[4];
+  __shared__ cx<R> rowp2[32];
   const RootDesc<R> d = rd[blockIdx.z];
   const int n = d.n;
   if (kk >= n) return;
-  // buffers alternate so that step n - 1 writes A: odd n starts from the copy in tmp
-  const bool fromtmp = ((kk ^ n) & 1) != 0;
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  if (i0 >= n || j0 >= n) return;
+  const bool fromtmp = ((kk / 2 + root_launches(n)) & 1) != 0;
   const cx<R>* src = fromtmp ? d.tmp : d.A;
   cx<R>* dst = fromtmp ? d.A : d.tmp;
   unsigned long long* keys = reinterpret_cast<unsigned long long*>(d.W);
-  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
-  if (i0 >= n || j0 >= n) return;
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
   const unsigned long long key = keys[kk];
   const int p = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
-  const int i = i0 + (threadIdx.x & 15), j = j0 + (threadIdx.x >> 4);
   if (key == 0ull || p < kk || p >= n) {  // no pivot recorded (an earlier step was singular)
-    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(errflag, ERRF_SINGULAR);
+    if (first) atomicOr(errflag, ERRF_SINGULAR);
     return;
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) d.perm[kk] = p;
   const cx<R> akk = src[p + (int64_t)kk * n];
   const double dd = abs2d(akk);
   if (dd == 0.0) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) atomicOr(errflag, ERRF_SINGULAR);
+    if (first) atomicOr(errflag, ERRF_SINGULAR);
     return;
   }
   const cx<R> pinv{(R)(akk.x / dd), (R)(-akk.y / dd)};
-  unsigned long long best = 0;
-  if (i < n && j < n) {
-    const int si = (i == kk) ? p : (i == p ? kk : i);
+  // entry (r, j) after step kk
+  auto v1 = [&](int r, int j) -> cx<R> {
+    if (r == kk) return j == kk ? pinv : src[p + (int64_t)j * n] * pinv;
+    const int sr = (r == p) ? kk : r;
+    const cx<R> aik = src[sr + (int64_t)kk * n];
+    if (j == kk) return czero<R>() - aik * pinv;
+    return src[sr + (int64_t)j * n] - aik * pinv * src[p + (int64_t)j * n];
+  };
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool two = kk + 1 < n;
+  const int k2 = kk + 1;
+  // this thread: row i, columns j0 + cg + 8 m.  The loads that every row
+  // other than k2 and p2 needs are issued before the second pivot is known.
+  const int i = i0 + (lane & 31), cg = (int)threadIdx.x >> 5;
+  const int sr = (i == p) ? kk : i;  // source row of row i in step kk
+  const bool rv = i < n && i != kk;
+  cx<R> s_j[4], p_j[4];
+  const cx<R> aik_i = rv ? src[sr + (int64_t)kk * n] : czero<R>();
+  const cx<R> s_k2 = rv && two ? src[sr + (int64_t)k2 * n] : czero<R>();
+  const cx<R> p_k2 = two ? src[p + (int64_t)k2 * n] : czero<R>();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int j = j0 + cg + 8 * m;
+    s_j[m] = (rv && j < n) ? src[sr + (int64_t)j * n] : czero<R>();
+    p_j[m] = (i < n && j < n) ? src[p + (int64_t)j * n] : czero<R>();
+  }
+  int p2 = 0;
+  cx<R> pinv2 = czero<R>();
+  if (two) {
+    unsigned long long best = 0;
+    for (int r = k2 + (int)threadIdx.x; r < n; r += 256) {
+      const unsigned long long kq = pivkey(abs2d(v1(r, k2)), r);
+      best = kq > best ? kq : best;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned hi = __shfl_xor((unsigned)(best >> 32), o, 64), lo = __shfl_xor((unsigned)best, o, 64);
+      const unsigned long long b2 = ((unsigned long long)hi << 32) | lo;
+      best = b2 > best ? b2 : best;
+    }
+    if (lane == 0) wred[wv] = best;
+    __syncthreads();
+    best = max(max(wred[0], wred[1]), max(wred[2], wred[3]));
+    p2 = (int)(0xFFFFFFFFu - (unsigned)(best & 0xFFFFFFFFull));
+    if (best == 0ull || p2 <= kk || p2 >= n) {
+      if (first) atomicOr(errflag, ERRF_SINGULAR);
+      return;  // uniform: every workgroup takes the same decision
+    }
+    const cx<R> a2 = v1(p2, k2);
+    const double d2 = abs2d(a2);
+    if (d2 == 0.0) {
+      if (first) atomicOr(errflag, ERRF_SINGULAR);
+      return;
+    }
+    pinv2 = cx<R>{(R)(a2.x / d2), (R)(-a2.y / d2)};
+  }
+  if (threadIdx.x < 32) {
+    const int j = j0 + (int)threadIdx.x;
+    if (j < n && two) rowp2[threadIdx.x] = v1(p2, j);
+  }
+  if (first) {
+    d.perm[kk] = p;
+    if (two) d.perm[kk + 1] = p2;
+  }
+  __syncthreads();
+  // rows k2 and p2 exchange in step kk + 1: those two rows load afresh
+  const bool plain = !two || (i != k2 && i != p2);
+  const int s2 = !two ? i : (i == k2 ? p2 : (i == p2 ? k2 : i));
+  // entry (i, j) after step kk from the preloaded values (i != kk)
+  auto v1pre = [&](int m, int j) -> cx<R> {
+    if (j == kk) return czero<R>() - aik_i * pinv;
+    return s_j[m] - aik_i * pinv * p_j[m];
+  };
+  cx<R> a = czero<R>();
+  if (two && i < n) {
+    if (!plain) a = v1(s2, k2);
+    else if (i == kk) a = p_k2 * pinv;
+    else a = s_k2 - aik_i * pinv * p_k2;
+  }
+  unsigned long long nbest = 0;
+  const int jn = kk + 2;  // the column whose pivot the next launch needs
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int j = j0 + cg + 8 * m;
+    if (i >= n || j >= n) continue;
+    // v1(s2, j)
+    cx<R> w;
+    if (!plain) w = v1(s2, j);
+    else if (i == kk) w = (j == kk) ? pinv : p_j[m] * pinv;
+    else w = v1pre(m, j);
     cx<R> v;
-    if (i == kk) {
-      v = (j == kk) ? pinv : src[p + (int64_t)j * n] * pinv;
+    if (!two) {
+      v = w;
+    } else if (i == k2) {
+      v = (j == k2) ? pinv2 : rowp2[j - j0] * pinv2;
     } else {
-      const cx<R> aik = src[si + (int64_t)kk * n];
-      if (j == kk) v = czero<R>() - aik * pinv;
-      else v = src[si + (int64_t)j * n] - aik * pinv * src[p + (int64_t)j * n];
+      v = (j == k2) ? czero<R>() - a * pinv2 : w - a * pinv2 * rowp2[j - j0];
     }
     dst[i + (int64_t)j * n] = v;
-    if (j == kk + 1 && i >= kk + 1) best = pivkey(abs2d(v), i);
+    if (j == jn && i >= jn) nbest = pivkey(abs2d(v), i);
   }
-  if (j0 <= kk + 1 && kk + 1 < j0 + 16 && kk + 1 < n) {
-    __shared__ unsigned long long red[256];
-    red[threadIdx.x] = best;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
-      __syncthreads();
+  // the wave holding column kk + 2 (in one half of its lanes) posts its key
+  if (two && jn < n && jn >= j0 && jn < j0 + 32 && (((jn - j0) & 7) >> 1) == wv) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const unsigned hi = __shfl_xor((unsigned)(nbest >> 32), o, 64), lo = __shfl_xor((unsigned)nbest, o, 64);
+      const unsigned long long b2 = ((unsigned long long)hi << 32) | lo;
+      nbest = b2 > nbest ? b2 : nbest;
     }
-    if (threadIdx.x == 0 && red[0]) atomicMax(keys + kk + 1, red[0]);
+    if (lane == 0 && nbest) atomicMax(keys + jn, nbest);
   }
 }
 
@@ -2220,8 +2352,8 @@ void launch_root_inverse(const RootDesc<R>* rd, int nprob, int nmax, GemmDesc<R>
     hipLaunchKernelGGL(k_root_prep<R>, dim3((unsigned)std::min<int64_t>(4096, (tot + 255) / 256), nprob), dim3(256),
                        0, s, rd);
     hipLaunchKernelGGL(k_root_pivot0<R>, dim3(nprob), dim3(256), 0, s, rd);
-    const int t = (nmax + 15) / 16;
-    for (int kk = 0; kk < nmax; ++kk)
+    const int t = (nmax + 31) / 32;
+    for (int kk = 0; kk < nmax; kk += 2)
       hipLaunchKernelGGL(k_root_gj<R>, dim3(t, t, nprob), dim3(256), 0, s, rd, kk, errflag);
   } else {
     for (int k0 = 0; k0 < nmax; k0 += ROOT_NB) {

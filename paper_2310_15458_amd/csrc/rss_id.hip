@@ -119,8 +119,12 @@ int gram_tile_groups(int nmax) {
   return std::max(1, (t * (t + 1) / 2 + 255) / 256);
 }
 
+// Three waves per SIMD (at most 168 registers; the spills fall in the row
+// staging, not in the accumulation loop): a 64-point box has only 136 tiles,
+// so the CU needs the third workgroup to keep its SIMDs issuing (two: 21.7 ms
+// of Gram time per FP32 factorization at 512^2 points, three: 19.9, four: 20.1).
 template <class R>
-__global__ __launch_bounds__(256) void k_gram(const Prob<R>* probs, Phase<R> ph, GramWs gw, int ldn) {
+__global__ __launch_bounds__(256, 3) void k_gram(const Prob<R>* probs, Phase<R> ph, GramWs gw, int ldn) {
   extern __shared__ __align__(16) double gsm[];
   double* sre = gsm;                 // GRAM_SR x ldn
   double* sim = gsm + GRAM_SR * ldn;  // GRAM_SR x ldn

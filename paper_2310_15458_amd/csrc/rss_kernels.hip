@@ -1944,7 +1944,7 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
   // and, for the Helmholtz kernel, the H0 table, staged in LDS
   __shared__ __align__(16) double stab[RSS_BESSEL_TAB];
   __shared__ double px[128], py[128], ps[128];
-  __shared__ int pbox[128], ploc[128], pgid[128];
+  __shared__ int pbox[128], pbx[128], pby[128], pn0[128], ploc[128], pgid[128];
   const PairDesc d = pd[blockIdx.x];
   const int tr = blockIdx.y % tiles_r, tc = blockIdx.y / tiles_r;
   const int i0 = tr * 64, j0 = tc * 64;
@@ -1962,6 +1962,10 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
       const ListEntry le = (isrow ? lists + d.roff : lists + d.coff)[k];
       const double x = P[2 * le.gid], y = P[2 * le.gid + 1];
       pbox[threadIdx.x] = le.box;
+      const int cnb = d.have_child ? child.nb : 1;  // child-grid coordinates of the box
+      pbx[threadIdx.x] = le.box % cnb;
+      pby[threadIdx.x] = le.box / cnb;
+      pn0[threadIdx.x] = d.have_child ? child.n0[le.box] : 0;
       ploc[threadIdx.x] = le.local;
       pgid[threadIdx.x] = le.gid;
       px[threadIdx.x] = x;
@@ -1980,12 +1984,12 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
     cx<R> v;
     bool stored = false;
     if (d.have_child) {
-      const int rb = pbox[li], cb = pbox[cj];
-      const int dx = cb % child.nb - rb % child.nb;
-      const int dy = cb / child.nb - rb / child.nb;
+      const int rb = pbox[li];
+      const int dx = pbx[cj] - pbx[li];
+      const int dy = pby[cj] - pby[li];
       if (abs(dx) <= 2 && abs(dy) <= 2) {
         const cx<R>* blk = child.A + child.boff[(int64_t)rb * 25 + slot_of(dx, dy)];
-        v = blk[ploc[li] + (int64_t)ploc[cj] * child.n0[rb]];
+        v = blk[ploc[li] + (int64_t)ploc[cj] * pn0[li]];
         stored = true;
       }
     }

@@ -107,24 +107,34 @@ __device__ __forceinline__ void dd_sqrt(double ah, double al, double& h, double&
 
 // ---------------------------------------------------------------------------
 // partial Gram matrices: workgroup (slot, chunk, tile group) accumulates
-// sum over the chunk's rows y of Y of  Re(y)^T Re(y) + Im(y)^T Im(y)  for 256
+// sum over the chunk's rows y of Y of  Re(y)^T Re(y) + Im(y)^T Im(y)  for NT
 // 4 x 4 tiles of the upper triangle.  Rows of Y: the M boxes of B (distance 2,
 // ascending offset order, each box's active rows), then the n_proxy proxy
 // points w K(y_p, x_j) s_j (s the point scale of the box's columns).  Rows are staged in LDS GRAM_SR at a time, as FP64.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_SR = 16;
 
+// threads (= 4 x 4 tiles) per workgroup: 192 or 256, whichever launches
+// fewer waves for a box's upper triangle (a 64-point box has 136 tiles: one
+// workgroup of 3 waves instead of 4, so that four of them share a CU)
+int gram_nt(int nmax) {
+  const int t = (nmax + 3) / 4, tiles = t * (t + 1) / 2;
+  const int w192 = (tiles + 191) / 192 * 3, w256 = (tiles + 255) / 256 * 4;
+  return w192 < w256 ? 192 : 256;
+}
 int gram_tile_groups(int nmax) {
-  const int t = (nmax + 3) / 4;
-  return std::max(1, (t * (t + 1) / 2 + 255) / 256);
+  const int t = (nmax + 3) / 4, nt = gram_nt(std::max(1, nmax));
+  return std::max(1, (t * (t + 1) / 2 + nt - 1) / nt);
 }
 
 // Three waves per SIMD (at most 168 registers; the spills fall in the row
 // staging, not in the accumulation loop): a 64-point box has only 136 tiles,
-// so the CU needs the third workgroup to keep its SIMDs issuing (two: 21.7 ms
-// of Gram time per FP32 factorization at 512^2 points, three: 19.9, four: 20.1).
-template <class R>
-__global__ __launch_bounds__(256, 3) void k_gram(const Prob<R>* probs, Phase<R> ph, GramWs gw, int ldn) {
+// so the CU needs more workgroups to keep its SIMDs issuing (Gram time per
+// FP32 factorization at 512^2 points with 256-thread workgroups: 21.7 ms at
+// two waves per SIMD, 19.9 at three, 20.1 at four; 192-thread workgroups at
+// three: 19.2).
+template <class R, int NT>
+__global__ __launch_bounds__(NT, 3) void k_gram(const Prob<R>* probs, Phase<R> ph, GramWs gw, int ldn) {
   extern __shared__ __align__(16) double gsm[];
   double* sre = gsm;                 // GRAM_SR x ldn
   double* sim = gsm + GRAM_SR * ldn;  // GRAM_SR x ldn
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(256, 3) void k_gram(const Prob<R>* probs, Phase<R> 
   const bool cplx = kp.kind == 1;  // Laplace and the degenerate kernel are real
   // this thread's 4 x 4 tile (ti <= tj) of the upper triangle
   const int T4 = (n + 3) / 4;
-  const int tile = tg * 256 + (int)threadIdx.x;
+  const int tile = tg * NT + (int)threadIdx.x;
   const bool act = tile < T4 * (T4 + 1) / 2;
   int tj = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
   while (tj * (tj + 1) / 2 > tile) --tj;
@@ -183,7 +193,7 @@ __global__ __launch_bounds__(256, 3) void k_gram(const Prob<R>* probs, Phase<R> 
   const double rad = pr.proxy_radius * L.side;
   for (int rb = r0; rb < r1; rb += GRAM_SR) {
     __syncthreads();
-    for (int e = threadIdx.x; e < GRAM_SR * n; e += 256) {
+    for (int e = threadIdx.x; e < GRAM_SR * n; e += NT) {
       const int rr = e % GRAM_SR, j = e / GRAM_SR, row = rb + rr;
       double re = 0.0, im = 0.0;
       if (row < r1) {
@@ -281,8 +291,11 @@ void launch_gram(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int
   if (ph.nbox == 0) return;
   const int ldn = ((nmax + 3) / 4) * 4;
   const size_t shm = (size_t)2 * GRAM_SR * ldn * sizeof(double);
-  hipLaunchKernelGGL(k_gram<R>, dim3(ph.nbox, gw.chunks, gram_tile_groups(nmax)), dim3(256), shm, s, probs,
-                     ph, gw, ldn);
+  const dim3 grid(ph.nbox, gw.chunks, gram_tile_groups(nmax));
+  if (gram_nt(nmax) == 192)
+    hipLaunchKernelGGL((k_gram<R, 192>), grid, dim3(192), shm, s, probs, ph, gw, ldn);
+  else
+    hipLaunchKernelGGL((k_gram<R, 256>), grid, dim3(256), shm, s, probs, ph, gw, ldn);
   if (gw.chunks > 1)
     hipLaunchKernelGGL(k_gram_sum<R>, dim3(ph.nbox, (unsigned)(((int64_t)nmax * nmax + 255) / 256)), dim3(256),
                        0, s, probs, ph, gw);

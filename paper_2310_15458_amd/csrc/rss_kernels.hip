@@ -64,7 +64,12 @@ __device__ __forceinline__ int nb_dy(int j) {
 // One workgroup per (box, problem) for the box's 25 blocks: the polynomial
 // table of H0 (15 KiB) is copied to LDS once, and the points of the box and
 // of each neighbour in turn (coordinates and scales) are staged there, so an
-// entry reads LDS only.  Same arithmetic as entry().
+// entry reads LDS only.  Same arithmetic as entry().  The entries are
+// symmetric bit for bit (the distance squares x_i - x_j, which is exactly
+// -(x_j - x_i); the point scales multiply in either order), so a box
+// evaluates its own block and the blocks toward the 12 neighbours that come
+// after it (dy > 0, or dy = 0 and dx > 0) and stores each of those twice,
+// A[b, b2] and its transpose A[b2, b].
 constexpr int RSS_BESSEL_TAB = RSS_BESSEL_NSEG * 2 * (RSS_BESSEL_DEG + 1);
 
 size_t leaf_assemble_lds(int nmax) { return ((size_t)RSS_BESSEL_TAB + (size_t)6 * nmax) * sizeof(double); }
@@ -92,11 +97,14 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs, int
       pb[2 * nmax + i] = point_scale(kp, x, y);
     }
   }
-  for (int s = 0; s < 25; ++s) {
+  for (int s = 12; s < 25; ++s) {  // the box itself, then the later neighbours
     const int64_t off = L.boff[(int64_t)b * 25 + s];
     if (off < 0) continue;
-    const int b2 = box_at(L, b, s % 5 - 2, s / 5 - 2);
+    const int dx = s % 5 - 2, dy = s / 5 - 2;
+    const int b2 = box_at(L, b, dx, dy);
     const int n = L.n0[b2];
+    // A[b2, b] (n x m): the slot of offset (-dx, -dy) of box b2
+    cx<R>* outT = s == 12 ? nullptr : L.A + L.boff[(int64_t)b2 * 25 + slot_of(-dx, -dy)];
     __syncthreads();  // the previous neighbour's readers are done
     const int* J = L.idx + L.ioff[b2];
     for (int j = threadIdx.x; j < n; j += 256) {
@@ -119,7 +127,9 @@ __global__ __launch_bounds__(256) void k_leaf_assemble(const Prob<R>* probs, int
         if (kp.bump) w *= pb[2 * nmax + i] * pc[2 * nmax + j];
         v = {w * k.x, w * k.y};
       }
-      out[i + (int64_t)j * m] = from_d<R>(v.x, v.y);
+      const cx<R> vr = from_d<R>(v.x, v.y);
+      out[i + (int64_t)j * m] = vr;
+      if (!self) outT[j + (int64_t)i * n] = vr;
     }
   }
 }

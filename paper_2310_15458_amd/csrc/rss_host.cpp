@@ -1527,10 +1527,23 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
         for (int sl = 0; sl < 25; ++sl) {
           const int64_t off = par.boff[(size_t)q * 25 + sl];
           if (off < 0) continue;
-          const int q2 = (q / pnb + sl / 5 - 2) * pnb + (q % pnb + sl % 5 - 2);
+          const int sdx = sl % 5 - 2, sdy = sl / 5 - 2;
+          const int q2 = (q / pnb + sdy) * pnb + (q % pnb + sdx);
           if (pcount[q] == 0 || pcount[q2] == 0) continue;
+          // parent boxes 2 apart: every pair of their children is at least 3
+          // apart, so no entry comes from a stored child block and the block
+          // is the transpose of its mirror bit for bit; the pair with
+          // (dy, dx) > (0, 0) writes both, its mirror gets no descriptor
+          const bool fresh = std::max(std::abs(sdx), std::abs(sdy)) == 2;
+          const bool later = sdy > 0 || (sdy == 0 && sdx > 0);
           PairDesc pd_;
           pd_.dst = (char*)par.d_A + off * E;
+          pd_.dstT = nullptr;
+          pd_.ldT = 0;
+          if (fresh && later) {
+            pd_.dstT = (char*)par.d_A + par.boff[(size_t)q2 * 25 + (2 - sdy) * 5 + (2 - sdx)] * E;
+            pd_.ldT = pcount[q2];
+          }
           pd_.ld = pcount[q];
           pd_.nr = pcount[q];
           pd_.nc = pcount[q2];
@@ -1538,7 +1551,7 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
           pd_.have_child = 1;
           pd_.roff = loff[q];
           pd_.coff = loff[q2];
-          pds.push_back(pd_);
+          if (!fresh || later) pds.push_back(pd_);
           const int qx = q % pnb, qy = q / pnb, rx = q2 % pnb, ry = q2 / pnb;
           for (int u = 0; u < 4; ++u)
             for (int v = 0; v < 4; ++v) {
@@ -1628,6 +1641,8 @@ void factor_batch(std::vector<rss_ctx*>& H, hipStream_t s) {
       cprobs.push_back(cp);
       PairDesc q;
       q.dst = rd.A;
+      q.dstT = nullptr;
+      q.ldT = 0;
       q.ld = nr;
       q.nr = nr;
       q.nc = nr;

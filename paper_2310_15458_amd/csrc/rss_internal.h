@@ -146,7 +146,9 @@ struct GemmDesc {
 // Fig. f:merge): rows/cols are lists of (child box, local position, global id).
 struct PairDesc {
   void* dst;    // destination block (complex<R>, column-major, leading dimension ld)
-  int ld;
+  void* dstT;   // when not null, the transposed block too (leading dimension ldT):
+                // a pair whose entries are all evaluated afresh (symmetric bit for bit)
+  int ld, ldT;
   int nr, nc;
   int prob;     // problem index (child level, kernel, points)
   int have_child;
@@ -194,7 +196,7 @@ bool launch_cpqr_mg(const Prob<R>* probs, const Phase<R>& ph, int nmax, int mmax
 // at most GRAM_NMAX points): partial Gram matrices of row chunks, their sum,
 // and the pivoted Cholesky factorization with T = R11^{-1} R12.
 constexpr int GRAM_NMAX = 192;
-// 4 x 4 tiles of the upper triangle of an n x n Gram matrix, in groups of 256
+// 4 x 4 tiles of the upper triangle of an n x n Gram matrix, in workgroups of 192 or 256
 int gram_tile_groups(int nmax);
 template <class R>
 void launch_gram(const Prob<R>* probs, const Phase<R>& ph, const GramWs& gw, int nmax, hipStream_t s);

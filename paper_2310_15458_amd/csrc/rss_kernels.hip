@@ -2017,6 +2017,7 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(const PairDesc* pd, cons
       v = from_d<R>(a.x, a.y);
     }
     out[i + (int64_t)j * d.ld] = v;
+    if (d.dstT) ((cx<R>*)d.dstT)[j + (int64_t)i * d.ldT] = v;
   }
 }
 

@@ -2139,7 +2139,8 @@ __global__ __launch_bounds__(1024) void k_root_panel(const RootDesc<R>* rd, int 
 }
 
 // Few problems: unblocked Gauss-Jordan, two pivot steps per launch for all of
-// them (ping-pong buffers, bound by launch latency); the first pivot of a
+// them (ping-pong buffers; each launch is bound by its chain of dependent
+// loads: key, pivot, search column, second pivot row, tile); the first pivot of a
 // launch is chosen by the launch that produces its column (packed |a| / index
 // keys in W, atomicMax), the second by every workgroup of the launch itself.
 // Pivot keys are zeroed and, for an odd number of launches (n + 1) / 2, A is

@@ -270,14 +270,15 @@ __global__ __launch_bounds__(NT, 3) void k_gram(const Prob<R>* probs, Phase<R> p
     }
 }
 
-// G = sum of the chunks' partial Gram matrices, in chunk order (deterministic)
+// G = sum of the chunks' partial Gram matrices, in chunk order (deterministic);
+// only the upper triangle, the part that k_gram writes and k_chol reads
 template <class R>
 __global__ __launch_bounds__(256) void k_gram_sum(const Prob<R>* probs, Phase<R> ph, GramWs gw) {
   const int slot = blockIdx.x, b = ph.box[slot];
   const int n = probs[ph.prob[slot]].L.cur[b];
   const int64_t nn = (int64_t)n * n;
   const int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  if (e >= nn) return;
+  if (e >= nn || e % n > e / n) return;
   const double* p = gw.part + gw.oP[slot];
   double h = 0.0, l = 0.0;
   for (int c = 0; c < gw.chunks; ++c) dd_add(h, l, p[(int64_t)c * 2 * nn + e], p[(int64_t)c * 2 * nn + nn + e], h, l);
